@@ -1,0 +1,36 @@
+// Oracle (test infrastructure only): helpers shared between the oracle's own files.
+#ifndef CFNEB_ORACLE_INTERNAL_H
+#define CFNEB_ORACLE_INTERNAL_H
+
+#include <cstdint>
+#include <vector>
+
+#include "oracle.h"
+
+namespace orc {
+
+void matmul3(const double* A, const double* B, double* C);
+void transpose3(const double* A, double* T);
+void rows_times(int n, const double* P, const double* M, double* out);
+
+// One neighbour entry (j, n) of atom i.
+struct Nbr {
+    int j;
+    int n[3];
+};
+
+// Full neighbour lists, one vector per atom, sorted by (j, n).
+int build_lists(int n, const double* R, const double* h, double rc, bool brute,
+                std::vector<std::vector<Nbr>>& lists);
+
+// Bond-wise evaluation: u_i and P_e = dU_i/dr^{ij} for every entry of i's list,
+// then forces and virial are assembled from P.
+int eval_with_lists(const orc_params* p, int n, const double* R, const double* h,
+                    const std::vector<std::vector<Nbr>>& lists,
+                    double* E, double* u, double* F, double* V);
+
+double cutoff_of(const orc_params* p);
+
+}  // namespace orc
+
+#endif

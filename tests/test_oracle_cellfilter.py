@@ -1,0 +1,110 @@
+"""Pins of the oracle's rotation-free cell filter (Sec. II.C): generalized forces
+against finite differences of the enthalpy in generalized coordinates, and the
+rotation invariance of R~, B and the generalized forces (Eq. (15))."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def _rot(seed):
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    return Q
+
+
+def _image(orc, kind, pressure=0.0):
+    rng = np.random.default_rng(5)
+    if kind == "lj":
+        w = W.fcc_vacancy_hop(2, 2, 2, 1.5496)
+        p = orc.default_params(orc.LJ, pressure_GPa=pressure)
+    else:
+        w = W.graphite_to_diamond(2, 2, 3, seed=4, sigma=0.05)
+        p = orc.default_params(orc.TERSOFF, pressure_GPa=pressure)
+    XA, XB = orc.build_endpoints(p, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+    X = 0.6 * XA + 0.4 * XB
+    X[:-3] += rng.normal(0, 0.02, X[:-3].shape)
+    return p, w["cell_init"], X
+
+
+@pytest.mark.parametrize("kind,pressure", [("lj", 0.0), ("ts", 0.0), ("ts", 15.0), ("lj", 40.0)])
+def test_generalized_forces_by_finite_differences(orc, kind, pressure):
+    p, h0, X = _image(orc, kind, pressure)
+    out = orc.cf_eval(p, h0, X)
+    n = X.shape[0] - 3
+    delta = 1e-6
+    # atom rows: F D^T is exactly -dH/dR~
+    for i in [0, 3, n // 2]:
+        for c in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, c] += delta
+            Xm[i, c] -= delta
+            fd = -(orc.cf_eval(p, h0, Xp)["H"] - orc.cf_eval(p, h0, Xm)["H"]) / (2 * delta)
+            assert out["Fg"][i, c] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+    # cell rows hold c_f B; the printed lattice force D^-T V D^-1 / c_f is twice the
+    # virtual-work conjugate of B: -dH = 1/2 Fg_cell : d(c_f B)
+    dcell = delta * n
+    for m in range(3):
+        for k in range(m, 3):
+            dX = np.zeros((3, 3))
+            dX[m, k] += dcell
+            dX[k, m] = dX[m, k]
+            Xp, Xm = X.copy(), X.copy()
+            Xp[n:] += dX
+            Xm[n:] -= dX
+            fd = -(orc.cf_eval(p, h0, Xp)["H"] - orc.cf_eval(p, h0, Xm)["H"]) / 2.0
+            pred = 0.5 * np.sum(out["Fg"][n:] * dX)
+            assert pred == pytest.approx(fd, rel=2e-5, abs=1e-9)
+
+
+def test_enthalpy_adds_p_omega(orc):
+    p0, h0, X = _image(orc, "ts", 0.0)
+    p1, _, _ = _image(orc, "ts", 15.0)
+    a, b = orc.cf_eval(p0, h0, X), orc.cf_eval(p1, h0, X)
+    omega = abs(np.linalg.det(a["h"]))
+    assert b["H"] - a["H"] == pytest.approx(15.0 / 160.21766208 * omega, rel=1e-12)
+    assert b["E"] == a["E"]
+
+
+def test_identity_deformation_at_reference_cell(orc):
+    p, h0, X = _image(orc, "lj")
+    XA, _ = orc.build_endpoints(p, X[:-3], h0, X[:-3], h0)
+    out = orc.cf_eval(p, h0, XA)
+    np.testing.assert_allclose(out["h"], h0, rtol=1e-15)
+    np.testing.assert_array_equal(out["R"], XA[:-3])
+    E, u, F, V = orc.evaluate(p, XA[:-3], h0)
+    assert out["E"] == pytest.approx(E, rel=1e-13)
+    np.testing.assert_allclose(out["Fg"][:-3], F, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["lj", "ts"])
+def test_rotation_free_coordinates_and_forces(orc, kind):
+    # a rigidly rotated final state (h -> h Q, R -> R Q) has the same B, R~ and
+    # generalized forces: the rotational degrees of freedom are gone (Eq. (15))
+    if kind == "lj":
+        w = W.fcc_vacancy_hop(2, 2, 2, 1.5496)
+        p = orc.default_params(orc.LJ)
+    else:
+        w = W.graphite_to_diamond(2, 2, 3, seed=4, sigma=0.05)
+        p = orc.default_params(orc.TERSOFF, pressure_GPa=5.0)
+    Q = _rot(3)
+    XA, XB = orc.build_endpoints(p, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+    _, XBr = orc.build_endpoints(p, w["pos_init"], w["cell_init"], w["pos_final"] @ Q,
+                                 w["cell_final"] @ Q)
+    np.testing.assert_allclose(XBr, XB, rtol=1e-12, atol=1e-10)
+    a, b = orc.cf_eval(p, w["cell_init"], XB), orc.cf_eval(p, w["cell_init"], XBr)
+    assert b["H"] == pytest.approx(a["H"], rel=1e-12)
+    np.testing.assert_allclose(b["Fg"], a["Fg"], atol=1e-8)
+    # the final structure itself has the energy of the unrotated input
+    E = orc.evaluate(p, w["pos_final"], w["cell_final"])[0]
+    assert a["E"] == pytest.approx(E, rel=1e-12)
+
+
+def test_non_spd_cell_rows_are_rejected(orc):
+    p, h0, X = _image(orc, "lj")
+    n = X.shape[0] - 3
+    X[n:] = -X[n:]
+    with pytest.raises(orc.OracleError) as e:
+        orc.cf_eval(p, h0, X)
+    assert e.value.code == orc.ECELL

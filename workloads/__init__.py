@@ -1,0 +1,146 @@
+"""Seeded synthetic band endpoints for the CFNEB workloads.
+
+This module only builds lattices and draws seeded noise; it holds none of the
+method's arithmetic, so the CPU oracle and the HIP library can both be fed from
+it.  All lengths in Angstrom; cells are 3x3 with lattice vectors as rows.
+
+The paper's own systems (Ti3O5 with a machine-learned potential, graphite to
+cubic diamond with an unnamed carbon potential, Sec. IV) are not reproducible
+here; these workloads stand in with the same shapes:
+
+* ``fcc_vacancy_hop``: Lennard-Jones FCC crystal with one vacancy; the final
+  state is the nearest neighbour of the vacancy hopped into it.
+* ``diamond_vacancy_hop``: the same hop in a cubic-diamond carbon crystal.
+* ``graphite_to_diamond``: an orthorhombic AB-graphite supercell and the same
+  atoms re-stacked ABC and puckered into a cubic-diamond-like (111) stacking,
+  the shape of the graphite-to-diamond band of Sec. IV.B.
+"""
+import math
+
+import numpy as np
+
+FCC_BASIS = np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
+
+
+def fcc_sites(nx, ny, nz, a):
+    """Site index ((ix*ny + iy)*nz + iz)*4 + b."""
+    sites = []
+    for ix in range(nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                for b in FCC_BASIS:
+                    sites.append((np.array([ix, iy, iz]) + b) * a)
+    cell = np.diag([nx * a, ny * a, nz * a])
+    return np.array(sites), cell
+
+
+def fcc_vacancy_hop(nx=4, ny=4, nz=4, a=1.5496):
+    """Vacancy at site 0; atom k sits on site k+1.  In the final state atom 0
+    (site 1, a nearest neighbour of site 0 at a/sqrt(2)) sits on site 0."""
+    sites, cell = fcc_sites(nx, ny, nz, a)
+    pos_i = sites[1:].copy()
+    pos_f = pos_i.copy()
+    pos_f[0] = sites[0]
+    return dict(pos_init=pos_i, cell_init=cell.copy(), pos_final=pos_f, cell_final=cell.copy(),
+                n=len(pos_i), types=np.zeros(len(pos_i), np.int32))
+
+
+def diamond_vacancy_hop(nx=2, ny=2, nz=2, a=3.566):
+    """Cubic diamond (8 sites per cube, site = cube*8 + b), vacancy at site 0.
+    The hopping atom sits on site 4, the nearest neighbour (a/4)(1,1,1) of site 0."""
+    basis = np.concatenate([FCC_BASIS, FCC_BASIS + 0.25])
+    sites = []
+    for ix in range(nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                for b in basis:
+                    sites.append((np.array([ix, iy, iz]) + b) * a)
+    sites = np.array(sites)
+    cell = np.diag([nx * a, ny * a, nz * a])
+    pos_i = sites[1:].copy()
+    pos_f = pos_i.copy()
+    pos_f[3] = sites[0]  # atom 3 is on site 4
+    return dict(pos_init=pos_i, cell_init=cell.copy(), pos_final=pos_f, cell_final=cell.copy(),
+                n=len(pos_i), types=np.zeros(len(pos_i), np.int32))
+
+
+def _honeycomb_layers(nx, ny, nlayers, d, pitch, shift_of_layer, pucker):
+    """Orthorhombic honeycomb stack.  Rectangle sqrt(3) d x 3 d holds 4 atoms at
+    (0,0), (0,d), (sqrt3 d/2, 1.5 d), (sqrt3 d/2, 2.5 d); layer l is shifted by
+    shift_of_layer(l) * d along y and its atoms move by pucker[b] along z.
+    Atom index ((l*nx + ix)*ny + iy)*4 + b, the same in every stacking."""
+    s3 = math.sqrt(3.0)
+    base = np.array([[0.0, 0.0], [0.0, d], [s3 * d / 2, 1.5 * d], [s3 * d / 2, 2.5 * d]])
+    Lx, Ly = nx * s3 * d, ny * 3.0 * d
+    pos = []
+    for layer in range(nlayers):
+        sy = shift_of_layer(layer) * d
+        for ix in range(nx):
+            for iy in range(ny):
+                for b in range(4):
+                    x = base[b, 0] + ix * s3 * d
+                    y = (base[b, 1] + iy * 3.0 * d + sy) % Ly
+                    z = layer * pitch + pucker[b]
+                    pos.append([x, y, z])
+    cell = np.diag([Lx, Ly, nlayers * pitch])
+    return np.array(pos), cell
+
+
+def graphite_to_diamond(nx, ny, ncz, seed, sigma=0.01, d_graphite=1.46, pitch_graphite=3.35,
+                        a_diamond=3.566):
+    """AB graphite (2 layers per orthorhombic cell, ncz cells along z) to the same
+    atoms in ABC stacking with (111)-diamond geometry.  ncz*2 must be a multiple of
+    3 so that the ABC stacking is periodic.  Both endpoints get independent seeded
+    N(0, sigma) displacements per atom and component (initial first, then final)."""
+    nlayers = 2 * ncz
+    if nlayers % 3 != 0:
+        raise ValueError("2*ncz must be a multiple of 3 for a periodic ABC stacking")
+    pos_i, cell_i = _honeycomb_layers(nx, ny, nlayers, d_graphite, pitch_graphite,
+                                      lambda l: l % 2, [0.0, 0.0, 0.0, 0.0])
+    d_dia = a_diamond / math.sqrt(6.0)      # in-plane projection of the diamond bond
+    pitch_dia = a_diamond / math.sqrt(3.0)  # (111) bilayer pitch
+    dz = a_diamond * math.sqrt(3.0) / 24.0  # half of the bilayer puckering
+    # the atoms on (0, d) and (sqrt3 d/2, 2.5 d) sit under an atom of the next layer
+    pos_f, cell_f = _honeycomb_layers(nx, ny, nlayers, d_dia, pitch_dia, lambda l: l % 3,
+                                      [-dz, +dz, -dz, +dz])
+    rng = np.random.default_rng(seed)
+    pos_i = pos_i + rng.normal(0.0, sigma, pos_i.shape)
+    pos_f = pos_f + rng.normal(0.0, sigma, pos_f.shape)
+    return dict(pos_init=pos_i, cell_init=cell_i, pos_final=pos_f, cell_final=cell_f,
+                n=len(pos_i), types=np.zeros(len(pos_i), np.int32))
+
+
+# ----------------------------------------------------------------- recipes
+def lj_fcc_hop_255():
+    """LJ FCC 4x4x4 conventional cells, a = 1.5496 sigma, one vacancy: 255 atoms."""
+    return fcc_vacancy_hop(4, 4, 4, 1.5496)
+
+
+def tersoff_graphite_4608(seed=1):
+    """Graphite to diamond-like, 4,608 atoms (12 x 8 rectangles, 12 layers)."""
+    return graphite_to_diamond(12, 8, 6, seed)
+
+
+def tersoff_graphite_98304(seed=2):
+    """Graphite to diamond-like, 98,304 atoms (32 x 32 rectangles, 24 layers)."""
+    return graphite_to_diamond(32, 32, 12, seed)
+
+
+def small_graphite(nx=3, ny=2, ncz=3, seed=7):
+    """A few-hundred-atom graphite band for fast parity tests."""
+    return graphite_to_diamond(nx, ny, ncz, seed)
+
+
+def random_cell(n, seed, density=0.08, skew=0.15, min_sep=0.0):
+    """Random positions in a random triclinic cell (tests of neighbour sets)."""
+    rng = np.random.default_rng(seed)
+    vol = n / density
+    L = vol ** (1.0 / 3.0)
+    h = np.diag([L, L, L]) * (1.0 + 0.2 * (rng.random(3) - 0.5))
+    h[1, 0] = skew * L * (rng.random() - 0.5)
+    h[2, 0] = skew * L * (rng.random() - 0.5)
+    h[2, 1] = skew * L * (rng.random() - 0.5)
+    s = rng.random((n, 3))
+    # unwrapped positions: some atoms sit one or two cells away
+    s += rng.integers(-2, 3, size=(n, 3)) * (rng.random((n, 3)) < 0.1)
+    return s @ h, h
