@@ -1,0 +1,190 @@
+/*
+ * cfneb.h -- C ABI of the MI355X (gfx950) cell-filter nudged elastic band library.
+ *
+ * Method: Jia, Shi, Sun, "Scalable cell filter nudged elastic band (CFNEB) for
+ * large-scale transition-path calculations", arXiv:2510.16721.
+ *
+ * The problem (Secs. I, II.A, III): two known endpoint configurations of the same
+ * atoms are joined by a chain of images; the chain is relaxed toward the minimum-
+ * energy path with the NEB force of Eq. (1) (true force perpendicular to the
+ * tangent plus a spring along it, climbing image on the highest image); lattice
+ * degrees of freedom move with the atoms through the rotation-free cell filter of
+ * Sec. II.C (Eqs. (10)-(17)); images are inserted or removed after iterations
+ * (Sec. III); the barrier is the highest image enthalpy minus the initial one.
+ *
+ * Conventions shared by every call:
+ *   - Units: eV, Angstrom, GPa.  A cell is a 3x3 row-major matrix whose ROWS are
+ *     the lattice vectors (Sec. II.B, Eq. (2)).  Positions are n x 3 row-major.
+ *   - Ownership: the caller owns every host array (copied during the call) and the
+ *     device workspace, whose size comes from cfneb_band_bytes.  The library never
+ *     allocates or frees device memory; it owns the opaque handle until
+ *     cfneb_destroy.  The HIP stream is the caller's; all device work of a band is
+ *     ordered on it.
+ *   - Errors: every call returns 0 (CFNEB_OK) or a negative CFNEB_E* code; text
+ *     for the last failure of a band is in cfneb_last_error.  A step that fails
+ *     leaves the band at its pre-step state.
+ *   - Threading: one host thread per band handle at a time.
+ */
+#ifndef CFNEB_H
+#define CFNEB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CFNEB_OK = 0,
+    CFNEB_EINVAL = -1,      /* bad argument or parameter */
+    CFNEB_ENOMEM = -2,      /* workspace smaller than cfneb_band_bytes */
+    CFNEB_EHIP = -3,        /* a HIP runtime call failed */
+    CFNEB_ECELL = -4,       /* cell not positive definite, or a neighbour shift beyond +-7 cells */
+    CFNEB_ENEIGH = -5,      /* an atom has more neighbours than nbr_cap */
+    CFNEB_ENONFINITE = -6,  /* energy, virial or force not finite */
+    CFNEB_ECAPACITY = -7,   /* image capacity exceeded */
+    CFNEB_ERANGE = -8       /* a squared spacing term outside [0, 2^40) */
+};
+
+enum { CFNEB_LJ = 1, CFNEB_TERSOFF_C = 2 };
+
+/* Parameters of one band.  cfneb_params_default fills every field. */
+typedef struct cfneb_params {
+    int potential;          /* CFNEB_LJ or CFNEB_TERSOFF_C */
+    int force_fp64;         /* 1: pair / three-body arithmetic in FP64; 0: FP32 with FP64 sums */
+    /* shifted Lennard-Jones: 4 eps [(s/r)^12 - (s/r)^6] - (same at rc) */
+    double lj_eps, lj_sigma, lj_rc;
+    int lj_shift;
+    /* Tersoff bond-order form, lambda3 = 0 (defaults: Tersoff 1988 carbon) */
+    double ts_A, ts_B, ts_lambda1, ts_lambda2, ts_beta, ts_n, ts_c, ts_d, ts_h, ts_R, ts_S;
+    /* band */
+    int n_images;           /* images including both fixed endpoints, >= 3 */
+    int max_images;         /* image capacity (adaptive insertion), <= 64 */
+    int min_images;         /* deletion never goes below this */
+    double k_spring;        /* eV / A^2 */
+    int climb_after;        /* climbing image from this step on; < 0: never */
+    int cell_filter;        /* 0: cell fixed; 2: rotation-free cell filter (Eq. (17)) */
+    double cell_factor;     /* c_f, generalized cell coordinate c_f B; <= 0: n_atoms */
+    double b_force_scale;   /* factor on the lattice force D^-T V D^-1 / c_f (default 1) */
+    double pressure_GPa;    /* hydrostatic pressure; images carry H = U + P Omega */
+    /* FIRE */
+    double fire_dt0, fire_dtmax, fire_maxstep;
+    int fire_nmin;
+    double fire_finc, fire_fdec, fire_astart, fire_fa;
+    /* adaptive images: every refine_every steps (0 = off); insert into the longest
+       interval if ins_den (M-1) d_k^2 > ins_num sum d^2; otherwise delete the image
+       whose longer neighbouring interval is shortest if
+       del_den (M-1) max(d_{j-1}^2, d_j^2) < del_num sum d^2 */
+    int refine_every;
+    int ins_num, ins_den, del_num, del_den;
+    int nbr_cap;            /* neighbour entries per atom */
+} cfneb_params;
+
+/* Optimizer and band bookkeeping, for checkpoints and tests. */
+typedef struct cfneb_fire_state {
+    double dt, alpha;
+    int n_pos;              /* FIRE count of consecutive P > 0 steps */
+    int fresh;              /* 1: the next step skips the P = F.v test */
+    int step;               /* steps taken (moves) */
+    int ci;                 /* climbing image of the last evaluation, -1 if none */
+} cfneb_fire_state;
+
+typedef struct cfneb_band cfneb_band;
+
+/* Fill *out with the defaults for a potential: LJ eps = sigma = 1, rc = 2.5,
+ * shifted; Tersoff 1988 carbon (R = 1.8, S = 2.1); 7 images, k = 1, climbing after
+ * 50 steps, rotation-free filter, c_f = n_atoms; FIRE dt0 0.005 (LJ) / 0.05
+ * (Tersoff), dtmax = 10 dt0, maxstep 0.1, Nmin 5, finc 1.1, fdec 0.5, alpha 0.1,
+ * f_alpha 0.99; refine off with thresholds 9/4 and 1/4; nbr_cap 128 (LJ) / 16. */
+int cfneb_params_default(int potential, cfneb_params* out);
+
+/* Device workspace bytes for a band of n_atoms atoms and up to max_images images
+ * (max_images <= 0: p->max_images).  This is also the band's HBM footprint. */
+int cfneb_band_bytes(const cfneb_params* p, int64_t n_atoms, int max_images, size_t* bytes);
+
+/* Build a band (Secs. II.C, III): h0 = cell_init is the reference cell of every
+ * image; the initial image has D = I and R~ = pos_init; the final image has
+ * B = D D^T with D = h0^-1 cell_final and R~ = pos_init + ds h0, where ds is the
+ * fractional displacement wrapped to the nearest image; the n_images - 2 moving
+ * images are linear in (R~, c_f B).  Every image is evaluated once.
+ * pos_*: n_atoms x 3 host arrays; cell_*: 3x3 host arrays; types: ignored (one
+ * species), may be NULL.  workspace: device pointer of workspace_bytes bytes,
+ * 256-byte aligned.  hip_stream: a hipStream_t (NULL: the null stream).
+ * Returns ENOMEM if workspace_bytes < cfneb_band_bytes(p, n_atoms, 0). */
+int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* types,
+                      const double* pos_init, const double* cell_init,
+                      const double* pos_final, const double* cell_final,
+                      void* workspace, size_t workspace_bytes, void* hip_stream,
+                      cfneb_band** out);
+
+/* Up to max_steps band steps.  One step: per moving image the cell-filter
+ * geometry, cell list, neighbour list, energy / forces / virial (Sec. II.B),
+ * generalized forces (Eq. (17)); improved tangent, springs and climbing image
+ * (Eq. (1)); fmax = largest row norm of the NEB force; if fmax < f_tol the band
+ * is converged and is not moved; otherwise a band-global FIRE move.  Every
+ * refine_every steps an image may be inserted or deleted (Sec. III).
+ * Outputs (any may be NULL): steps taken, fmax of the last evaluation,
+ * converged flag. */
+int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, double* fmax,
+               int* converged);
+
+/* One adaptive-image decision now (Sec. III): squared spacings between
+ * consecutive images summed exactly in fixed point, then at most one insertion
+ * (midpoint of the longest interval) or deletion (never the climbing image),
+ * followed by a FIRE velocity reset.  inserted_at / deleted_at: logical index of
+ * the new or removed image, -1 for none. */
+int cfneb_refine(cfneb_band* b, int* inserted_at, int* deleted_at);
+
+/* Readout: H[k] for the n_images current images (cap >= n_images), the barrier
+ * max_k H_k - H_0, the climbing image (-1 if none) and the path coordinate
+ * xi_k = sum_{j<k} |X_{j+1} - X_j| / sum_j |X_{j+1} - X_j| (path_coord may be NULL).
+ * A freshly inserted image reports the mean of its neighbours until evaluated. */
+int cfneb_energies(const cfneb_band* b, double* H, int cap, int* n_images, double* barrier,
+                   int* ci_index, double* path_coord);
+
+/* Cartesian positions (n_atoms x 3) and cell (3x3) of current image k:
+ * h = h0 D, R = R~ D with D = symsqrt(B). */
+int cfneb_get_image(const cfneb_band* b, int k, double* pos, double* cell);
+
+/* Checkpoint: generalized coordinates X and velocities v of the n_images images,
+ * each (n_atoms + 3) x 3 row-major (rows of R~, then rows of c_f B), into arrays
+ * of cap_images images; FIRE state. */
+int cfneb_get_state(const cfneb_band* b, double* X, double* v, int cap_images, int* n_images,
+                    cfneb_fire_state* st);
+
+/* Restore a checkpoint (same layout); every image is evaluated again.  v may be NULL. */
+int cfneb_set_state(cfneb_band* b, int n_images, const double* X, const double* v,
+                    const cfneb_fire_state* st);
+
+/* Data of image k from its last evaluation (any output may be NULL): potential
+ * energy E, enthalpy H, virial V (3x3, V_mn = -1/2 sum r^ij_m f^ij_n, Eq. (8)),
+ * Cartesian force F (n x 3), generalized force Fg ((n+3) x 3, Eq. (17)), NEB force
+ * Fneb ((n+3) x 3; filled only for moving images and only when the band was
+ * created with record_neb_force set, else zero), positions R (n x 3), cell h (3x3). */
+int cfneb_image_data(const cfneb_band* b, int k, double* E, double* H, double* V, double* F,
+                     double* Fg, double* Fneb, double* R, double* h);
+
+/* Keep the NEB force of every moving image in device memory at each step so
+ * that cfneb_image_data can return it (costs one extra store per row). */
+int cfneb_record_neb_force(cfneb_band* b, int on);
+
+/* Neighbour set of image k from its last evaluation: cnt[i] entries per atom,
+ * written as (j, n0, n1, n2) int32 quadruples into ent (cap quadruples), atom by
+ * atom, each atom's entries in the (deterministic) order the device built them.
+ * The entries of atom i are every (j, n) != (i, 0) with
+ *     r = (R_j - R_i) + ((n0 h_0 + n1 h_1) + n2 h_2),  (r_x r_x + r_y r_y) + r_z r_z < rc^2
+ * each operation rounded on its own in FP64.  *total is the number of entries
+ * (may exceed cap; then ent holds the first cap). */
+int cfneb_neighbours(const cfneb_band* b, int k, int32_t* cnt, int32_t* ent, int64_t cap,
+                     int64_t* total);
+
+int cfneb_destroy(cfneb_band* b);
+
+const char* cfneb_strerror(int code);
+const char* cfneb_last_error(const cfneb_band* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

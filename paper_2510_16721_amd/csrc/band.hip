@@ -1,0 +1,318 @@
+// Band-wide NEB projection (Eq. (1)), climbing image, springs and FIRE.
+//
+// Every moving image k's NEB force is
+//     F_NEB = Fg + c+ tau+ + c- tau-,   tau+ = X_{k+1} - X_k,  tau- = X_k - X_{k-1}
+// because the improved tangent is a combination a tau+ + b tau-: with
+// t = (a tau+ + b tau-) / |.|, the projection Fg - (Fg.t) t + k (|tau+| - |tau-|) t
+// (or Fg - 2 (Fg.t) t for the climbing image) only needs ten dot products per image.
+// Pass 1 (k_band_dots) streams X, Fg and v once to get them; one wave then forms the
+// coefficients and the band-global FIRE quantities P = F.v, |F|, |v| from them;
+// pass 2 (k_band_update) forms F_NEB row by row, the new velocity and the row
+// maxima; pass 3 (k_band_move) moves X once fmax and the step clamp are known.
+//
+// Generalized forces are formed on the fly: atom rows F D^T from the stored
+// Cartesian forces, cell rows from the per-image lattice force (Eq. (17)).
+#include "cfneb_dev.h"
+
+namespace cfneb {
+
+template <typename T>
+__device__ inline void gen_force_row(const BandDev& b, int slot, int r, double* f)
+{
+    if (r < b.N) {
+        const T* F = reinterpret_cast<const T*>(b.F) + size_t(slot) * slot_rows(b);
+        const double fx = double(F[r]), fy = double(F[b.ld + r]), fz = double(F[2 * size_t(b.ld) + r]);
+        const double* D = b.geom[slot].D;
+        for (int c = 0; c < 3; ++c) f[c] = fx * D[3 * c] + fy * D[3 * c + 1] + fz * D[3 * c + 2];
+    } else {
+        const double* G = b.scal[slot].Fcell + 3 * (r - b.N);
+        f[0] = G[0];
+        f[1] = G[1];
+        f[2] = G[2];
+    }
+}
+
+__global__ void k_begin_call(BandDev b, double f_tol)
+{
+    BandState* st = b.st;
+    st->f_tol = f_tol;
+    st->steps_call = 0;
+    st->done = 0;
+    st->err = 0;
+}
+
+// 10 dots per moving image: |t+|^2 |t-|^2 t+.t- F.t+ F.t- F.F F.v v.v v.t+ v.t-
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BandDev b)
+{
+    __shared__ double lds[4 * 10];
+    const BandState* st = b.st;
+    const int k = blockIdx.y;
+    if (band_stopped(st) || !image_active(st, k, 0)) return;
+    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
+    const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
+    double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (r < b.N + 3) {
+        const double* X0 = Xs(b, s0);
+        const double* Xm = Xs(b, sm);
+        const double* Xp = Xs(b, sp);
+        const double* V = Vs(b, st->vcur, s0);
+        double f[3];
+        gen_force_row<T>(b, s0, r, f);
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = size_t(c) * b.ld + r;
+            const double x = X0[o];
+            const double tp = Xp[o] - x, tm = x - Xm[o], v = V[o];
+            a[0] += tp * tp;
+            a[1] += tm * tm;
+            a[2] += tp * tm;
+            a[3] += f[c] * tp;
+            a[4] += f[c] * tm;
+            a[5] += f[c] * f[c];
+            a[6] += f[c] * v;
+            a[7] += v * v;
+            a[8] += v * tp;
+            a[9] += v * tm;
+        }
+    }
+    block_sum<10>(a, lds);
+    if (threadIdx.x == 0) {
+        double* out = b.dotpart + (size_t(k) * b.ntR + blockIdx.x) * 10;
+        for (int q = 0; q < 10; ++q) out[q] = a[q];
+    }
+}
+
+__device__ inline void tangent_coeffs(double Hm, double H0, double Hp, double& a, double& c)
+{
+    if (Hp > H0 && H0 > Hm) {
+        a = 1.0;
+        c = 0.0;
+    } else if (Hp < H0 && H0 < Hm) {
+        a = 0.0;
+        c = 1.0;
+    } else {
+        const double up = fabs(Hp - H0), dn = fabs(Hm - H0);
+        const double big = fmax(up, dn), small = fmin(up, dn);
+        if (Hp > Hm) {
+            a = big;
+            c = small;
+        } else {
+            a = small;
+            c = big;
+        }
+    }
+}
+
+// One block per band: reduce the dot partials, choose tangents and the climbing
+// image, form the projection coefficients and the FIRE proposal.
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_scalars(BandDev b)
+{
+    __shared__ double dots[CFNEB_MAX_IMAGES][10];
+    BandState* st = b.st;
+    if (band_stopped(st)) return;
+    const int M = st->M;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 1 + wid; k <= M - 2; k += CFNEB_TILE / 64) {
+        double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const double* part = b.dotpart + size_t(k) * b.ntR * 10;
+        for (int t = lane; t < b.ntR; t += 64)
+            for (int q = 0; q < 10; ++q) a[q] += part[size_t(t) * 10 + q];
+        for (int q = 0; q < 10; ++q) a[q] = wave_sum(a[q]);
+        if (lane == 0)
+            for (int q = 0; q < 10; ++q) dots[k][q] = a[q];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+
+    double H[CFNEB_MAX_IMAGES];
+    for (int k = 0; k < M; ++k) H[k] = b.scal[st->slot[k]].H;
+    int ci = -1;
+    if (b.climb_after >= 0 && st->step >= b.climb_after) {
+        for (int k = 1; k <= M - 2; ++k)
+            if (ci < 0 || H[k] > H[ci]) ci = k;
+    }
+    st->ci = ci;
+    double Pw = 0.0, FF = 0.0, VV = 0.0;
+    for (int k = 1; k <= M - 2; ++k) {
+        const double* d = dots[k];
+        double a, c;
+        tangent_coeffs(H[k - 1], H[k], H[k + 1], a, c);
+        const double tt = a * a * d[0] + 2.0 * a * c * d[2] + c * c * d[1];
+        const double nt = sqrt(fmax(tt, 0.0));
+        double cp = 0.0, cm = 0.0;
+        if (nt > 0.0) {
+            const double ft = (a * d[3] + c * d[4]) / nt;
+            const double s = (k == ci) ? -2.0 * ft : b.k_spring * (sqrt(d[0]) - sqrt(d[1])) - ft;
+            cp = s * a / nt;
+            cm = s * c / nt;
+        }
+        st->cplus[k] = cp;
+        st->cminus[k] = cm;
+        Pw += d[6] + cp * d[8] + cm * d[9];
+        FF += d[5] + cp * cp * d[0] + cm * cm * d[1] + 2.0 * cp * d[3] + 2.0 * cm * d[4] + 2.0 * cp * cm * d[2];
+        VV += d[7];
+    }
+    // FIRE (Bitzek et al. 2006) proposal; committed only if the band moves.
+    double cv = 1.0, cf = 0.0, dt = st->dt, alpha = st->alpha;
+    int np = st->n_pos;
+    if (!st->fresh) {
+        if (Pw > 0.0) {
+            const double nf = sqrt(fmax(FF, 0.0)), nv = sqrt(fmax(VV, 0.0));
+            if (nf > 0.0) {
+                cv = 1.0 - alpha;
+                cf = alpha * nv / nf;
+            }
+            if (np > b.nmin) {
+                dt = fmin(dt * b.finc, b.dtmax);
+                alpha *= b.fa;
+            }
+            np += 1;
+        } else {
+            cv = 0.0;
+            cf = 0.0;
+            alpha = b.astart;
+            dt *= b.fdec;
+            np = 0;
+        }
+    }
+    st->cv = cv;
+    st->cf = cf;
+    st->dt_new = dt;
+    st->alpha_new = alpha;
+    st->n_pos_new = np;
+}
+
+// F_NEB per row, v' = (cv v + cf F_NEB) + dt' F_NEB into the other buffer, and the
+// row maxima of |F_NEB| and |dt' v'|.
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BandDev b)
+{
+    __shared__ double lds[4 * 3];
+    BandState* st = b.st;
+    const int k = blockIdx.y;
+    if (band_stopped(st) || !image_active(st, k, 0)) return;
+    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
+    const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
+    double m[3] = {0.0, 0.0, 0.0};  // max |F_NEB row|^2, max |dr row|^2, non-finite flag
+    if (r < b.N + 3) {
+        const double cp = st->cplus[k], cm = st->cminus[k];
+        const double cv = st->cv, cf = st->cf, dt = st->dt_new;
+        const double* X0 = Xs(b, s0);
+        const double* Xm = Xs(b, sm);
+        const double* Xp = Xs(b, sp);
+        const double* V = Vs(b, st->vcur, s0);
+        double* Vn = Vs(b, st->vcur ^ 1, s0);
+        double* FN = b.FN + size_t(s0) * slot_rows(b);
+        const int rec = st->record_fneb;
+        double f[3];
+        gen_force_row<T>(b, s0, r, f);
+        double f2 = 0.0, v2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = size_t(c) * b.ld + r;
+            const double x = X0[o];
+            const double fn = f[c] + cp * (Xp[o] - x) + cm * (x - Xm[o]);
+            const double vn = (cv * V[o] + cf * fn) + dt * fn;
+            Vn[o] = vn;
+            if (rec) FN[o] = fn;
+            f2 += fn * fn;
+            const double dr = dt * vn;
+            v2 += dr * dr;
+        }
+        m[0] = f2;
+        m[1] = v2;
+        m[2] = (isfinite(f2) && isfinite(v2)) ? 0.0 : 1.0;
+    }
+    block_max<3>(m, lds);
+    if (threadIdx.x == 0) {
+        double* out = b.maxpart + (size_t(k) * b.ntR + blockIdx.x) * 3;
+        out[0] = m[0];
+        out[1] = m[1];
+        out[2] = m[2];
+    }
+}
+
+// fmax, convergence, step clamp; commit the FIRE proposal when the band moves.
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_finalize(BandDev b)
+{
+    __shared__ double lds[4 * 3];
+    BandState* st = b.st;
+    if (band_stopped(st)) {
+        if (threadIdx.x == 0) st->move = 0;
+        return;
+    }
+    const int M = st->M;
+    double m[3] = {0.0, 0.0, 0.0};
+    const int total = (M - 2) * b.ntR;
+    for (int t = threadIdx.x; t < total; t += CFNEB_TILE) {
+        const int k = 1 + t / b.ntR, tile = t % b.ntR;
+        const double* p = b.maxpart + (size_t(k) * b.ntR + tile) * 3;
+        m[0] = fmax(m[0], p[0]);
+        m[1] = fmax(m[1], p[1]);
+        m[2] = fmax(m[2], p[2]);
+    }
+    block_max<3>(m, lds);
+    if (threadIdx.x != 0) return;
+    const double fmaxv = sqrt(m[0]);
+    st->fmax = fmaxv;
+    st->move = 0;
+    st->refine_due = 0;
+    if (m[2] != 0.0 || !isfinite(fmaxv) || !isfinite(m[1])) {
+        set_error(st, CFNEB_ENONFINITE);
+        return;
+    }
+    if (fmaxv < st->f_tol) {
+        st->done = 1;
+        return;
+    }
+    const double maxdr = sqrt(m[1]);
+    st->scale = (maxdr > b.maxstep) ? b.maxstep / maxdr : 1.0;
+    st->move = 1;
+    st->dt = st->dt_new;
+    st->alpha = st->alpha_new;
+    st->n_pos = st->n_pos_new;
+    st->fresh = 0;
+    st->vcur ^= 1;
+    st->step += 1;
+    st->steps_call += 1;
+    st->refine_due = (b.refine_every > 0 && st->step % b.refine_every == 0) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_move(BandDev b)
+{
+    const BandState* st = b.st;
+    const int k = blockIdx.y;
+    if (!st->move || st->err != 0 || !image_active(st, k, 0)) return;
+    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
+    if (r >= b.N + 3) return;
+    const int s0 = st->slot[k];
+    double* X = Xs(b, s0);
+    const double* V = Vs(b, st->vcur, s0);
+    const double sc = st->scale, dt = st->dt;
+    for (int c = 0; c < 3; ++c) {
+        const size_t o = size_t(c) * b.ld + r;
+        X[o] += sc * (dt * V[o]);
+    }
+}
+
+void launch_begin_call(const BandDev& b, double f_tol, hipStream_t s)
+{
+    k_begin_call<<<1, 1, 0, s>>>(b, f_tol);
+}
+
+void launch_band_update(const BandDev& b, hipStream_t s)
+{
+    const dim3 gR(b.ntR, b.Mcap);
+    if (b.fp64)
+        k_band_dots<double><<<gR, CFNEB_TILE, 0, s>>>(b);
+    else
+        k_band_dots<float><<<gR, CFNEB_TILE, 0, s>>>(b);
+    k_band_scalars<<<1, CFNEB_TILE, 0, s>>>(b);
+    if (b.fp64)
+        k_band_update<double><<<gR, CFNEB_TILE, 0, s>>>(b);
+    else
+        k_band_update<float><<<gR, CFNEB_TILE, 0, s>>>(b);
+    k_band_finalize<<<1, CFNEB_TILE, 0, s>>>(b);
+    k_band_move<<<gR, CFNEB_TILE, 0, s>>>(b);
+}
+
+}  // namespace cfneb

@@ -1,0 +1,249 @@
+// Device-side layout and helpers of the CFNEB library (gfx950).
+//
+// HBM layout of one band (all inside the caller's workspace, 256-B aligned):
+//   X      [slot][3][ld]  FP64  generalized coordinates: rows 0..N-1 = R~ (SoA),
+//                               rows N..N+2 = the three rows of c_f B
+//   V      [2][slot][3][ld] FP64 FIRE velocities, ping-pong (vcur selects)
+//   R      [slot][3][ld]  FP64  Cartesian positions R = R~ D of the last evaluation
+//   F      [slot][3][ld]  T     Cartesian forces (T = float, or double for FP64 bands)
+//   FN     [slot][3][ld]  FP64  NEB force (only when recording is on)
+//   binfo  [slot][N]      int4  (bin, image offset n_x, n_y, n_z) per atom
+//   bins   [slot][...]    int   counts, starts, cursors, atoms-by-bin
+//   nbr    [slot][cap][N] u32   packed neighbour entries, entry-major (coalesced)
+//   ncnt   [slot][N]      int   neighbour count (may exceed cap: overflow)
+//   dvec   [slot][cap][N] T4    Tersoff: bond vector and length
+//   bo     [slot][cap][N] T2    Tersoff: b_ij and db/dzeta
+//   P      [slot][cap][N] T4    Tersoff: dU_i/dr^ij per bond
+//   geom / scal [slot]          per-image 3x3 geometry and reduced scalars
+//   partial buffers             fixed-order block partials of every reduction
+//   state                       band scalars (FIRE, slot table, flags)
+// A "slot" is a physical image buffer; the slot table maps logical image k to a slot,
+// so inserting or deleting an image rewrites the table, not the data.
+#ifndef CFNEB_DEV_H
+#define CFNEB_DEV_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cfneb.h"
+
+#define CFNEB_MAX_IMAGES 64
+#define CFNEB_TILE 256           // threads per block of every streaming kernel
+#define CFNEB_MAX_SHIFT 7        // packed shifts are 4-bit offset-binary
+#define CFNEB_J_BITS 20
+#define CFNEB_MAX_ATOMS (1 << CFNEB_J_BITS)
+
+namespace cfneb {
+
+struct ImageGeom {
+    double D[9], Dinv[9], h[9], hinv[9];
+    double omega;
+    double w[3];
+    int nb[3];
+    int reach[3];
+    int nbins;
+    int err;
+};
+
+struct ImageScal {
+    double E, H;
+    double V[9];
+    double Fcell[9];  // generalized force on the three cell rows
+};
+
+struct BandState {
+    int M;                         // current number of images
+    int slot[CFNEB_MAX_IMAGES];    // logical image -> physical slot
+    int vcur;                      // current velocity buffer
+    int step;                      // moves taken in total
+    int steps_call;                // moves taken in the current cfneb_step call
+    int done;                      // converged in the current call
+    int err;                       // first error code of the current call (0 = none)
+    int ci;                        // climbing image of the last evaluation, -1 none
+    int fresh, n_pos;
+    double dt, alpha;
+    double f_tol;
+    double fmax;                   // fmax of the last evaluation
+    int record_fneb;
+    // proposal of the current step (committed by the finalize kernel)
+    double cplus[CFNEB_MAX_IMAGES], cminus[CFNEB_MAX_IMAGES];
+    double cv, cf, dt_new, alpha_new;
+    int n_pos_new;
+    int move;
+    double scale;
+    // refine
+    int refine_due;                // 1: refine kernels act at the end of this step
+    int ins, del;                  // last refine decision (logical index, -1 none)
+    int changed;
+    int new_slot, ins_a, ins_b;    // slots of an insertion
+    double d2[CFNEB_MAX_IMAGES];   // squared spacings (reporting)
+    // readout
+    double barrier;
+    double xi[CFNEB_MAX_IMAGES];
+    double Hlog[CFNEB_MAX_IMAGES];
+};
+
+// Everything a kernel needs, passed by value.
+struct BandDev {
+    int N, ld, Mcap, ntA, ntR, nbcap, cap;
+    int potential, fp64;
+    double rc, rc2;
+    double lj_eps, lj_sig2, lj_eshift;
+    double ts_A, ts_B, ts_l1, ts_l2, ts_bn, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
+    double k_spring;
+    int climb_after, cell_filter;
+    double cf, bscale, press;
+    double dt0, dtmax, maxstep;
+    int nmin;
+    double finc, fdec, astart, fa;
+    int refine_every, ins_num, ins_den, del_num, del_den, max_images, min_images;
+    double h0[9];
+    // device pointers
+    double* X;
+    double* V;
+    double* R;
+    void* F;
+    double* FN;
+    int4* binfo;
+    int* bcount;
+    int* bstart;
+    int* bcursor;
+    int* batoms;
+    uint32_t* nbr;
+    int* ncnt;
+    void* dvec;
+    void* bo;
+    void* P;
+    ImageGeom* geom;
+    ImageScal* scal;
+    double* evpart;     // [slot][ntA][10]
+    double* dotpart;    // [k][ntR][10]
+    double* maxpart;    // [k][ntR][2]
+    uint64_t* refpart;  // [k][ntR][2]
+    double* staging;    // endpoint upload and readout area
+    BandState* st;
+};
+
+// ---------------------------------------------------------------- helpers
+__host__ __device__ inline size_t slot_rows(const BandDev& b) { return size_t(3) * b.ld; }
+
+__device__ inline double* Xs(const BandDev& b, int slot) { return b.X + size_t(slot) * slot_rows(b); }
+__device__ inline double* Vs(const BandDev& b, int buf, int slot)
+{
+    return b.V + (size_t(buf) * b.Mcap + slot) * slot_rows(b);
+}
+__device__ inline double* Rs(const BandDev& b, int slot) { return b.R + size_t(slot) * slot_rows(b); }
+
+__device__ inline uint32_t pack_nbr(int j, int n0, int n1, int n2)
+{
+    return uint32_t(j) | (uint32_t(n0 + 8) << 20) | (uint32_t(n1 + 8) << 24) | (uint32_t(n2 + 8) << 28);
+}
+__device__ inline int nbr_j(uint32_t e) { return int(e & 0xFFFFFu); }
+__device__ inline int nbr_n(uint32_t e, int k) { return int((e >> (20 + 4 * k)) & 0xFu) - 8; }
+
+// Logical image range of a per-image launch: all images, or the moving ones.
+__device__ inline bool image_active(const BandState* st, int k, int all_images)
+{
+    const int M = st->M;
+    return all_images ? (k < M) : (k >= 1 && k < M - 1);
+}
+
+__device__ inline bool band_stopped(const BandState* st) { return st->done != 0 || st->err != 0; }
+
+__device__ inline void set_error(BandState* st, int code)
+{
+    atomicCAS(&st->err, 0, code);
+}
+
+// 64-lane wavefront sum with a fixed butterfly order (deterministic).
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block (CFNEB_TILE threads = 4 waves) sum of NV doubles in a fixed order; the
+// result is valid in thread 0.  lds must hold 4 * NV doubles.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* lds)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[wid * NV + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = ((lds[q] + lds[NV + q]) + lds[2 * NV + q]) + lds[3 * NV + q];
+    __syncthreads();
+}
+
+template <int NV>
+__device__ inline void block_max(double (&v)[NV], double* lds)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_max(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[wid * NV + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            v[q] = fmax(fmax(lds[q], lds[NV + q]), fmax(lds[2 * NV + q], lds[3 * NV + q]));
+    __syncthreads();
+}
+
+// 3x3 helpers (row-major)
+__host__ __device__ inline double det3(const double* a)
+{
+    return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6])
+         + a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+__host__ __device__ inline void inv3(const double* a, double* o)
+{
+    const double id = 1.0 / det3(a);
+    o[0] = (a[4] * a[8] - a[5] * a[7]) * id;
+    o[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+    o[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+    o[3] = (a[5] * a[6] - a[3] * a[8]) * id;
+    o[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+    o[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+    o[6] = (a[3] * a[7] - a[4] * a[6]) * id;
+    o[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+    o[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+}
+__host__ __device__ inline void mm3(const double* a, const double* b, double* c)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            c[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+}
+
+// ---------------------------------------------------------------- launchers
+// Defined in the kernel translation units, called by the host runtime.
+void launch_init_endpoints(const BandDev& b, hipStream_t s);
+void launch_init_images(const BandDev& b, int M, hipStream_t s);
+void launch_init_state(const BandDev& b, int M, hipStream_t s);
+void launch_begin_call(const BandDev& b, double f_tol, hipStream_t s);
+void launch_geom(const BandDev& b, int all_images, hipStream_t s);
+void launch_nlist(const BandDev& b, int all_images, hipStream_t s);
+void launch_forces(const BandDev& b, int all_images, hipStream_t s);
+void launch_evaluate(const BandDev& b, int all_images, hipStream_t s);
+void launch_band_update(const BandDev& b, hipStream_t s);
+void launch_refine(const BandDev& b, int forced, hipStream_t s);
+void launch_readout(const BandDev& b, hipStream_t s);
+void launch_image_positions(const BandDev& b, int k, hipStream_t s);
+void launch_set_state_fixup(const BandDev& b, int M, hipStream_t s);
+
+}  // namespace cfneb
+
+#endif

@@ -1,0 +1,272 @@
+// Cell-filter geometry of every image and band construction (Sec. II.C).
+//
+// Per image: B = (cell rows of X) / c_f, D = symsqrt(B) (the rotation-free gauge,
+// Eq. (15)), h = h0 D, h^-1, Omega = |det h|, the perpendicular widths of the cell
+// and the bin grid of the cell list.
+#include "cfneb_dev.h"
+
+namespace cfneb {
+
+// Symmetric positive square root by cyclic Jacobi rotations on the symmetric part.
+// Returns false if an eigenvalue is not positive.
+__device__ bool sym_sqrt(const double* Bin, double* D)
+{
+    double a[3][3], q[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            a[i][j] = 0.5 * (Bin[3 * i + j] + Bin[3 * j + i]);
+            q[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int it = 0; it < 64; ++it) {
+        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        const double on = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off <= 1e-36 * on) break;
+        for (int pr = 0; pr < 3; ++pr) {
+            const int p = (pr == 2) ? 1 : 0;
+            const int r = (pr == 0) ? 1 : 2;
+            const double apr = a[p][r];
+            if (apr == 0.0) continue;
+            const double th = (a[r][r] - a[p][p]) / (2.0 * apr);
+            const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+            const double c = rsqrt(t * t + 1.0);
+            const double s = t * c;
+            for (int k = 0; k < 3; ++k) {
+                const double x = a[k][p], y = a[k][r];
+                a[k][p] = c * x - s * y;
+                a[k][r] = s * x + c * y;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const double x = a[p][k], y = a[r][k];
+                a[p][k] = c * x - s * y;
+                a[r][k] = s * x + c * y;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const double x = q[k][p], y = q[k][r];
+                q[k][p] = c * x - s * y;
+                q[k][r] = s * x + c * y;
+            }
+        }
+    }
+    double rt[3];
+    for (int i = 0; i < 3; ++i) {
+        if (!(a[i][i] > 0.0)) return false;
+        rt[i] = sqrt(a[i][i]);
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            D[3 * i + j] = q[i][0] * rt[0] * q[j][0] + q[i][1] * rt[1] * q[j][1] + q[i][2] * rt[2] * q[j][2];
+    return true;
+}
+
+__device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
+{
+    double B[9];
+    const double icf = 1.0 / b.cf;
+    for (int q = 0; q < 3; ++q)
+        for (int c = 0; c < 3; ++c) B[3 * q + c] = X[size_t(c) * b.ld + b.N + q] * icf;
+    if (!sym_sqrt(B, g.D)) return false;
+    inv3(g.D, g.Dinv);
+    mm3(b.h0, g.D, g.h);
+    inv3(g.h, g.hinv);
+    g.omega = fabs(det3(g.h));
+    if (!(g.omega > 0.0) || !isfinite(g.omega)) return false;
+    for (int k = 0; k < 3; ++k) {
+        const double* u = g.h + 3 * ((k + 1) % 3);
+        const double* v = g.h + 3 * ((k + 2) % 3);
+        const double cx = u[1] * v[2] - u[2] * v[1];
+        const double cy = u[2] * v[0] - u[0] * v[2];
+        const double cz = u[0] * v[1] - u[1] * v[0];
+        g.w[k] = g.omega / sqrt(cx * cx + cy * cy + cz * cz);
+    }
+    // Bins along fractional axis k have perpendicular width w_k / nb_k >= rc (1 + 1e-9),
+    // so a +-1 bin stencil holds every pair closer than rc.  Cells narrower than that
+    // get one bin and a stencil wide enough for all the periodic images needed.
+    for (int k = 0; k < 3; ++k) {
+        const double q = g.w[k] / (b.rc * (1.0 + 1e-9));
+        if (q >= 1.0) {
+            g.nb[k] = int(fmin(floor(q), 1024.0));
+            g.reach[k] = 1;
+        } else {
+            g.nb[k] = 1;
+            g.reach[k] = int(ceil(b.rc / g.w[k])) + 1;
+        }
+    }
+    while (g.nb[0] * g.nb[1] * g.nb[2] > b.nbcap) {
+        int k = 0;
+        if (g.nb[1] > g.nb[k]) k = 1;
+        if (g.nb[2] > g.nb[k]) k = 2;
+        g.nb[k] -= 1;  // wider bins keep the +-1 stencil valid
+    }
+    g.nbins = g.nb[0] * g.nb[1] * g.nb[2];
+    for (int k = 0; k < 3; ++k)
+        if (g.reach[k] > 8) return false;  // shifts beyond the 4-bit packing
+    return true;
+}
+
+__global__ void k_geom(BandDev b, int all_images)
+{
+    BandState* st = b.st;
+    const int k = threadIdx.x;
+    if (band_stopped(st) || k >= b.Mcap || !image_active(st, k, all_images)) return;
+    const int slot = st->slot[k];
+    ImageGeom g;
+    g.err = 0;
+    if (!image_geometry(b, Xs(b, slot), g)) {
+        g.err = 1;
+        set_error(st, CFNEB_ECELL);
+    }
+    b.geom[slot] = g;
+}
+
+// ---------------------------------------------------------------- construction
+// staging: RA (3N, row-major) | RB (3N) | hA (9) | hB (9) | BB (9) | h0inv (9) | hBinv (9)
+__global__ void k_init_endpoints(BandDev b)
+{
+    double* sg = b.staging + 6 * size_t(b.N);
+    const double* hB = sg + 9;
+    double* BB = sg + 18;
+    double* h0inv = sg + 27;
+    double* hBinv = sg + 36;
+    inv3(b.h0, h0inv);
+    inv3(hB, hBinv);
+    double Dr[9], DrT[9];
+    mm3(h0inv, hB, Dr);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) DrT[3 * i + j] = Dr[3 * j + i];
+    mm3(Dr, DrT, BB);
+}
+
+__global__ void k_init_images(BandDev b, int M)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (r >= b.N + 3 || k >= M) return;
+    const double* RA = b.staging;
+    const double* RB = b.staging + 3 * size_t(b.N);
+    const double* sg = b.staging + 6 * size_t(b.N);
+    const double* BB = sg + 18;
+    const double* h0inv = sg + 27;
+    const double* hBinv = sg + 36;
+    double xa[3], xb[3];
+    if (r < b.N) {
+        const double* a = RA + 3 * size_t(r);
+        const double* c = RB + 3 * size_t(r);
+        double ds[3];
+        for (int q = 0; q < 3; ++q) {
+            const double sa = a[0] * h0inv[q] + a[1] * h0inv[3 + q] + a[2] * h0inv[6 + q];
+            const double sb = c[0] * hBinv[q] + c[1] * hBinv[3 + q] + c[2] * hBinv[6 + q];
+            ds[q] = sb - sa;
+            ds[q] -= rint(ds[q]);
+        }
+        for (int q = 0; q < 3; ++q) {
+            xa[q] = a[q];
+            xb[q] = a[q] + (ds[0] * b.h0[q] + ds[1] * b.h0[3 + q] + ds[2] * b.h0[6 + q]);
+        }
+    } else {
+        const int row = r - b.N;
+        for (int q = 0; q < 3; ++q) {
+            xa[q] = (row == q) ? b.cf : 0.0;
+            xb[q] = b.cf * BB[3 * row + q];
+        }
+    }
+    double* X = Xs(b, k);
+    const double t = double(k) / double(M - 1);
+    {
+#pragma clang fp contract(off)
+        for (int q = 0; q < 3; ++q) {
+            double x;
+            if (k == 0)
+                x = xa[q];
+            else if (k == M - 1)
+                x = xb[q];
+            else
+                x = xa[q] + t * (xb[q] - xa[q]);
+            X[size_t(q) * b.ld + r] = x;
+        }
+    }
+}
+
+__global__ void k_init_state(BandDev b, int M)
+{
+    BandState* st = b.st;
+    st->M = M;
+    for (int k = 0; k < CFNEB_MAX_IMAGES; ++k) st->slot[k] = (k < b.Mcap) ? k : 0;
+    st->vcur = 0;
+    st->step = 0;
+    st->steps_call = 0;
+    st->done = 0;
+    st->err = 0;
+    st->ci = -1;
+    st->fresh = 1;
+    st->n_pos = 0;
+    st->alpha = b.astart;
+    st->dt = b.dt0;
+    st->f_tol = 0.0;
+    st->fmax = 0.0;
+    st->move = 0;
+    st->refine_due = 0;
+    st->ins = st->del = -1;
+    st->changed = 0;
+}
+
+// Positions and cell of one logical image from the current coordinates.
+__global__ void k_image_geom_one(BandDev b, int k)
+{
+    BandState* st = b.st;
+    if (k < 0 || k >= st->M) return;
+    ImageGeom g;
+    const bool ok = image_geometry(b, Xs(b, st->slot[k]), g);
+    double* out = b.staging + 3 * size_t(b.N);
+    for (int q = 0; q < 9; ++q) out[q] = ok ? g.h[q] : 0.0;
+    for (int q = 0; q < 9; ++q) out[9 + q] = ok ? g.D[q] : 0.0;
+}
+
+__global__ void k_image_positions(BandDev b, int k)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    BandState* st = b.st;
+    if (i >= b.N || k < 0 || k >= st->M) return;
+    const double* X = Xs(b, st->slot[k]);
+    const double* D = b.staging + 3 * size_t(b.N) + 9;
+    const double x = X[i], y = X[b.ld + i], z = X[2 * size_t(b.ld) + i];
+    for (int c = 0; c < 3; ++c) b.staging[3 * size_t(i) + c] = x * D[c] + y * D[3 + c] + z * D[6 + c];
+}
+
+// After a checkpoint restore: the slot table is the identity and v is taken as given.
+__global__ void k_set_state_fixup(BandDev b, int M)
+{
+    BandState* st = b.st;
+    st->M = M;
+    for (int k = 0; k < CFNEB_MAX_IMAGES; ++k) st->slot[k] = (k < b.Mcap) ? k : 0;
+    st->vcur = 0;
+    st->done = 0;
+    st->err = 0;
+}
+
+void launch_init_endpoints(const BandDev& b, hipStream_t s) { k_init_endpoints<<<1, 1, 0, s>>>(b); }
+
+void launch_init_images(const BandDev& b, int M, hipStream_t s)
+{
+    dim3 grid((b.N + 3 + CFNEB_TILE - 1) / CFNEB_TILE, M);
+    k_init_images<<<grid, CFNEB_TILE, 0, s>>>(b, M);
+}
+
+void launch_init_state(const BandDev& b, int M, hipStream_t s) { k_init_state<<<1, 1, 0, s>>>(b, M); }
+
+void launch_geom(const BandDev& b, int all_images, hipStream_t s)
+{
+    k_geom<<<1, CFNEB_MAX_IMAGES, 0, s>>>(b, all_images);
+}
+
+void launch_image_positions(const BandDev& b, int k, hipStream_t s)
+{
+    k_image_geom_one<<<1, 1, 0, s>>>(b, k);
+    k_image_positions<<<(b.N + CFNEB_TILE - 1) / CFNEB_TILE, CFNEB_TILE, 0, s>>>(b, k);
+}
+
+void launch_set_state_fixup(const BandDev& b, int M, hipStream_t s)
+{
+    k_set_state_fixup<<<1, 1, 0, s>>>(b, M);
+}
+
+}  // namespace cfneb

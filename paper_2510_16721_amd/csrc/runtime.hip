@@ -1,0 +1,681 @@
+// Host runtime and C ABI of the CFNEB library: workspace layout, band creation,
+// the captured step graph, checkpoints and readout.  All arithmetic of the band
+// step runs in the kernels; the host only lays out memory, launches and copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cfneb_dev.h"
+
+using namespace cfneb;
+
+namespace {
+
+constexpr double kEvPerA3InGPa = 160.21766208;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    int N, ld, Mcap, ntA, ntR, nbcap, cap, fp64, tersoff;
+    size_t X, V, R, F, FN, binfo, bcount, bstart, bcursor, batoms, nbr, ncnt, dvec, bo, P, geom, scal,
+        evpart, dotpart, maxpart, refpart, staging, state, total;
+};
+
+bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout* L)
+{
+    if (n_atoms < 1 || n_atoms >= CFNEB_MAX_ATOMS) return false;
+    if (max_images < 3 || max_images > CFNEB_MAX_IMAGES) return false;
+    if (p->nbr_cap < 1 || p->nbr_cap > 1024) return false;
+    L->N = int(n_atoms);
+    L->ld = ((L->N + 3 + 63) / 64) * 64;
+    L->Mcap = max_images;
+    L->ntA = (L->N + CFNEB_TILE - 1) / CFNEB_TILE;
+    L->ntR = (L->N + 3 + CFNEB_TILE - 1) / CFNEB_TILE;
+    L->nbcap = 2 * L->N + 64;
+    L->cap = p->nbr_cap;
+    L->fp64 = p->force_fp64 ? 1 : 0;
+    L->tersoff = (p->potential == CFNEB_TERSOFF_C) ? 1 : 0;
+    const size_t M = size_t(L->Mcap), N = size_t(L->N), rows = 3 * size_t(L->ld);
+    const size_t tsz = L->fp64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L->X = take(M * rows * 8);
+    L->V = take(2 * M * rows * 8);
+    L->R = take(M * rows * 8);
+    L->F = take(M * rows * tsz);
+    L->FN = take(M * rows * 8);
+    L->binfo = take(M * N * 16);
+    L->bcount = take(M * (L->nbcap + 1) * 4);
+    L->bstart = take(M * (L->nbcap + 1) * 4);
+    L->bcursor = take(M * (L->nbcap + 1) * 4);
+    L->batoms = take(M * N * 4);
+    L->nbr = take(M * size_t(L->cap) * N * 4);
+    L->ncnt = take(M * N * 4);
+    L->dvec = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
+    L->bo = take(L->tersoff ? M * size_t(L->cap) * N * 2 * tsz : 0);
+    L->P = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
+    L->geom = take(M * sizeof(ImageGeom));
+    L->scal = take(M * sizeof(ImageScal));
+    L->evpart = take(M * L->ntA * 10 * 8);
+    L->dotpart = take(M * L->ntR * 10 * 8);
+    L->maxpart = take(M * L->ntR * 3 * 8);
+    L->refpart = take(M * L->ntR * 2 * 8);
+    L->staging = take((6 * N + 64) * 8);
+    L->state = take(sizeof(BandState));
+    L->total = off;
+    return true;
+}
+
+const char* err_text(int code)
+{
+    switch (code) {
+    case CFNEB_OK: return "ok";
+    case CFNEB_EINVAL: return "invalid argument";
+    case CFNEB_ENOMEM: return "workspace too small";
+    case CFNEB_EHIP: return "HIP runtime error";
+    case CFNEB_ECELL: return "cell not positive definite or neighbour shift out of range";
+    case CFNEB_ENEIGH: return "neighbour list capacity exceeded";
+    case CFNEB_ENONFINITE: return "non-finite energy, virial or force";
+    case CFNEB_ECAPACITY: return "image capacity exceeded";
+    case CFNEB_ERANGE: return "spacing term out of range";
+    default: return "unknown error";
+    }
+}
+
+}  // namespace
+
+struct cfneb_band {
+    cfneb_params p;
+    BandDev d;
+    Layout L;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BandState* host_state = nullptr;  // pinned
+    bool use_graph = true;
+    std::string last_error;
+};
+
+namespace {
+
+int fail(cfneb_band* b, int code, const std::string& what)
+{
+    if (b) b->last_error = what + ": " + err_text(code);
+    return code;
+}
+
+#define HIP_TRY(b, call)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((b), CFNEB_EHIP, std::string(#call) + " -> " + hipGetErrorString(e_)); \
+    } while (0)
+
+int read_state(cfneb_band* b)
+{
+    HIP_TRY(b, hipMemcpyAsync(b->host_state, b->d.st, sizeof(BandState), hipMemcpyDeviceToHost,
+                              b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    return CFNEB_OK;
+}
+
+int write_state(cfneb_band* b)
+{
+    HIP_TRY(b, hipMemcpyAsync(b->d.st, b->host_state, sizeof(BandState), hipMemcpyHostToDevice,
+                              b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    return CFNEB_OK;
+}
+
+int check_kernels(cfneb_band* b, const char* what)
+{
+    HIP_TRY(b, hipGetLastError());
+    (void)what;
+    return CFNEB_OK;
+}
+
+void fill_dev(cfneb_band* b, void* ws)
+{
+    const cfneb_params* p = &b->p;
+    const Layout& L = b->L;
+    BandDev& d = b->d;
+    std::memset(&d, 0, sizeof(d));
+    d.N = L.N;
+    d.ld = L.ld;
+    d.Mcap = L.Mcap;
+    d.ntA = L.ntA;
+    d.ntR = L.ntR;
+    d.nbcap = L.nbcap;
+    d.cap = L.cap;
+    d.potential = p->potential;
+    d.fp64 = L.fp64;
+    if (p->potential == CFNEB_LJ) {
+        d.rc = p->lj_rc;
+    } else {
+        d.rc = p->ts_S;
+    }
+    d.rc2 = d.rc * d.rc;
+    d.lj_eps = p->lj_eps;
+    d.lj_sig2 = p->lj_sigma * p->lj_sigma;
+    if (p->lj_shift) {
+        const double q = d.lj_sig2 / (p->lj_rc * p->lj_rc);
+        const double q3 = q * q * q;
+        d.lj_eshift = 4.0 * p->lj_eps * (q3 * q3 - q3);
+    }
+    d.ts_A = p->ts_A;
+    d.ts_B = p->ts_B;
+    d.ts_l1 = p->ts_lambda1;
+    d.ts_l2 = p->ts_lambda2;
+    d.ts_bn = std::pow(p->ts_beta, p->ts_n);
+    d.ts_n = p->ts_n;
+    d.ts_c2 = p->ts_c * p->ts_c;
+    d.ts_d2 = p->ts_d * p->ts_d;
+    d.ts_c2d2 = d.ts_c2 / d.ts_d2;
+    d.ts_h = p->ts_h;
+    d.ts_R = p->ts_R;
+    d.ts_S = p->ts_S;
+    d.k_spring = p->k_spring;
+    d.climb_after = p->climb_after;
+    d.cell_filter = p->cell_filter;
+    d.cf = p->cell_factor > 0.0 ? p->cell_factor : double(L.N);
+    d.bscale = p->b_force_scale;
+    d.press = p->pressure_GPa / kEvPerA3InGPa;
+    d.dt0 = p->fire_dt0;
+    d.dtmax = p->fire_dtmax;
+    d.maxstep = p->fire_maxstep;
+    d.nmin = p->fire_nmin;
+    d.finc = p->fire_finc;
+    d.fdec = p->fire_fdec;
+    d.astart = p->fire_astart;
+    d.fa = p->fire_fa;
+    d.refine_every = p->refine_every;
+    d.ins_num = p->ins_num;
+    d.ins_den = p->ins_den;
+    d.del_num = p->del_num;
+    d.del_den = p->del_den;
+    d.max_images = p->max_images;
+    d.min_images = p->min_images;
+    char* base = static_cast<char*>(ws);
+    d.X = reinterpret_cast<double*>(base + L.X);
+    d.V = reinterpret_cast<double*>(base + L.V);
+    d.R = reinterpret_cast<double*>(base + L.R);
+    d.F = base + L.F;
+    d.FN = reinterpret_cast<double*>(base + L.FN);
+    d.binfo = reinterpret_cast<int4*>(base + L.binfo);
+    d.bcount = reinterpret_cast<int*>(base + L.bcount);
+    d.bstart = reinterpret_cast<int*>(base + L.bstart);
+    d.bcursor = reinterpret_cast<int*>(base + L.bcursor);
+    d.batoms = reinterpret_cast<int*>(base + L.batoms);
+    d.nbr = reinterpret_cast<uint32_t*>(base + L.nbr);
+    d.ncnt = reinterpret_cast<int*>(base + L.ncnt);
+    d.dvec = L.tersoff ? base + L.dvec : nullptr;
+    d.bo = L.tersoff ? base + L.bo : nullptr;
+    d.P = L.tersoff ? base + L.P : nullptr;
+    d.geom = reinterpret_cast<ImageGeom*>(base + L.geom);
+    d.scal = reinterpret_cast<ImageScal*>(base + L.scal);
+    d.evpart = reinterpret_cast<double*>(base + L.evpart);
+    d.dotpart = reinterpret_cast<double*>(base + L.dotpart);
+    d.maxpart = reinterpret_cast<double*>(base + L.maxpart);
+    d.refpart = reinterpret_cast<uint64_t*>(base + L.refpart);
+    d.staging = reinterpret_cast<double*>(base + L.staging);
+    d.st = reinterpret_cast<BandState*>(base + L.state);
+}
+
+int validate(const cfneb_params* p, int64_t n_atoms)
+{
+    if (!p) return CFNEB_EINVAL;
+    if (p->potential != CFNEB_LJ && p->potential != CFNEB_TERSOFF_C) return CFNEB_EINVAL;
+    if (n_atoms < 1 || n_atoms >= CFNEB_MAX_ATOMS) return CFNEB_EINVAL;
+    if (p->n_images < 3 || p->max_images < p->n_images || p->max_images > CFNEB_MAX_IMAGES)
+        return CFNEB_EINVAL;
+    if (p->min_images < 3) return CFNEB_EINVAL;
+    if (p->cell_filter != 0 && p->cell_filter != 2) return CFNEB_EINVAL;
+    if (p->nbr_cap < 1 || p->nbr_cap > 1024) return CFNEB_EINVAL;
+    if (!(p->fire_dt0 > 0.0) || !(p->fire_maxstep > 0.0)) return CFNEB_EINVAL;
+    if (p->refine_every < 0 || p->ins_num < 0 || p->ins_den < 1 || p->del_num < 0 || p->del_den < 1)
+        return CFNEB_EINVAL;
+    const double rc = p->potential == CFNEB_LJ ? p->lj_rc : p->ts_S;
+    if (!(rc > 0.0)) return CFNEB_EINVAL;
+    return CFNEB_OK;
+}
+
+int image_slot(const cfneb_band* b, int k)
+{
+    if (k < 0 || k >= b->host_state->M) return -1;
+    return b->host_state->slot[k];
+}
+
+// SoA slab (3 x ld) -> row-major (rows x 3)
+void soa_to_aos(const double* soa, int ld, int rows, double* aos)
+{
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < 3; ++c) aos[3 * size_t(r) + c] = soa[size_t(c) * ld + r];
+}
+
+void aos_to_soa(const double* aos, int ld, int rows, double* soa)
+{
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < 3; ++c) soa[size_t(c) * ld + r] = aos[3 * size_t(r) + c];
+}
+
+int launch_step_direct(cfneb_band* b)
+{
+    launch_evaluate(b->d, 0, b->stream);
+    launch_band_update(b->d, b->stream);
+    launch_refine(b->d, 0, b->stream);
+    return check_kernels(b, "step");
+}
+
+int ensure_graph(cfneb_band* b)
+{
+    if (b->exec || !b->use_graph) return CFNEB_OK;
+    HIP_TRY(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed));
+    launch_evaluate(b->d, 0, b->capture_stream);
+    launch_band_update(b->d, b->capture_stream);
+    launch_refine(b->d, 0, b->capture_stream);
+    HIP_TRY(b, hipStreamEndCapture(b->capture_stream, &b->graph));
+    HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return CFNEB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfneb_params_default(int potential, cfneb_params* out)
+{
+    if (!out || (potential != CFNEB_LJ && potential != CFNEB_TERSOFF_C)) return CFNEB_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    cfneb_params& p = *out;
+    p.potential = potential;
+    p.force_fp64 = 0;
+    p.lj_eps = 1.0;
+    p.lj_sigma = 1.0;
+    p.lj_rc = 2.5;
+    p.lj_shift = 1;
+    p.ts_A = 1393.6;
+    p.ts_B = 346.74;
+    p.ts_lambda1 = 3.4879;
+    p.ts_lambda2 = 2.2119;
+    p.ts_beta = 1.5724e-7;
+    p.ts_n = 0.72751;
+    p.ts_c = 38049.0;
+    p.ts_d = 4.3484;
+    p.ts_h = -0.57058;
+    p.ts_R = 1.8;
+    p.ts_S = 2.1;
+    p.n_images = 7;
+    p.max_images = 7;
+    p.min_images = 3;
+    p.k_spring = 1.0;
+    p.climb_after = 50;
+    p.cell_filter = 2;
+    p.cell_factor = 0.0;
+    p.b_force_scale = 1.0;
+    p.pressure_GPa = 0.0;
+    p.fire_dt0 = potential == CFNEB_LJ ? 0.005 : 0.05;
+    p.fire_dtmax = 10.0 * p.fire_dt0;
+    p.fire_maxstep = 0.1;
+    p.fire_nmin = 5;
+    p.fire_finc = 1.1;
+    p.fire_fdec = 0.5;
+    p.fire_astart = 0.1;
+    p.fire_fa = 0.99;
+    p.refine_every = 0;
+    p.ins_num = 9;
+    p.ins_den = 4;
+    p.del_num = 1;
+    p.del_den = 4;
+    p.nbr_cap = potential == CFNEB_LJ ? 128 : 16;
+    return CFNEB_OK;
+}
+
+int cfneb_band_bytes(const cfneb_params* p, int64_t n_atoms, int max_images, size_t* bytes)
+{
+    if (!bytes) return CFNEB_EINVAL;
+    const int rc = validate(p, n_atoms);
+    if (rc != CFNEB_OK) return rc;
+    Layout L;
+    if (!make_layout(p, n_atoms, max_images > 0 ? max_images : p->max_images, &L)) return CFNEB_EINVAL;
+    *bytes = L.total;
+    return CFNEB_OK;
+}
+
+int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* types,
+                      const double* pos_init, const double* cell_init, const double* pos_final,
+                      const double* cell_final, void* workspace, size_t workspace_bytes,
+                      void* hip_stream, cfneb_band** out)
+{
+    (void)types;
+    if (!out || !pos_init || !cell_init || !pos_final || !cell_final || !workspace) return CFNEB_EINVAL;
+    *out = nullptr;
+    int rc = validate(p, n_atoms);
+    if (rc != CFNEB_OK) return rc;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return CFNEB_EINVAL;
+    auto* b = new (std::nothrow) cfneb_band();
+    if (!b) return CFNEB_ENOMEM;
+    b->p = *p;
+    if (!make_layout(p, n_atoms, p->max_images, &b->L)) {
+        delete b;
+        return CFNEB_EINVAL;
+    }
+    if (workspace_bytes < b->L.total) {
+        delete b;
+        return CFNEB_ENOMEM;
+    }
+    const char* ng = std::getenv("CFNEB_NO_GRAPH");
+    b->use_graph = !(ng && ng[0] == '1');
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    fill_dev(b, workspace);
+    for (int q = 0; q < 9; ++q) b->d.h0[q] = cell_init[q];
+    auto bail = [&](int code) {
+        cfneb_destroy(b);
+        return code;
+    };
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->host_state), sizeof(BandState), hipHostMallocDefault) !=
+        hipSuccess)
+        return bail(CFNEB_EHIP);
+    if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(CFNEB_EHIP);
+    const size_t N = size_t(n_atoms);
+    if (hipMemsetAsync(workspace, 0, b->L.total, b->stream) != hipSuccess) return bail(CFNEB_EHIP);
+    // upload the endpoints to the staging area: RA | RB | hA | hB
+    std::vector<double> stage(6 * N + 18);
+    std::memcpy(stage.data(), pos_init, 3 * N * sizeof(double));
+    std::memcpy(stage.data() + 3 * N, pos_final, 3 * N * sizeof(double));
+    std::memcpy(stage.data() + 6 * N, cell_init, 9 * sizeof(double));
+    std::memcpy(stage.data() + 6 * N + 9, cell_final, 9 * sizeof(double));
+    if (hipMemcpyAsync(b->d.staging, stage.data(), stage.size() * sizeof(double), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess)
+        return bail(CFNEB_EHIP);
+    launch_init_endpoints(b->d, b->stream);
+    launch_init_images(b->d, p->n_images, b->stream);
+    launch_init_state(b->d, p->n_images, b->stream);
+    launch_evaluate(b->d, 1, b->stream);
+    if (hipGetLastError() != hipSuccess) return bail(CFNEB_EHIP);
+    rc = read_state(b);
+    if (rc != CFNEB_OK) return bail(rc);
+    if (b->host_state->err != 0) return bail(b->host_state->err);
+    *out = b;
+    return CFNEB_OK;
+}
+
+int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, double* fmax,
+               int* converged)
+{
+    if (!b || max_steps < 0) return CFNEB_EINVAL;
+    launch_begin_call(b->d, f_tol, b->stream);
+    int rc = ensure_graph(b);
+    if (rc != CFNEB_OK) return rc;
+    const int check_every = 16;
+    for (int s = 0; s < max_steps; ++s) {
+        if (b->exec) {
+            HIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+        } else {
+            rc = launch_step_direct(b);
+            if (rc != CFNEB_OK) return rc;
+        }
+        if ((s + 1) % check_every == 0 && s + 1 < max_steps) {
+            rc = read_state(b);
+            if (rc != CFNEB_OK) return rc;
+            if (b->host_state->done || b->host_state->err) break;
+        }
+    }
+    rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    const BandState& st = *b->host_state;
+    if (steps_done) *steps_done = st.steps_call;
+    if (fmax) *fmax = st.fmax;
+    if (converged) *converged = st.done;
+    if (st.err != 0) return fail(b, st.err, "cfneb_step");
+    return CFNEB_OK;
+}
+
+int cfneb_refine(cfneb_band* b, int* inserted_at, int* deleted_at)
+{
+    if (!b) return CFNEB_EINVAL;
+    launch_begin_call(b->d, 0.0, b->stream);
+    launch_refine(b->d, 1, b->stream);
+    int rc = check_kernels(b, "refine");
+    if (rc == CFNEB_OK) rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    if (inserted_at) *inserted_at = b->host_state->ins;
+    if (deleted_at) *deleted_at = b->host_state->del;
+    if (b->host_state->err != 0) return fail(b, b->host_state->err, "cfneb_refine");
+    return CFNEB_OK;
+}
+
+int cfneb_energies(const cfneb_band* cb, double* H, int cap, int* n_images, double* barrier,
+                   int* ci_index, double* path_coord)
+{
+    auto* b = const_cast<cfneb_band*>(cb);
+    if (!b) return CFNEB_EINVAL;
+    launch_readout(b->d, b->stream);
+    int rc = check_kernels(b, "readout");
+    if (rc == CFNEB_OK) rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    const BandState& st = *b->host_state;
+    if (n_images) *n_images = st.M;
+    if (H && cap < st.M) return fail(b, CFNEB_EINVAL, "cfneb_energies: cap");
+    for (int k = 0; k < st.M; ++k) {
+        if (H) H[k] = st.Hlog[k];
+        if (path_coord) path_coord[k] = st.xi[k];
+    }
+    if (barrier) *barrier = st.barrier;
+    if (ci_index) *ci_index = st.ci;
+    return CFNEB_OK;
+}
+
+int cfneb_get_image(const cfneb_band* cb, int k, double* pos, double* cell)
+{
+    auto* b = const_cast<cfneb_band*>(cb);
+    if (!b) return CFNEB_EINVAL;
+    int rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    if (image_slot(b, k) < 0) return CFNEB_EINVAL;
+    launch_image_positions(b->d, k, b->stream);
+    rc = check_kernels(b, "get_image");
+    if (rc != CFNEB_OK) return rc;
+    const size_t N = size_t(b->L.N);
+    if (pos)
+        HIP_TRY(b, hipMemcpyAsync(pos, b->d.staging, 3 * N * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if (cell)
+        HIP_TRY(b, hipMemcpyAsync(cell, b->d.staging + 3 * N, 9 * sizeof(double), hipMemcpyDeviceToHost,
+                                  b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    return CFNEB_OK;
+}
+
+int cfneb_get_state(const cfneb_band* cb, double* X, double* v, int cap_images, int* n_images,
+                    cfneb_fire_state* fs)
+{
+    auto* b = const_cast<cfneb_band*>(cb);
+    if (!b) return CFNEB_EINVAL;
+    int rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    const BandState st = *b->host_state;
+    if (n_images) *n_images = st.M;
+    if ((X || v) && cap_images < st.M) return fail(b, CFNEB_EINVAL, "cfneb_get_state: cap");
+    const int rows = b->L.N + 3, ld = b->L.ld;
+    std::vector<double> slab(3 * size_t(ld));
+    for (int k = 0; k < st.M; ++k) {
+        const int slot = st.slot[k];
+        if (X) {
+            HIP_TRY(b, hipMemcpy(slab.data(), b->d.X + size_t(slot) * 3 * ld, slab.size() * 8,
+                                 hipMemcpyDeviceToHost));
+            soa_to_aos(slab.data(), ld, rows, X + size_t(k) * 3 * rows);
+        }
+        if (v) {
+            const double* src = b->d.V + (size_t(st.vcur) * b->L.Mcap + slot) * 3 * ld;
+            HIP_TRY(b, hipMemcpy(slab.data(), src, slab.size() * 8, hipMemcpyDeviceToHost));
+            soa_to_aos(slab.data(), ld, rows, v + size_t(k) * 3 * rows);
+        }
+    }
+    if (fs) {
+        fs->dt = st.dt;
+        fs->alpha = st.alpha;
+        fs->n_pos = st.n_pos;
+        fs->fresh = st.fresh;
+        fs->step = st.step;
+        fs->ci = st.ci;
+    }
+    return CFNEB_OK;
+}
+
+int cfneb_set_state(cfneb_band* b, int n_images, const double* X, const double* v,
+                    const cfneb_fire_state* fs)
+{
+    if (!b || !X || !fs || n_images < 3 || n_images > b->L.Mcap) return CFNEB_EINVAL;
+    int rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    const int rows = b->L.N + 3, ld = b->L.ld;
+    std::vector<double> slab(3 * size_t(ld), 0.0);
+    for (int k = 0; k < n_images; ++k) {
+        aos_to_soa(X + size_t(k) * 3 * rows, ld, rows, slab.data());
+        HIP_TRY(b, hipMemcpy(b->d.X + size_t(k) * 3 * ld, slab.data(), slab.size() * 8, hipMemcpyHostToDevice));
+        std::fill(slab.begin(), slab.end(), 0.0);
+        if (v && k > 0 && k < n_images - 1) aos_to_soa(v + size_t(k) * 3 * rows, ld, rows, slab.data());
+        HIP_TRY(b, hipMemcpy(b->d.V + size_t(k) * 3 * ld, slab.data(), slab.size() * 8, hipMemcpyHostToDevice));
+        std::fill(slab.begin(), slab.end(), 0.0);
+    }
+    BandState& st = *b->host_state;
+    st.M = n_images;
+    for (int k = 0; k < CFNEB_MAX_IMAGES; ++k) st.slot[k] = k < b->L.Mcap ? k : 0;
+    st.vcur = 0;
+    st.dt = fs->dt;
+    st.alpha = fs->alpha;
+    st.n_pos = fs->n_pos;
+    st.fresh = fs->fresh;
+    st.step = fs->step;
+    st.ci = fs->ci;
+    st.done = 0;
+    st.err = 0;
+    st.refine_due = 0;
+    rc = write_state(b);
+    if (rc != CFNEB_OK) return rc;
+    launch_evaluate(b->d, 1, b->stream);
+    rc = check_kernels(b, "set_state");
+    if (rc == CFNEB_OK) rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    if (b->host_state->err != 0) return fail(b, b->host_state->err, "cfneb_set_state");
+    return CFNEB_OK;
+}
+
+int cfneb_image_data(const cfneb_band* cb, int k, double* E, double* H, double* V, double* F,
+                     double* Fg, double* Fneb, double* R, double* h)
+{
+    auto* b = const_cast<cfneb_band*>(cb);
+    if (!b) return CFNEB_EINVAL;
+    int rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    const int slot = image_slot(b, k);
+    if (slot < 0) return CFNEB_EINVAL;
+    const int N = b->L.N, ld = b->L.ld;
+    ImageScal sc;
+    ImageGeom g;
+    HIP_TRY(b, hipMemcpy(&sc, b->d.scal + slot, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(b, hipMemcpy(&g, b->d.geom + slot, sizeof(g), hipMemcpyDeviceToHost));
+    if (E) *E = sc.E;
+    if (H) *H = sc.H;
+    if (V) std::memcpy(V, sc.V, 9 * sizeof(double));
+    if (h) std::memcpy(h, g.h, 9 * sizeof(double));
+    std::vector<double> slab(3 * size_t(ld));
+    if (F || Fg) {
+        std::vector<double> fa(3 * size_t(N));
+        if (b->L.fp64) {
+            HIP_TRY(b, hipMemcpy(slab.data(), static_cast<double*>(b->d.F) + size_t(slot) * 3 * ld, slab.size() * 8,
+                                 hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> sf(3 * size_t(ld));
+            HIP_TRY(b, hipMemcpy(sf.data(), static_cast<float*>(b->d.F) + size_t(slot) * 3 * ld, sf.size() * 4,
+                                 hipMemcpyDeviceToHost));
+            for (size_t q = 0; q < sf.size(); ++q) slab[q] = double(sf[q]);
+        }
+        soa_to_aos(slab.data(), ld, N, fa.data());
+        if (F) std::memcpy(F, fa.data(), fa.size() * sizeof(double));
+        if (Fg) {
+            // generalized force rows as the band kernels form them: F D^T, then the
+            // lattice force rows
+            for (int i = 0; i < N; ++i)
+                for (int c = 0; c < 3; ++c)
+                    Fg[3 * size_t(i) + c] = fa[3 * size_t(i)] * g.D[3 * c] + fa[3 * size_t(i) + 1] * g.D[3 * c + 1] +
+                                            fa[3 * size_t(i) + 2] * g.D[3 * c + 2];
+            std::memcpy(Fg + 3 * size_t(N), sc.Fcell, 9 * sizeof(double));
+        }
+    }
+    if (Fneb) {
+        HIP_TRY(b, hipMemcpy(slab.data(), b->d.FN + size_t(slot) * 3 * ld, slab.size() * 8, hipMemcpyDeviceToHost));
+        soa_to_aos(slab.data(), ld, N + 3, Fneb);
+    }
+    if (R) {
+        HIP_TRY(b, hipMemcpy(slab.data(), b->d.R + size_t(slot) * 3 * ld, slab.size() * 8, hipMemcpyDeviceToHost));
+        soa_to_aos(slab.data(), ld, N, R);
+    }
+    return CFNEB_OK;
+}
+
+int cfneb_record_neb_force(cfneb_band* b, int on)
+{
+    if (!b) return CFNEB_EINVAL;
+    int rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    b->host_state->record_fneb = on ? 1 : 0;
+    return write_state(b);
+}
+
+int cfneb_neighbours(const cfneb_band* cb, int k, int32_t* cnt, int32_t* ent, int64_t cap, int64_t* total)
+{
+    auto* b = const_cast<cfneb_band*>(cb);
+    if (!b || !cnt) return CFNEB_EINVAL;
+    int rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    const int slot = image_slot(b, k);
+    if (slot < 0) return CFNEB_EINVAL;
+    const size_t N = size_t(b->L.N), C = size_t(b->L.cap);
+    std::vector<uint32_t> nb(C * N);
+    HIP_TRY(b, hipMemcpy(cnt, b->d.ncnt + size_t(slot) * N, N * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(b, hipMemcpy(nb.data(), b->d.nbr + size_t(slot) * C * N, nb.size() * 4, hipMemcpyDeviceToHost));
+    int64_t t = 0;
+    for (size_t i = 0; i < N; ++i) {
+        const int c = cnt[i] < int(C) ? cnt[i] : int(C);
+        for (int e = 0; e < c; ++e, ++t) {
+            if (t >= cap || !ent) continue;
+            const uint32_t v = nb[size_t(e) * N + i];
+            ent[4 * t + 0] = int32_t(v & 0xFFFFFu);
+            ent[4 * t + 1] = int32_t((v >> 20) & 0xFu) - 8;
+            ent[4 * t + 2] = int32_t((v >> 24) & 0xFu) - 8;
+            ent[4 * t + 3] = int32_t((v >> 28) & 0xFu) - 8;
+        }
+    }
+    if (total) *total = t;
+    return CFNEB_OK;
+}
+
+int cfneb_destroy(cfneb_band* b)
+{
+    if (!b) return CFNEB_EINVAL;
+    if (b->stream || b->host_state) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->host_state) (void)hipHostFree(b->host_state);
+    delete b;
+    return CFNEB_OK;
+}
+
+const char* cfneb_strerror(int code) { return err_text(code); }
+
+const char* cfneb_last_error(const cfneb_band* b) { return b ? b->last_error.c_str() : "no band"; }
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+"""The C-ABI library loads on a machine without a GPU and exports every entry
+point that include/cfneb.h declares; host-only calls work."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "cfneb.h")).read()
+    return sorted(set(re.findall(r"\b(cfneb_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2510_16721_amd import cfneb
+    if not os.path.exists(cfneb.LIB_PATH):
+        from paper_2510_16721_amd import build
+        build.build()
+    return cfneb.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert "cfneb_create_band" in names and "cfneb_step" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_binding_covers_the_header():
+    from paper_2510_16721_amd import cfneb
+    assert sorted(cfneb.SYMBOLS) == _declared()
+
+
+def test_params_default_and_struct_layout(L):
+    from paper_2510_16721_amd import cfneb
+    p = cfneb.default_params(cfneb.CFNEB_TERSOFF_C)
+    # the last field lands where the C struct has it only if the layouts agree
+    assert p.nbr_cap == 16 and p.del_den == 4 and p.ts_S == 2.1 and p.ts_c == 38049.0
+    p = cfneb.default_params(cfneb.CFNEB_LJ)
+    assert p.nbr_cap == 128 and p.fire_dt0 == 0.005 and p.fire_dtmax == pytest.approx(0.05)
+
+
+def test_band_bytes_and_argument_checks(L):
+    from paper_2510_16721_amd import cfneb
+    p = cfneb.default_params(cfneb.CFNEB_LJ, n_images=7, max_images=7)
+    small = cfneb.band_bytes(p, 255)
+    big = cfneb.band_bytes(p, 255, 40)
+    assert 0 < small < big
+    with pytest.raises(cfneb.CfnebError):
+        cfneb.band_bytes(p, 0)
+    bad = cfneb.default_params(cfneb.CFNEB_LJ, n_images=2)
+    with pytest.raises(cfneb.CfnebError):
+        cfneb.band_bytes(bad, 10)
+    bad = cfneb.default_params(cfneb.CFNEB_LJ, max_images=65, n_images=7)
+    with pytest.raises(cfneb.CfnebError):
+        cfneb.band_bytes(bad, 10)
+    assert L.cfneb_strerror(-5) == b"neighbour list capacity exceeded"
