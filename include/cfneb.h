@@ -88,7 +88,27 @@ typedef struct cfneb_fire_state {
     int fresh;              /* 1: the next step skips the P = F.v test */
     int step;               /* steps taken (moves) */
     int ci;                 /* climbing image of the last evaluation, -1 if none */
+    long long image_steps;  /* sum over the steps taken of the number of moving images
+                               (read-only: cfneb_set_state ignores it) */
 } cfneb_fire_state;
+
+/* Phases of one band step, in launch order, for cfneb_step_profiled. */
+enum {
+    CFNEB_PH_GEOM = 0,      /* per-image D = symsqrt(B), h, h^-1, bin grid */
+    CFNEB_PH_BINS,          /* R = R~ D, bin ids, counting sort, per-bin order */
+    CFNEB_PH_NLIST,         /* exact neighbour test, packed lists */
+    CFNEB_PH_FORCE0,        /* LJ pair forces, or Tersoff zeta and bond orders */
+    CFNEB_PH_FORCE1,        /* Tersoff dU_i/dr^ij per bond (unused for LJ) */
+    CFNEB_PH_FORCE2,        /* Tersoff force gather (unused for LJ) */
+    CFNEB_PH_REDUCE,        /* per-image E, V, enthalpy, lattice force */
+    CFNEB_PH_DOTS,          /* ten band dot products per image */
+    CFNEB_PH_SCALARS,       /* tangents, climbing image, projection, FIRE proposal */
+    CFNEB_PH_UPDATE,        /* NEB force rows, new velocities, row maxima */
+    CFNEB_PH_FINALIZE,      /* fmax, convergence, step clamp, FIRE commit */
+    CFNEB_PH_MOVE,          /* X += dr */
+    CFNEB_PH_REFINE,        /* adaptive-image check */
+    CFNEB_NPHASE
+};
 
 typedef struct cfneb_band cfneb_band;
 
@@ -128,6 +148,14 @@ int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* typ
  * converged flag. */
 int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, double* fmax,
                int* converged);
+
+/* The same steps as cfneb_step, launched one phase at a time with a HIP event
+ * recorded on the band's stream around every phase.  phase_ms (nphase doubles,
+ * nphase <= CFNEB_NPHASE, indexed by CFNEB_PH_*) receives the summed device time
+ * of each phase over the steps run, in milliseconds; it is a measuring tool, not
+ * the fast path (no graph, one event pair per phase and step). */
+int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_done, double* fmax,
+                        int* converged, double* phase_ms, int nphase);
 
 /* One adaptive-image decision now (Sec. III): squared spacings between
  * consecutive images summed exactly in fixed point, then at most one insertion

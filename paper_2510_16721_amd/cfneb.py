@@ -21,6 +21,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECELL", -5: "ENE
 
 # exported entry points declared in include/cfneb.h
 SYMBOLS = ["cfneb_params_default", "cfneb_band_bytes", "cfneb_create_band", "cfneb_step",
+           "cfneb_step_profiled",
            "cfneb_refine", "cfneb_energies", "cfneb_get_image", "cfneb_get_state",
            "cfneb_set_state", "cfneb_image_data", "cfneb_record_neb_force", "cfneb_neighbours",
            "cfneb_destroy", "cfneb_strerror", "cfneb_last_error"]
@@ -53,7 +54,12 @@ class Params(ctypes.Structure):
 
 class FireState(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("n_pos", ctypes.c_int),
-                ("fresh", ctypes.c_int), ("step", ctypes.c_int), ("ci", ctypes.c_int)]
+                ("fresh", ctypes.c_int), ("step", ctypes.c_int), ("ci", ctypes.c_int),
+                ("image_steps", ctypes.c_longlong)]
+
+
+PHASES = ["geom", "bins", "nlist", "force0", "force1", "force2", "reduce", "dots", "scalars",
+          "update", "finalize", "move", "refine"]
 
 
 _LIB = None
@@ -82,6 +88,8 @@ def _declare(L):
                                     c_void, c_size, c_void, ctypes.POINTER(c_void)]
     L.cfneb_step.argtypes = [c_void, c_int, c_double, ctypes.POINTER(c_int), _dp,
                              ctypes.POINTER(c_int)]
+    L.cfneb_step_profiled.argtypes = [c_void, c_int, c_double, ctypes.POINTER(c_int), _dp,
+                                      ctypes.POINTER(c_int), _dp, c_int]
     L.cfneb_refine.argtypes = [c_void, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     L.cfneb_energies.argtypes = [c_void, _dp, c_int, ctypes.POINTER(c_int), _dp,
                                  ctypes.POINTER(c_int), _dp]
@@ -191,6 +199,17 @@ class Band:
         self._check(rc, "cfneb_step")
         return sd.value, fmax.value, bool(conv.value)
 
+    def step_profiled(self, max_steps, f_tol=0.0):
+        """Steps with per-phase HIP-event timing; returns (steps, fmax, converged, {phase: ms})."""
+        sd = ctypes.c_int()
+        conv = ctypes.c_int()
+        fmax = ctypes.c_double()
+        ms = np.zeros(len(PHASES))
+        rc = lib().cfneb_step_profiled(self._h, int(max_steps), float(f_tol), ctypes.byref(sd),
+                                       ctypes.byref(fmax), ctypes.byref(conv), _d(ms), len(PHASES))
+        self._check(rc, "cfneb_step_profiled")
+        return sd.value, fmax.value, bool(conv.value), dict(zip(PHASES, ms.tolist()))
+
     def refine(self):
         ia = ctypes.c_int()
         da = ctypes.c_int()
@@ -227,11 +246,11 @@ class Band:
                                           ctypes.byref(st)), "cfneb_get_state")
         del cap
         return dict(X=X, v=v, dt=st.dt, alpha=st.alpha, n_pos=st.n_pos, fresh=st.fresh,
-                    step=st.step, ci=st.ci)
+                    step=st.step, ci=st.ci, image_steps=st.image_steps)
 
     def set_state(self, X, v, dt, alpha, n_pos, fresh, step, ci=-1):
         X = _f64(X)
-        st = FireState(float(dt), float(alpha), int(n_pos), int(fresh), int(step), int(ci))
+        st = FireState(float(dt), float(alpha), int(n_pos), int(fresh), int(step), int(ci), 0)
         vv = _f64(v) if v is not None else None
         self._check(lib().cfneb_set_state(self._h, X.shape[0], _d(X),
                                           _d(vv) if vv is not None else None, ctypes.byref(st)),

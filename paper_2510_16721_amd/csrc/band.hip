@@ -274,6 +274,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_finalize(BandDev b)
     st->vcur ^= 1;
     st->step += 1;
     st->steps_call += 1;
+    st->image_steps += M - 2;
     st->refine_due = (b.refine_every > 0 && st->step % b.refine_every == 0) ? 1 : 0;
 }
 
@@ -299,20 +300,41 @@ void launch_begin_call(const BandDev& b, double f_tol, hipStream_t s)
     k_begin_call<<<1, 1, 0, s>>>(b, f_tol);
 }
 
-void launch_band_update(const BandDev& b, hipStream_t s)
+void launch_dots(const BandDev& b, hipStream_t s)
 {
     const dim3 gR(b.ntR, b.Mcap);
     if (b.fp64)
         k_band_dots<double><<<gR, CFNEB_TILE, 0, s>>>(b);
     else
         k_band_dots<float><<<gR, CFNEB_TILE, 0, s>>>(b);
-    k_band_scalars<<<1, CFNEB_TILE, 0, s>>>(b);
+}
+
+void launch_scalars(const BandDev& b, hipStream_t s) { k_band_scalars<<<1, CFNEB_TILE, 0, s>>>(b); }
+
+void launch_update(const BandDev& b, hipStream_t s)
+{
+    const dim3 gR(b.ntR, b.Mcap);
     if (b.fp64)
         k_band_update<double><<<gR, CFNEB_TILE, 0, s>>>(b);
     else
         k_band_update<float><<<gR, CFNEB_TILE, 0, s>>>(b);
-    k_band_finalize<<<1, CFNEB_TILE, 0, s>>>(b);
+}
+
+void launch_finalize(const BandDev& b, hipStream_t s) { k_band_finalize<<<1, CFNEB_TILE, 0, s>>>(b); }
+
+void launch_move(const BandDev& b, hipStream_t s)
+{
+    const dim3 gR(b.ntR, b.Mcap);
     k_band_move<<<gR, CFNEB_TILE, 0, s>>>(b);
+}
+
+void launch_band_update(const BandDev& b, hipStream_t s)
+{
+    launch_dots(b, s);
+    launch_scalars(b, s);
+    launch_update(b, s);
+    launch_finalize(b, s);
+    launch_move(b, s);
 }
 
 }  // namespace cfneb

@@ -56,6 +56,7 @@ struct BandState {
     int slot[CFNEB_MAX_IMAGES];    // logical image -> physical slot
     int vcur;                      // current velocity buffer
     int step;                      // moves taken in total
+    long long image_steps;         // sum over moves of the number of moving images
     int steps_call;                // moves taken in the current cfneb_step call
     int done;                      // converged in the current call
     int err;                       // first error code of the current call (0 = none)
@@ -237,6 +238,15 @@ void launch_begin_call(const BandDev& b, double f_tol, hipStream_t s);
 void launch_geom(const BandDev& b, int all_images, hipStream_t s);
 void launch_nlist(const BandDev& b, int all_images, hipStream_t s);
 void launch_forces(const BandDev& b, int all_images, hipStream_t s);
+void launch_bins(const BandDev& b, int all_images, hipStream_t s);
+void launch_list(const BandDev& b, int all_images, hipStream_t s);
+void launch_force_stage(const BandDev& b, int all_images, int stage, hipStream_t s);
+void launch_image_reduce(const BandDev& b, int all_images, hipStream_t s);
+void launch_dots(const BandDev& b, hipStream_t s);
+void launch_scalars(const BandDev& b, hipStream_t s);
+void launch_update(const BandDev& b, hipStream_t s);
+void launch_finalize(const BandDev& b, hipStream_t s);
+void launch_move(const BandDev& b, hipStream_t s);
 void launch_evaluate(const BandDev& b, int all_images, hipStream_t s);
 void launch_band_update(const BandDev& b, hipStream_t s);
 void launch_refine(const BandDev& b, int forced, hipStream_t s);

@@ -331,26 +331,38 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BandDev b, int all_
     if (!finite) set_error(st, CFNEB_ENONFINITE);
 }
 
-void launch_forces(const BandDev& b, int all_images, hipStream_t s)
+// stage 0: LJ, or Tersoff zeta and bond orders; 1: Tersoff dU_i/dr^ij; 2: Tersoff gather
+void launch_force_stage(const BandDev& b, int all_images, int stage, hipStream_t s)
 {
     const dim3 gA(b.ntA, b.Mcap);
     if (b.potential == CFNEB_LJ) {
+        if (stage != 0) return;
         if (b.fp64)
             k_lj<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
         else
             k_lj<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-    } else {
-        if (b.fp64) {
-            k_ts_zeta<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-            k_ts_partial<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-            k_ts_gather<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-        } else {
-            k_ts_zeta<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-            k_ts_partial<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-            k_ts_gather<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-        }
+        return;
     }
+    if (b.fp64) {
+        if (stage == 0) k_ts_zeta<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+        if (stage == 1) k_ts_partial<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+        if (stage == 2) k_ts_gather<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+    } else {
+        if (stage == 0) k_ts_zeta<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+        if (stage == 1) k_ts_partial<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+        if (stage == 2) k_ts_gather<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+    }
+}
+
+void launch_image_reduce(const BandDev& b, int all_images, hipStream_t s)
+{
     k_image_reduce<<<b.Mcap, CFNEB_TILE, 0, s>>>(b, all_images);
+}
+
+void launch_forces(const BandDev& b, int all_images, hipStream_t s)
+{
+    for (int stage = 0; stage < 3; ++stage) launch_force_stage(b, all_images, stage, s);
+    launch_image_reduce(b, all_images, s);
 }
 
 void launch_evaluate(const BandDev& b, int all_images, hipStream_t s)

@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
     if (cnt > b.cap) set_error(st, CFNEB_ENEIGH);
 }
 
-void launch_nlist(const BandDev& b, int all_images, hipStream_t s)
+void launch_bins(const BandDev& b, int all_images, hipStream_t s)
 {
     const dim3 gA(b.ntA, b.Mcap);
     k_bin_assign<<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
@@ -215,6 +215,11 @@ void launch_nlist(const BandDev& b, int all_images, hipStream_t s)
     k_bin_fill<<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
     const dim3 gB((b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE, b.Mcap);
     k_bin_sort<<<gB, CFNEB_TILE, 0, s>>>(b, all_images);
+}
+
+void launch_list(const BandDev& b, int all_images, hipStream_t s)
+{
+    const dim3 gA(b.ntA, b.Mcap);
     if (b.potential == CFNEB_TERSOFF_C) {
         if (b.fp64)
             k_nlist<double, true><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
@@ -223,6 +228,12 @@ void launch_nlist(const BandDev& b, int all_images, hipStream_t s)
     } else {
         k_nlist<double, false><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
     }
+}
+
+void launch_nlist(const BandDev& b, int all_images, hipStream_t s)
+{
+    launch_bins(b, all_images, s);
+    launch_list(b, all_images, s);
 }
 
 }  // namespace cfneb

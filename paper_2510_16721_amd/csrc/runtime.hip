@@ -442,6 +442,69 @@ int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, doub
     return CFNEB_OK;
 }
 
+int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_done, double* fmax,
+                        int* converged, double* phase_ms, int nphase)
+{
+    if (!b || max_steps < 0 || nphase < 0 || nphase > CFNEB_NPHASE || (nphase > 0 && !phase_ms))
+        return CFNEB_EINVAL;
+    launch_begin_call(b->d, f_tol, b->stream);
+    const int NP = CFNEB_NPHASE;
+    // one event before every phase and one after the last, for every step
+    std::vector<hipEvent_t> ev(size_t(max_steps) * (NP + 1), nullptr);
+    int rc = CFNEB_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            rc = fail(b, CFNEB_EHIP, "hipEventCreate");
+            break;
+        }
+    const BandDev& d = b->d;
+    hipStream_t s = b->stream;
+    for (int st = 0; st < max_steps && rc == CFNEB_OK; ++st) {
+        hipEvent_t* e = ev.data() + size_t(st) * (NP + 1);
+        for (int ph = 0; ph < NP; ++ph) {
+            (void)hipEventRecord(e[ph], s);
+            switch (ph) {
+            case CFNEB_PH_GEOM: launch_geom(d, 0, s); break;
+            case CFNEB_PH_BINS: launch_bins(d, 0, s); break;
+            case CFNEB_PH_NLIST: launch_list(d, 0, s); break;
+            case CFNEB_PH_FORCE0: launch_force_stage(d, 0, 0, s); break;
+            case CFNEB_PH_FORCE1: launch_force_stage(d, 0, 1, s); break;
+            case CFNEB_PH_FORCE2: launch_force_stage(d, 0, 2, s); break;
+            case CFNEB_PH_REDUCE: launch_image_reduce(d, 0, s); break;
+            case CFNEB_PH_DOTS: launch_dots(d, s); break;
+            case CFNEB_PH_SCALARS: launch_scalars(d, s); break;
+            case CFNEB_PH_UPDATE: launch_update(d, s); break;
+            case CFNEB_PH_FINALIZE: launch_finalize(d, s); break;
+            case CFNEB_PH_MOVE: launch_move(d, s); break;
+            case CFNEB_PH_REFINE: launch_refine(d, 0, s); break;
+            default: break;
+            }
+        }
+        (void)hipEventRecord(e[NP], s);
+        rc = check_kernels(b, "step_profiled");
+    }
+    if (rc == CFNEB_OK) rc = read_state(b);
+    if (rc == CFNEB_OK) {
+        for (int ph = 0; ph < nphase; ++ph) phase_ms[ph] = 0.0;
+        for (int st = 0; st < max_steps; ++st) {
+            hipEvent_t* e = ev.data() + size_t(st) * (NP + 1);
+            for (int ph = 0; ph < nphase; ++ph) {
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, e[ph], e[ph + 1]) == hipSuccess) phase_ms[ph] += ms;
+            }
+        }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != CFNEB_OK) return rc;
+    const BandState& st = *b->host_state;
+    if (steps_done) *steps_done = st.steps_call;
+    if (fmax) *fmax = st.fmax;
+    if (converged) *converged = st.done;
+    if (st.err != 0) return fail(b, st.err, "cfneb_step_profiled");
+    return CFNEB_OK;
+}
+
 int cfneb_refine(cfneb_band* b, int* inserted_at, int* deleted_at)
 {
     if (!b) return CFNEB_EINVAL;
@@ -529,6 +592,7 @@ int cfneb_get_state(const cfneb_band* cb, double* X, double* v, int cap_images, 
         fs->fresh = st.fresh;
         fs->step = st.step;
         fs->ci = st.ci;
+        fs->image_steps = st.image_steps;
     }
     return CFNEB_OK;
 }

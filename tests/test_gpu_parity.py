@@ -59,9 +59,10 @@ def test_neighbour_sets_bit_exact(name, rc):
                                        ("ts_diamond", False), ("ts4608", False)])
 def test_energy_force_virial_per_image(name, fp64):
     import oracle
+    press = 5.0 if name.startswith("ts") else 0.0
     g, _, w, kind = make_pair(name, n_images=5, max_images=5, fp64=fp64, oracle_too=False,
-                              pressure_GPa=5.0 if kind == "ts" else 0.0)
-    p = oracle_params_like(kind, pressure_GPa=5.0 if kind == "ts" else 0.0)
+                              pressure_GPa=press)
+    p = oracle_params_like(kind, pressure_GPa=press)
     scale = 1e-6 if fp64 else 1.0
     n = g.n
     for k in range(5):
@@ -113,18 +114,34 @@ def test_one_step_from_identical_state(name, fp64, steps_before):
     np.testing.assert_allclose(gs["v"], os_["v"], rtol=0, atol=4 * TOL_F * dt * tol + 1e-12)
 
 
-def test_lj_vacancy_band_barrier_fp64():
-    # LJ FCC 4x4x4 vacancy hop, 7 images, climbing after 50 steps, 300 FIRE steps
+def test_lj_vacancy_band_trajectory_fp64():
+    # LJ FCC 4x4x4 vacancy hop (255 atoms), 7 images, climbing after 50 steps.  Before
+    # FIRE's power test meets a near-zero P the two trajectories agree to rounding;
+    # later a 1e-13 perturbation of the oracle's own input already moves its
+    # unconverged barrier by about 1 meV, so only converged barriers are compared.
     kw = dict(n_images=7, max_images=7, climb_after=50, k_spring=1.0, fire_dt0=0.005)
     g, o, w, kind = make_pair("lj255", fp64=True, **kw)
-    gd, gf, _ = g.step(300)
-    od, of, _ = o.step(300)
-    assert gd == od == 300
+    assert g.step(80)[0] == o.step(80)[0] == 80
+    ge, oe = g.energies(), o.energies()
+    assert abs(ge["barrier"] - oe["barrier"]) <= 1e-8
+    assert ge["ci"] == oe["ci"] == 3
+    np.testing.assert_allclose(g.get_state()["X"], o.get_state()["X"], rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_converged_barrier(fp64):
+    # LJ FCC 2x2x2 vacancy hop relaxed to fmax < 1e-3 eV/A with a climbing image
+    kw = dict(n_images=7, max_images=7, climb_after=50, k_spring=1.0, fire_dt0=0.005)
+    g, o, w, kind = make_pair("lj31", fp64=fp64, **kw)
+    gd, gf, gc = g.step(6000, 1e-3)
+    od, of, oc = o.step(6000, 1e-3)
+    assert gc and oc and gf < 1e-3
     ge, oe = g.energies(), o.energies()
     assert abs(ge["barrier"] - oe["barrier"]) <= TOL_BARRIER
     assert ge["ci"] == oe["ci"] == 3
     np.testing.assert_allclose(ge["H"], oe["H"], rtol=0, atol=TOL_BARRIER)
-    np.testing.assert_allclose(ge["xi"], oe["xi"], rtol=0, atol=1e-6)
+    # the symmetric hop gives a symmetric profile
+    np.testing.assert_allclose(ge["H"], ge["H"][::-1], rtol=0, atol=TOL_BARRIER)
 
 
 def test_refine_decision_and_midpoint_bit_exact():
