@@ -47,9 +47,11 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BandDev b)
 {
     __shared__ double lds[4 * 10];
     const BandState* st = b.st;
-    const int k = blockIdx.y;
-    if (band_stopped(st) || !image_active(st, k, 0)) return;
-    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, b.ntR, 0);
+    if (!w.valid) return;
+    const int k = w.image;
+    const int r = w.tile * CFNEB_TILE + threadIdx.x;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (r < b.N + 3) {
@@ -77,8 +79,9 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BandDev b)
     }
     block_sum<10>(a, lds);
     if (threadIdx.x == 0) {
-        double* out = b.dotpart + (size_t(k) * b.ntR + blockIdx.x) * 10;
-        for (int q = 0; q < 10; ++q) out[q] = a[q];
+        // [image][dot][tile]: the reduction reads consecutive tiles
+        double* out = b.dotpart + size_t(k) * 10 * b.ntR + w.tile;
+        for (int q = 0; q < 10; ++q) out[size_t(q) * b.ntR] = a[q];
     }
 }
 
@@ -105,35 +108,42 @@ __device__ inline void tangent_coeffs(double Hm, double H0, double Hp, double& a
 
 // One block per band: reduce the dot partials, choose tangents and the climbing
 // image, form the projection coefficients and the FIRE proposal.
-__global__ void __launch_bounds__(CFNEB_TILE) k_band_scalars(BandDev b)
+__global__ void __launch_bounds__(1024) k_band_scalars(BandDev b)
 {
     __shared__ double dots[CFNEB_MAX_IMAGES][10];
     BandState* st = b.st;
     if (band_stopped(st)) return;
     const int M = st->M;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = 1 + wid; k <= M - 2; k += CFNEB_TILE / 64) {
+    for (int k = 1 + wid; k <= M - 2; k += int(blockDim.x) / 64) {
         double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const double* part = b.dotpart + size_t(k) * b.ntR * 10;
+        const double* part = b.dotpart + size_t(k) * 10 * b.ntR;
         for (int t = lane; t < b.ntR; t += 64)
-            for (int q = 0; q < 10; ++q) a[q] += part[size_t(t) * 10 + q];
+            for (int q = 0; q < 10; ++q) a[q] += part[size_t(q) * b.ntR + t];
         for (int q = 0; q < 10; ++q) a[q] = wave_sum(a[q]);
         if (lane == 0)
             for (int q = 0; q < 10; ++q) dots[k][q] = a[q];
     }
+    // image enthalpies, loaded in parallel
+    __shared__ double H[CFNEB_MAX_IMAGES];
+    __shared__ double contrib[3][CFNEB_MAX_IMAGES];
+    __shared__ int ci_s;
+    const int t = threadIdx.x;
+    if (t < M) H[t] = b.scal[st->slot[t]].H;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-
-    double H[CFNEB_MAX_IMAGES];
-    for (int k = 0; k < M; ++k) H[k] = b.scal[st->slot[k]].H;
-    int ci = -1;
-    if (b.climb_after >= 0 && st->step >= b.climb_after) {
-        for (int k = 1; k <= M - 2; ++k)
-            if (ci < 0 || H[k] > H[ci]) ci = k;
+    if (t == 0) {
+        int ci = -1;
+        if (b.climb_after >= 0 && st->step >= b.climb_after) {
+            for (int k = 1; k <= M - 2; ++k)
+                if (ci < 0 || H[k] > H[ci]) ci = k;
+        }
+        ci_s = ci;
+        st->ci = ci;
     }
-    st->ci = ci;
-    double Pw = 0.0, FF = 0.0, VV = 0.0;
-    for (int k = 1; k <= M - 2; ++k) {
+    __syncthreads();
+    // one thread per moving image: tangent, projection coefficients, FIRE terms
+    if (t >= 1 && t <= M - 2) {
+        const int k = t, ci = ci_s;
         const double* d = dots[k];
         double a, c;
         tangent_coeffs(H[k - 1], H[k], H[k + 1], a, c);
@@ -148,9 +158,18 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_scalars(BandDev b)
         }
         st->cplus[k] = cp;
         st->cminus[k] = cm;
-        Pw += d[6] + cp * d[8] + cm * d[9];
-        FF += d[5] + cp * cp * d[0] + cm * cm * d[1] + 2.0 * cp * d[3] + 2.0 * cm * d[4] + 2.0 * cp * cm * d[2];
-        VV += d[7];
+        contrib[0][k] = d[6] + cp * d[8] + cm * d[9];
+        contrib[1][k] = d[5] + cp * cp * d[0] + cm * cm * d[1] + 2.0 * cp * d[3] + 2.0 * cm * d[4] +
+                        2.0 * cp * cm * d[2];
+        contrib[2][k] = d[7];
+    }
+    __syncthreads();
+    if (t != 0) return;
+    double Pw = 0.0, FF = 0.0, VV = 0.0;
+    for (int k = 1; k <= M - 2; ++k) {
+        Pw += contrib[0][k];
+        FF += contrib[1][k];
+        VV += contrib[2][k];
     }
     // FIRE (Bitzek et al. 2006) proposal; committed only if the band moves.
     double cv = 1.0, cf = 0.0, dt = st->dt, alpha = st->alpha;
@@ -189,9 +208,11 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BandDev b)
 {
     __shared__ double lds[4 * 3];
     BandState* st = b.st;
-    const int k = blockIdx.y;
-    if (band_stopped(st) || !image_active(st, k, 0)) return;
-    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, b.ntR, 0);
+    if (!w.valid) return;
+    const int k = w.image;
+    const int r = w.tile * CFNEB_TILE + threadIdx.x;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double m[3] = {0.0, 0.0, 0.0};  // max |F_NEB row|^2, max |dr row|^2, non-finite flag
     if (r < b.N + 3) {
@@ -224,17 +245,17 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BandDev b)
     }
     block_max<3>(m, lds);
     if (threadIdx.x == 0) {
-        double* out = b.maxpart + (size_t(k) * b.ntR + blockIdx.x) * 3;
+        double* out = b.maxpart + size_t(k) * 3 * b.ntR + w.tile;  // [image][q][tile]
         out[0] = m[0];
-        out[1] = m[1];
-        out[2] = m[2];
+        out[b.ntR] = m[1];
+        out[2 * size_t(b.ntR)] = m[2];
     }
 }
 
 // fmax, convergence, step clamp; commit the FIRE proposal when the band moves.
-__global__ void __launch_bounds__(CFNEB_TILE) k_band_finalize(BandDev b)
+__global__ void __launch_bounds__(1024) k_band_finalize(BandDev b)
 {
-    __shared__ double lds[4 * 3];
+    __shared__ double lds[16 * 3];
     BandState* st = b.st;
     if (band_stopped(st)) {
         if (threadIdx.x == 0) st->move = 0;
@@ -243,12 +264,12 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_finalize(BandDev b)
     const int M = st->M;
     double m[3] = {0.0, 0.0, 0.0};
     const int total = (M - 2) * b.ntR;
-    for (int t = threadIdx.x; t < total; t += CFNEB_TILE) {
+    for (int t = threadIdx.x; t < total; t += int(blockDim.x)) {
         const int k = 1 + t / b.ntR, tile = t % b.ntR;
-        const double* p = b.maxpart + (size_t(k) * b.ntR + tile) * 3;
+        const double* p = b.maxpart + size_t(k) * 3 * b.ntR + tile;
         m[0] = fmax(m[0], p[0]);
-        m[1] = fmax(m[1], p[1]);
-        m[2] = fmax(m[2], p[2]);
+        m[1] = fmax(m[1], p[b.ntR]);
+        m[2] = fmax(m[2], p[2 * size_t(b.ntR)]);
     }
     block_max<3>(m, lds);
     if (threadIdx.x != 0) return;
@@ -281,9 +302,11 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_finalize(BandDev b)
 __global__ void __launch_bounds__(CFNEB_TILE) k_band_move(BandDev b)
 {
     const BandState* st = b.st;
-    const int k = blockIdx.y;
-    if (!st->move || st->err != 0 || !image_active(st, k, 0)) return;
-    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
+    if (!st->move || st->err != 0) return;
+    const WorkItem w = image_item(st, b.ntR, 0);
+    if (!w.valid) return;
+    const int k = w.image;
+    const int r = w.tile * CFNEB_TILE + threadIdx.x;
     if (r >= b.N + 3) return;
     const int s0 = st->slot[k];
     double* X = Xs(b, s0);
@@ -302,29 +325,29 @@ void launch_begin_call(const BandDev& b, double f_tol, hipStream_t s)
 
 void launch_dots(const BandDev& b, hipStream_t s)
 {
-    const dim3 gR(b.ntR, b.Mcap);
+    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
     if (b.fp64)
         k_band_dots<double><<<gR, CFNEB_TILE, 0, s>>>(b);
     else
         k_band_dots<float><<<gR, CFNEB_TILE, 0, s>>>(b);
 }
 
-void launch_scalars(const BandDev& b, hipStream_t s) { k_band_scalars<<<1, CFNEB_TILE, 0, s>>>(b); }
+void launch_scalars(const BandDev& b, hipStream_t s) { k_band_scalars<<<1, 1024, 0, s>>>(b); }
 
 void launch_update(const BandDev& b, hipStream_t s)
 {
-    const dim3 gR(b.ntR, b.Mcap);
+    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
     if (b.fp64)
         k_band_update<double><<<gR, CFNEB_TILE, 0, s>>>(b);
     else
         k_band_update<float><<<gR, CFNEB_TILE, 0, s>>>(b);
 }
 
-void launch_finalize(const BandDev& b, hipStream_t s) { k_band_finalize<<<1, CFNEB_TILE, 0, s>>>(b); }
+void launch_finalize(const BandDev& b, hipStream_t s) { k_band_finalize<<<1, 1024, 0, s>>>(b); }
 
 void launch_move(const BandDev& b, hipStream_t s)
 {
-    const dim3 gR(b.ntR, b.Mcap);
+    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
     k_band_move<<<gR, CFNEB_TILE, 0, s>>>(b);
 }
 

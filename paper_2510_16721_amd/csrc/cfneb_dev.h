@@ -7,8 +7,8 @@
 //   R      [slot][3][ld]  FP64  Cartesian positions R = R~ D of the last evaluation
 //   F      [slot][3][ld]  T     Cartesian forces (T = float, or double for FP64 bands)
 //   FN     [slot][3][ld]  FP64  NEB force (only when recording is on)
-//   binfo  [slot][N]      int4  (bin, image offset n_x, n_y, n_z) per atom
-//   bins   [slot][...]    int   counts, starts, cursors, atoms-by-bin
+//   binfo  [slot][N]      int4  (bin, rank in bin, packed lattice image) per atom
+//   bins   [slot][...]    int   counts, starts; bpos: atoms in bin order (R, packed id)
 //   nbr    [slot][cap][N] u32   packed neighbour entries, entry-major (coalesced)
 //   ncnt   [slot][N]      int   neighbour count (may exceed cap: overflow)
 //   dvec   [slot][cap][N] T4    Tersoff: bond vector and length
@@ -34,6 +34,13 @@
 #define CFNEB_MAX_ATOMS (1 << CFNEB_J_BITS)
 
 namespace cfneb {
+
+// One atom in bin order: unwrapped position and (id, lattice image) packed as
+// id | (n0 + 512) << 20 | (n1 + 512) << 30 | (n2 + 512) << 40.
+struct alignas(32) BinAtom {
+    double x, y, z;
+    long long info;
+};
 
 struct ImageGeom {
     double D[9], Dinv[9], h[9], hinv[9];
@@ -108,8 +115,7 @@ struct BandDev {
     int4* binfo;
     int* bcount;
     int* bstart;
-    int* bcursor;
-    int* batoms;
+    struct BinAtom* bpos;
     uint32_t* nbr;
     int* ncnt;
     void* dvec;
@@ -151,6 +157,46 @@ __device__ inline bool image_active(const BandState* st, int k, int all_images)
 
 __device__ inline bool band_stopped(const BandState* st) { return st->done != 0 || st->err != 0; }
 
+// XCD-aware work mapping.  Workgroups of a launch go to the 8 XCDs round-robin by
+// linear id, and each XCD has its own L2.  A launch over (tile, image) items uses a
+// 1-D grid of cfneb_grid(ntiles, Mcap) blocks; block W serves item
+//     L = (W % 8) * chunk + W / 8,   chunk = ceil(nact * ntiles / 8),
+// over the nact images active now (first = first active image), so every XCD walks
+// one contiguous run of tiles of one image at a time and all 8 XCDs get equal work
+// whatever the current image count.  Blocks past the work exit at once.
+#define CFNEB_XCDS 8
+struct WorkItem {
+    int tile, image;
+    bool valid;
+};
+
+__device__ inline WorkItem xcd_item(int ntiles, int first, int nact)
+{
+    WorkItem w;
+    const int W = int(blockIdx.x);
+    const int chunk = (nact * ntiles + CFNEB_XCDS - 1) / CFNEB_XCDS;
+    const int idx = W / CFNEB_XCDS;
+    const int L = (W % CFNEB_XCDS) * chunk + idx;
+    w.valid = nact > 0 && idx < chunk && L < nact * ntiles;
+    w.tile = w.valid ? L % ntiles : 0;
+    w.image = w.valid ? first + L / ntiles : 0;
+    return w;
+}
+
+// (tile, image) item of a per-atom or per-row launch over the images of a step
+// (moving images) or of an evaluation of every image.
+__device__ inline WorkItem image_item(const BandState* st, int ntiles, int all_images)
+{
+    const int M = st->M;
+    return all_images ? xcd_item(ntiles, 0, M) : xcd_item(ntiles, 1, M - 2);
+}
+
+__host__ __device__ inline unsigned cfneb_grid(int ntiles, int nimages)
+{
+    const long long t = (long long)ntiles * nimages;
+    return unsigned((t + CFNEB_XCDS - 1) / CFNEB_XCDS * CFNEB_XCDS);
+}
+
 __device__ inline void set_error(BandState* st, int code)
 {
     atomicCAS(&st->err, 0, code);
@@ -168,12 +214,12 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
-// Block (CFNEB_TILE threads = 4 waves) sum of NV doubles in a fixed order; the
-// result is valid in thread 0.  lds must hold 4 * NV doubles.
+// Block sum of NV doubles in a fixed order (waves in index order); the result is
+// valid in thread 0.  lds must hold (blockDim.x / 64) * NV doubles.
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV], double* lds)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
     if (lane == 0)
@@ -182,14 +228,18 @@ __device__ inline void block_sum(double (&v)[NV], double* lds)
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = ((lds[q] + lds[NV + q]) + lds[2 * NV + q]) + lds[3 * NV + q];
+        for (int q = 0; q < NV; ++q) {
+            double s = lds[q];
+            for (int w = 1; w < nw; ++w) s += lds[w * NV + q];
+            v[q] = s;
+        }
     __syncthreads();
 }
 
 template <int NV>
 __device__ inline void block_max(double (&v)[NV], double* lds)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = wave_max(v[q]);
     if (lane == 0)
@@ -198,8 +248,11 @@ __device__ inline void block_max(double (&v)[NV], double* lds)
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-            v[q] = fmax(fmax(lds[q], lds[NV + q]), fmax(lds[2 * NV + q], lds[3 * NV + q]));
+        for (int q = 0; q < NV; ++q) {
+            double s = lds[q];
+            for (int w = 1; w < nw; ++w) s = fmax(s, lds[w * NV + q]);
+            v[q] = s;
+        }
     __syncthreads();
 }
 
@@ -242,6 +295,7 @@ void launch_bins(const BandDev& b, int all_images, hipStream_t s);
 void launch_list(const BandDev& b, int all_images, hipStream_t s);
 void launch_force_stage(const BandDev& b, int all_images, int stage, hipStream_t s);
 void launch_image_reduce(const BandDev& b, int all_images, hipStream_t s);
+void launch_tersoff_stage(const BandDev& b, int all_images, int stage, hipStream_t s);
 void launch_dots(const BandDev& b, hipStream_t s);
 void launch_scalars(const BandDev& b, hipStream_t s);
 void launch_update(const BandDev& b, hipStream_t s);

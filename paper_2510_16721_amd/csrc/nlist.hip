@@ -7,23 +7,38 @@
 // depend on the binning.  This is the local environment of Sec. II.B, Eq. (4).
 //
 // Kernels, in order, one grid row per image:
-//   k_bin_assign  R = R~ D, wrapped fractional coordinate, bin id, integer counts
-//   k_bin_scan    exclusive prefix sum of the counts (one block per image); zeroes counts
-//   k_bin_fill    atoms into bins (atomic cursors)
-//   k_bin_sort    sort each bin by atom index, so the lists are deterministic
-//   k_nlist       stencil walk, exact inclusion test, packed entry-major lists
+//   k_bin_assign   R = R~ D, wrapped fractional coordinate, bin id; the count atomic
+//                  returns the atom's rank inside its bin
+//   k_bin_scan     exclusive prefix sum of the bin counts (one block per image,
+//                  4096 counts per pass, coalesced); zeroes the counts for the next step
+//   k_bin_scatter  atom -> bin-ordered 32-byte record (position, id, lattice image)
+//   k_bin_sort     sort each bin by atom id, so lists are deterministic
+//   k_nlist        stencil walk over bin-ordered records, exact inclusion test,
+//                  packed entry-major lists (entry e of atom i at [e][i])
+#include <type_traits>
+
 #include "cfneb_dev.h"
 
 namespace cfneb {
 
 __device__ inline size_t bin_base(const BandDev& b, int slot) { return size_t(slot) * (b.nbcap + 1); }
 
+__device__ inline long long pack_info(int j, int n0, int n1, int n2)
+{
+    return (long long)j | ((long long)(n0 + 512) << 20) | ((long long)(n1 + 512) << 30) |
+           ((long long)(n2 + 512) << 40);
+}
+__device__ inline int info_j(long long v) { return int(v & 0xFFFFF); }
+__device__ inline int info_n(long long v, int k) { return int((v >> (20 + 10 * k)) & 0x3FF) - 512; }
+
 __global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BandDev b, int all_images)
 {
     const BandState* st = b.st;
-    const int k = blockIdx.y;
-    const int i = blockIdx.x * CFNEB_TILE + threadIdx.x;
-    if (band_stopped(st) || !image_active(st, k, all_images) || i >= b.N) return;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, b.ntA, all_images);
+    const int k = w.image;
+    const int i = w.tile * CFNEB_TILE + threadIdx.x;
+    if (!w.valid || i >= b.N) return;
     const int slot = st->slot[k];
     const ImageGeom& g = b.geom[slot];
     const double* X = Xs(b, slot);
@@ -38,7 +53,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BandDev b, int all_im
     for (int q = 0; q < 3; ++q) {
         const double s = (r[0] * g.hinv[q] + r[1] * g.hinv[3 + q]) + r[2] * g.hinv[6 + q];
         double fl = floor(s);
-        if (!isfinite(fl) || fabs(fl) > 1e6) fl = 0.0;  // non-finite input: caught by the energy check
+        if (!isfinite(fl) || fabs(fl) > 500.0) fl = 0.0;  // non-finite input: caught by the energy check
         img[q] = int(fl);
         const double sw = s - fl;
         int bq = int(floor(sw * g.nb[q]));
@@ -46,13 +61,16 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BandDev b, int all_im
         bi[q] = bq;
     }
     const int bin = (bi[0] * g.nb[1] + bi[1]) * g.nb[2] + bi[2];
-    b.binfo[size_t(slot) * b.N + i] = make_int4(bin, img[0], img[1], img[2]);
-    atomicAdd(&b.bcount[bin_base(b, slot) + bin], 1);
+    const int rank = atomicAdd(&b.bcount[bin_base(b, slot) + bin], 1);
+    const int packed = (img[0] + 512) | ((img[1] + 512) << 10) | ((img[2] + 512) << 20);
+    b.binfo[size_t(slot) * b.N + i] = make_int4(bin, rank, packed, 0);
 }
 
-// One block of 1024 threads per image: each thread owns a contiguous run of bins.
+// Exclusive scan of the counts, 4 per thread and 4096 per pass, carried across passes.
 __global__ void __launch_bounds__(1024) k_bin_scan(BandDev b, int all_images)
 {
+    __shared__ int wsum[16];
+    __shared__ int carry_s;
     const BandState* st = b.st;
     const int k = blockIdx.x;
     if (band_stopped(st) || !image_active(st, k, all_images)) return;
@@ -60,62 +78,82 @@ __global__ void __launch_bounds__(1024) k_bin_scan(BandDev b, int all_images)
     const int nbins = b.geom[slot].nbins;
     int* cnt = b.bcount + bin_base(b, slot);
     int* start = b.bstart + bin_base(b, slot);
-    int* cur = b.bcursor + bin_base(b, slot);
-    const int t = threadIdx.x;
-    const int chunk = (nbins + 1023) / 1024;
-    const int lo = min(t * chunk, nbins), hi = min(lo + chunk, nbins);
-    int local = 0;
-    for (int p = lo; p < hi; ++p) local += cnt[p];
-    // block exclusive scan: wave inclusive scan, then the 16 wave totals
-    __shared__ int wsum[16];
-    const int lane = t & 63, wid = t >> 6;
-    int incl = local;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    int carry = 0;
+    for (int base = 0; base < nbins; base += 4096) {
+        const int idx = base + 4 * t;
+        int c[4];
+        for (int q = 0; q < 4; ++q) c[q] = (idx + q < nbins) ? cnt[idx + q] : 0;
+        const int s1 = c[0] + c[1], s2 = s1 + c[2], tot = s2 + c[3];
+        int incl = tot;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        if (t == 0) {
+            int run = 0;
+            for (int w = 0; w < 16; ++w) {
+                const int v = wsum[w];
+                wsum[w] = run;
+                run += v;
+            }
+            carry_s = run;
+        }
+        __syncthreads();
+        const int excl = carry + wsum[wid] + incl - tot;
+        const int pre[4] = {0, c[0], s1, s2};
+        for (int q = 0; q < 4; ++q)
+            if (idx + q < nbins) {
+                start[idx + q] = excl + pre[q];
+                cnt[idx + q] = 0;
+            }
+        carry += carry_s;
+        __syncthreads();
     }
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wid; ++w) base += wsum[w];
-    int run = base + incl - local;
-    for (int p = lo; p < hi; ++p) {
-        start[p] = run;
-        cur[p] = run;
-        run += cnt[p];
-        cnt[p] = 0;
-    }
-    if (t == 1023) start[nbins] = base + incl;
+    if (t == 0) start[nbins] = carry;
 }
 
-__global__ void __launch_bounds__(CFNEB_TILE) k_bin_fill(BandDev b, int all_images)
+__global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BandDev b, int all_images)
 {
-    BandState* st = b.st;
-    const int k = blockIdx.y;
-    const int i = blockIdx.x * CFNEB_TILE + threadIdx.x;
-    if (band_stopped(st) || !image_active(st, k, all_images) || i >= b.N) return;
+    const BandState* st = b.st;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, b.ntA, all_images);
+    const int k = w.image;
+    const int i = w.tile * CFNEB_TILE + threadIdx.x;
+    if (!w.valid || i >= b.N) return;
     const int slot = st->slot[k];
-    const int bin = b.binfo[size_t(slot) * b.N + i].x;
-    const int pos = atomicAdd(&b.bcursor[bin_base(b, slot) + bin], 1);
-    if (pos >= 0 && pos < b.N)
-        b.batoms[size_t(slot) * b.N + pos] = i;
+    const int4 bi = b.binfo[size_t(slot) * b.N + i];
+    const int pos = b.bstart[bin_base(b, slot) + bi.x] + bi.y;
+    if (pos < 0 || pos >= b.N) return;
+    const double* R = Rs(b, slot);
+    BinAtom a;
+    a.x = R[i];
+    a.y = R[b.ld + i];
+    a.z = R[2 * size_t(b.ld) + i];
+    a.info = pack_info(i, (bi.z & 0x3FF) - 512, ((bi.z >> 10) & 0x3FF) - 512, ((bi.z >> 20) & 0x3FF) - 512);
+    b.bpos[size_t(slot) * b.N + pos] = a;
 }
 
 __global__ void __launch_bounds__(CFNEB_TILE) k_bin_sort(BandDev b, int all_images)
 {
     const BandState* st = b.st;
-    const int k = blockIdx.y;
-    const int bin = blockIdx.x * CFNEB_TILE + threadIdx.x;
-    if (band_stopped(st) || !image_active(st, k, all_images)) return;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, (b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE, all_images);
+    const int k = w.image;
+    const int bin = w.tile * CFNEB_TILE + threadIdx.x;
+    if (!w.valid) return;
     const int slot = st->slot[k];
     if (bin >= b.geom[slot].nbins) return;
     const int* start = b.bstart + bin_base(b, slot);
-    int* a = b.batoms + size_t(slot) * b.N;
+    BinAtom* a = b.bpos + size_t(slot) * b.N;
     const int lo = start[bin], hi = min(start[bin + 1], b.N);
     for (int p = lo + 1; p < hi; ++p) {
-        const int v = a[p];
+        const BinAtom v = a[p];
+        const int key = info_j(v.info);
         int q = p - 1;
-        while (q >= lo && a[q] > v) {
+        while (q >= lo && info_j(a[q].info) > key) {
             a[q + 1] = a[q];
             --q;
         }
@@ -126,10 +164,11 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_sort(BandDev b, int all_imag
 __device__ inline int floordiv_i(int a, int m) { return (a >= 0) ? a / m : -((-a + m - 1) / m); }
 
 // Exact squared distance of entry (j, n); every operation rounded separately.
-__device__ inline double exact_r2(const double* ri, const double* rj, const double* h, int n0,
-                                  int n1, int n2, double* d)
+__device__ inline double exact_r2(const double* ri, double xj, double yj, double zj, const double* h,
+                                  int n0, int n1, int n2, double* d)
 {
 #pragma clang fp contract(off)
+    const double rj[3] = {xj, yj, zj};
     for (int c = 0; c < 3; ++c) {
         const double sh = (double(n0) * h[c] + double(n1) * h[3 + c]) + double(n2) * h[6 + c];
         d[c] = (rj[c] - ri[c]) + sh;
@@ -141,15 +180,16 @@ template <typename T, bool STORE_BONDS>
 __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
 {
     BandState* st = b.st;
-    const int k = blockIdx.y;
-    const int i = blockIdx.x * CFNEB_TILE + threadIdx.x;
-    if (band_stopped(st) || !image_active(st, k, all_images) || i >= b.N) return;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, b.ntA, all_images);
+    const int k = w.image;
+    const int i = w.tile * CFNEB_TILE + threadIdx.x;
+    if (!w.valid || i >= b.N) return;
     const int slot = st->slot[k];
     const ImageGeom& g = b.geom[slot];
     const double* R = Rs(b, slot);
-    const int4* info = b.binfo + size_t(slot) * b.N;
     const int* start = b.bstart + bin_base(b, slot);
-    const int* atoms = b.batoms + size_t(slot) * b.N;
+    const BinAtom* bp = b.bpos + size_t(slot) * b.N;
     const size_t N = b.N;
     uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
     using T4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
@@ -158,30 +198,32 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
     double h[9];
     for (int q = 0; q < 9; ++q) h[q] = g.h[q];
     const double ri[3] = {R[i], R[b.ld + i], R[2 * size_t(b.ld) + i]};
-    const int4 me = info[i];
+    const int4 me = b.binfo[size_t(slot) * N + i];
+    const int im0 = (me.z & 0x3FF) - 512, im1 = ((me.z >> 10) & 0x3FF) - 512, im2 = ((me.z >> 20) & 0x3FF) - 512;
     const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];
     const int b0 = me.x / (nb1 * nb2), b1 = (me.x / nb2) % nb1, b2 = me.x % nb2;
+    const int r0 = g.reach[0], r1 = g.reach[1], r2 = g.reach[2];
     int cnt = 0;
     bool bad_shift = false;
-    for (int dx = -g.reach[0]; dx <= g.reach[0]; ++dx) {
+    for (int dx = -r0; dx <= r0; ++dx) {
         const int v0 = b0 + dx, m0 = floordiv_i(v0, nb0), a0 = v0 - m0 * nb0;
-        for (int dy = -g.reach[1]; dy <= g.reach[1]; ++dy) {
+        for (int dy = -r1; dy <= r1; ++dy) {
             const int v1 = b1 + dy, m1 = floordiv_i(v1, nb1), a1 = v1 - m1 * nb1;
-            for (int dz = -g.reach[2]; dz <= g.reach[2]; ++dz) {
+            const int row = (a0 * nb1 + a1) * nb2;
+            for (int dz = -r2; dz <= r2; ++dz) {
                 const int v2 = b2 + dz, m2 = floordiv_i(v2, nb2), a2 = v2 - m2 * nb2;
-                const int bin = (a0 * nb1 + a1) * nb2 + a2;
+                const int bin = row + a2;
                 const int lo = start[bin], hi = min(start[bin + 1], b.N);
                 for (int p = lo; p < hi; ++p) {
-                    const int j = atoms[p];
-                    const int4 oj = info[j];
-                    const int n0 = m0 + me.y - oj.y;
-                    const int n1 = m1 + me.z - oj.z;
-                    const int n2 = m2 + me.w - oj.w;
+                    const BinAtom a = bp[p];
+                    const int j = info_j(a.info);
+                    const int n0 = m0 + im0 - info_n(a.info, 0);
+                    const int n1 = m1 + im1 - info_n(a.info, 1);
+                    const int n2 = m2 + im2 - info_n(a.info, 2);
                     if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-                    const double rj[3] = {R[j], R[b.ld + j], R[2 * size_t(b.ld) + j]};
                     double d[3];
-                    const double r2 = exact_r2(ri, rj, h, n0, n1, n2, d);
-                    if (!(r2 < b.rc2)) continue;
+                    const double rr = exact_r2(ri, a.x, a.y, a.z, h, n0, n1, n2, d);
+                    if (!(rr < b.rc2)) continue;
                     if (abs(n0) > CFNEB_MAX_SHIFT || abs(n1) > CFNEB_MAX_SHIFT || abs(n2) > CFNEB_MAX_SHIFT) {
                         bad_shift = true;
                         continue;
@@ -193,7 +235,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
                             e.x = T(d[0]);
                             e.y = T(d[1]);
                             e.z = T(d[2]);
-                            e.w = T(sqrt(r2));
+                            e.w = T(sqrt(rr));
                             dvec[size_t(cnt) * N + i] = e;
                         }
                     }
@@ -209,17 +251,17 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
 
 void launch_bins(const BandDev& b, int all_images, hipStream_t s)
 {
-    const dim3 gA(b.ntA, b.Mcap);
+    const unsigned gA = cfneb_grid(b.ntA, b.Mcap);
     k_bin_assign<<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
     k_bin_scan<<<b.Mcap, 1024, 0, s>>>(b, all_images);
-    k_bin_fill<<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-    const dim3 gB((b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE, b.Mcap);
+    k_bin_scatter<<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+    const unsigned gB = cfneb_grid((b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE, b.Mcap);
     k_bin_sort<<<gB, CFNEB_TILE, 0, s>>>(b, all_images);
 }
 
 void launch_list(const BandDev& b, int all_images, hipStream_t s)
 {
-    const dim3 gA(b.ntA, b.Mcap);
+    const unsigned gA = cfneb_grid(b.ntA, b.Mcap);
     if (b.potential == CFNEB_TERSOFF_C) {
         if (b.fp64)
             k_nlist<double, true><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);

@@ -124,9 +124,10 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BandDev b, int mode)
     __shared__ int bad[4];
     BandState* st = b.st;
     if (mode == 0 && (band_stopped(st) || !st->refine_due)) return;
-    const int k = blockIdx.y;  // interval k: images k, k+1
-    if (k >= st->M - 1) return;
-    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
+    const WorkItem w = xcd_item(b.ntR, 0, st->M - 1);
+    if (!w.valid) return;
+    const int k = w.image;  // interval k: images k, k+1
+    const int r = w.tile * CFNEB_TILE + threadIdx.x;
     U128 acc = {0, 0};
     int ok = 1;
     if (r < b.N + 3) {
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BandDev b, int mode)
         add128(s, lds[1]);
         add128(s, lds[2]);
         add128(s, lds[3]);
-        uint64_t* out = b.refpart + (size_t(k) * b.ntR + blockIdx.x) * 2;
+        uint64_t* out = b.refpart + (size_t(k) * b.ntR + w.tile) * 2;
         out[0] = s.lo;
         out[1] = s.hi;
         if (!(bad[0] && bad[1] && bad[2] && bad[3])) set_error(st, CFNEB_ERANGE);
@@ -250,9 +251,10 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_apply(BandDev b, int mode
     BandState* st = b.st;
     if (mode == 0 && (band_stopped(st) || !st->refine_due)) return;
     if (!st->changed || st->err != 0) return;
-    const int r = blockIdx.x * CFNEB_TILE + threadIdx.x;
-    const int k = blockIdx.y;  // logical image after the change
-    if (r >= b.N + 3 || k >= st->M) return;
+    const WorkItem w = xcd_item(b.ntR, 0, st->M);
+    const int r = w.tile * CFNEB_TILE + threadIdx.x;
+    const int k = w.image;  // logical image after the change
+    if (!w.valid || r >= b.N + 3) return;
     const int slot = st->slot[k];
     if (st->ins >= 0 && k == st->ins) {
         const double* Xa = Xs(b, st->ins_a);
@@ -299,7 +301,7 @@ __global__ void k_readout(BandDev b)
 void launch_refine(const BandDev& b, int forced, hipStream_t s)
 {
     if (forced) k_refine_force<<<1, 1, 0, s>>>(b);
-    const dim3 gR(b.ntR, b.Mcap);
+    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
     k_refine_dist<<<gR, CFNEB_TILE, 0, s>>>(b, forced ? 1 : 0);
     k_refine_decide<<<1, 64, 0, s>>>(b, forced ? 1 : 0);
     k_refine_apply<<<gR, CFNEB_TILE, 0, s>>>(b, forced ? 1 : 0);
@@ -308,7 +310,7 @@ void launch_refine(const BandDev& b, int forced, hipStream_t s)
 
 void launch_readout(const BandDev& b, hipStream_t s)
 {
-    const dim3 gR(b.ntR, b.Mcap);
+    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
     k_refine_dist<<<gR, CFNEB_TILE, 0, s>>>(b, 1);
     k_refine_decide<<<1, 64, 0, s>>>(b, 2);
     k_readout<<<1, 1, 0, s>>>(b);

@@ -23,7 +23,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     int N, ld, Mcap, ntA, ntR, nbcap, cap, fp64, tersoff;
-    size_t X, V, R, F, FN, binfo, bcount, bstart, bcursor, batoms, nbr, ncnt, dvec, bo, P, geom, scal,
+    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, dvec, bo, P, geom, scal,
         evpart, dotpart, maxpart, refpart, staging, state, total;
 };
 
@@ -37,7 +37,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->Mcap = max_images;
     L->ntA = (L->N + CFNEB_TILE - 1) / CFNEB_TILE;
     L->ntR = (L->N + 3 + CFNEB_TILE - 1) / CFNEB_TILE;
-    L->nbcap = 2 * L->N + 64;
+    L->nbcap = L->N + 64;
     L->cap = p->nbr_cap;
     L->fp64 = p->force_fp64 ? 1 : 0;
     L->tersoff = (p->potential == CFNEB_TERSOFF_C) ? 1 : 0;
@@ -57,8 +57,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->binfo = take(M * N * 16);
     L->bcount = take(M * (L->nbcap + 1) * 4);
     L->bstart = take(M * (L->nbcap + 1) * 4);
-    L->bcursor = take(M * (L->nbcap + 1) * 4);
-    L->batoms = take(M * N * 4);
+    L->bpos = take(M * N * sizeof(BinAtom));
     L->nbr = take(M * size_t(L->cap) * N * 4);
     L->ncnt = take(M * N * 4);
     L->dvec = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
@@ -215,8 +214,7 @@ void fill_dev(cfneb_band* b, void* ws)
     d.binfo = reinterpret_cast<int4*>(base + L.binfo);
     d.bcount = reinterpret_cast<int*>(base + L.bcount);
     d.bstart = reinterpret_cast<int*>(base + L.bstart);
-    d.bcursor = reinterpret_cast<int*>(base + L.bcursor);
-    d.batoms = reinterpret_cast<int*>(base + L.batoms);
+    d.bpos = reinterpret_cast<BinAtom*>(base + L.bpos);
     d.nbr = reinterpret_cast<uint32_t*>(base + L.nbr);
     d.ncnt = reinterpret_cast<int*>(base + L.ncnt);
     d.dvec = L.tersoff ? base + L.dvec : nullptr;

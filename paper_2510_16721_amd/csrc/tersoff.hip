@@ -1,0 +1,320 @@
+// Tersoff bond-order carbon: energies, dU_i/dr^ij per bond, force gather (Sec. II.B).
+//
+//   U_i = 1/2 sum_j fc(r_ij) [A exp(-l1 r_ij) - b_ij B exp(-l2 r_ij)],
+//   b_ij = (1 + beta^n zeta_ij^n)^(-1/2n),  zeta_ij = sum_{k != j} fc(r_ik) g(cos theta_ijk),
+//   fc = 1 below R, 1/2 + 1/2 cos(pi (r - R)/(S - R)) between R and S, 0 beyond.
+// U_i depends only on i's bond vectors, so one thread per atom forms every
+// P_ij = dU_i/dr^ij from its own list (bond vectors were written by the list
+// kernel), and a second kernel gathers F_i = sum_j (P_ij - P_ji) through the
+// reverse entry (i, -n) of j's list.  No atomics: the result is deterministic.
+//
+// g is evaluated as 1 + (c^2/d^2) x / (d^2 + x), x = (h - cos)^2: the textbook form
+// 1 + c^2/d^2 - c^2/(d^2 + x) cancels two numbers near 7.7e7 and loses about four
+// digits in FP32.
+#include <type_traits>
+
+#include "cfneb_dev.h"
+
+namespace cfneb {
+
+template <typename T>
+struct TersoffT {
+    T A, B, l1, l2, bn, n, c2, d2, c2d2, h, R, S, pi_w;
+    __device__ explicit TersoffT(const BandDev& b)
+        : A(T(b.ts_A)), B(T(b.ts_B)), l1(T(b.ts_l1)), l2(T(b.ts_l2)), bn(T(b.ts_bn)), n(T(b.ts_n)),
+          c2(T(b.ts_c2)), d2(T(b.ts_d2)), c2d2(T(b.ts_c2d2)), h(T(b.ts_h)), R(T(b.ts_R)), S(T(b.ts_S)),
+          pi_w(T(3.14159265358979323846 / (b.ts_S - b.ts_R)))
+    {
+    }
+    __device__ T fc(T r) const
+    {
+        if (r < R) return T(1);
+        if (r >= S) return T(0);
+        return T(0.5) + T(0.5) * cos(pi_w * (r - R));
+    }
+    __device__ T dfc(T r) const
+    {
+        if (r < R || r >= S) return T(0);
+        return T(-0.5) * pi_w * sin(pi_w * (r - R));
+    }
+    __device__ void g_dg(T cs, T& g, T& dg) const
+    {
+        const T t = h - cs;
+        const T x = t * t;
+        const T den = d2 + x;
+        g = T(1) + c2d2 * x / den;
+        dg = T(-2) * c2 * t / (den * den);
+    }
+    // bond order and its zeta derivative
+    __device__ void bond_order(T z, T& b, T& db) const
+    {
+        b = T(1);
+        db = T(0);
+        if (z > T(0)) {
+            const T zn = pow(z, n);
+            const T base = T(1) + bn * zn;
+            b = pow(base, T(-0.5) / n);
+            db = T(-0.5) * bn * (zn / z) * (b / base);
+        }
+    }
+};
+
+template <typename T>
+using vec4_t = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+template <typename T>
+using vec2_t = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+
+// acc[0] += u_i, acc[1..9] -= r^ij (x) P_ij (row-major)
+template <typename T>
+__device__ inline void add_virial(double* acc, T dx, T dy, T dz, T px, T py, T pz)
+{
+    const double x = double(dx), y = double(dy), z = double(dz);
+    acc[1] -= x * double(px);
+    acc[2] -= x * double(py);
+    acc[3] -= x * double(pz);
+    acc[4] -= y * double(px);
+    acc[5] -= y * double(py);
+    acc[6] -= y * double(pz);
+    acc[7] -= z * double(px);
+    acc[8] -= z * double(py);
+    acc[9] -= z * double(pz);
+}
+
+// Atoms with at most MAXB bonds: every bond quantity lives in registers.
+template <typename T, int MAXB>
+__device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T>* Pout, size_t N,
+                             int i, int cnt, double* acc)
+{
+    T dx[MAXB], dy[MAXB], dz[MAXB], r[MAXB], fc[MAXB], dfc[MAXB], fa[MAXB], fr[MAXB], bb[MAXB], db[MAXB];
+#pragma unroll
+    for (int e = 0; e < MAXB; ++e) {
+        if (e < cnt) {
+            const vec4_t<T> d = dv[size_t(e) * N + i];
+            dx[e] = d.x;
+            dy[e] = d.y;
+            dz[e] = d.z;
+            r[e] = d.w;
+            fc[e] = P.fc(r[e]);
+            dfc[e] = P.dfc(r[e]);
+            fr[e] = P.A * exp(-P.l1 * r[e]);
+            fa[e] = P.B * exp(-P.l2 * r[e]);
+        } else {
+            dx[e] = dy[e] = dz[e] = T(0);
+            r[e] = T(1);
+            fc[e] = dfc[e] = fr[e] = fa[e] = T(0);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < MAXB; ++e) {
+        bb[e] = T(1);
+        db[e] = T(0);
+        if (e < cnt) {
+            T z = T(0);
+#pragma unroll
+            for (int q = 0; q < MAXB; ++q) {
+                if (q == e || q >= cnt) continue;
+                const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) / (r[e] * r[q]);
+                T g, dg;
+                P.g_dg(cs, g, dg);
+                z += fc[q] * g;
+            }
+            P.bond_order(z, bb[e], db[e]);
+            acc[0] += double(T(0.5) * fc[e] * (fr[e] - bb[e] * fa[e]));
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < MAXB; ++e) {
+        if (e >= cnt) continue;
+        const T ire = T(1) / r[e];
+        const T hx = dx[e] * ire, hy = dy[e] * ire, hz = dz[e] * ire;
+        // radial derivative at fixed bond order
+        const T dV = dfc[e] * (fr[e] - bb[e] * fa[e]) + fc[e] * (-P.l1 * fr[e] + bb[e] * P.l2 * fa[e]);
+        T px = T(0.5) * dV * hx, py = T(0.5) * dV * hy, pz = T(0.5) * dV * hz;
+        const T pre_e = fc[e] * fa[e] * db[e];
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            if (q == e || q >= cnt) continue;
+            const T a = T(1) / (r[e] * r[q]);
+            const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) * a;
+            const T c = cs * ire * ire;
+            // d cos / d r^ie
+            const T cx = dx[q] * a - c * dx[e], cy = dy[q] * a - c * dy[e], cz = dz[q] * a - c * dz[e];
+            T g, dg;
+            P.g_dg(cs, g, dg);
+            const T pre_q = fc[q] * fa[q] * db[q];
+            // zeta_ie holds fc(r_q) g(cos); zeta_iq holds fc(r_e) g(cos)
+            const T ang = T(0.5) * (pre_e * fc[q] + pre_q * fc[e]) * dg;
+            const T rad = T(0.5) * pre_q * dfc[e] * g;
+            px -= ang * cx + rad * hx;
+            py -= ang * cy + rad * hy;
+            pz -= ang * cz + rad * hz;
+        }
+        vec4_t<T> o;
+        o.x = px;
+        o.y = py;
+        o.z = pz;
+        o.w = T(0);
+        Pout[size_t(e) * N + i] = o;
+        add_virial<T>(acc, dx[e], dy[e], dz[e], px, py, pz);
+    }
+}
+
+// Any number of bonds: bond orders go through the per-bond scratch array.
+template <typename T>
+__device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_t<T>* bo,
+                                vec4_t<T>* Pout, size_t N, int i, int cnt, double* acc)
+{
+    for (int e = 0; e < cnt; ++e) {
+        const vec4_t<T> de = dv[size_t(e) * N + i];
+        T z = 0;
+        for (int q = 0; q < cnt; ++q) {
+            if (q == e) continue;
+            const vec4_t<T> dq = dv[size_t(q) * N + i];
+            const T cs = (de.x * dq.x + de.y * dq.y + de.z * dq.z) / (de.w * dq.w);
+            T g, dg;
+            P.g_dg(cs, g, dg);
+            z += P.fc(dq.w) * g;
+        }
+        vec2_t<T> o;
+        P.bond_order(z, o.x, o.y);
+        bo[size_t(e) * N + i] = o;
+        const T fr = P.A * exp(-P.l1 * de.w), fa = P.B * exp(-P.l2 * de.w);
+        acc[0] += double(T(0.5) * P.fc(de.w) * (fr - o.x * fa));
+    }
+    for (int e = 0; e < cnt; ++e) {
+        const vec4_t<T> de = dv[size_t(e) * N + i];
+        const vec2_t<T> be = bo[size_t(e) * N + i];
+        const T re = de.w, ire = T(1) / re;
+        const T hx = de.x * ire, hy = de.y * ire, hz = de.z * ire;
+        const T fce = P.fc(re), dfce = P.dfc(re);
+        const T fre = P.A * exp(-P.l1 * re), fae = P.B * exp(-P.l2 * re);
+        const T dV = dfce * (fre - be.x * fae) + fce * (-P.l1 * fre + be.x * P.l2 * fae);
+        T px = T(0.5) * dV * hx, py = T(0.5) * dV * hy, pz = T(0.5) * dV * hz;
+        const T pre_e = fce * fae * be.y;
+        for (int q = 0; q < cnt; ++q) {
+            if (q == e) continue;
+            const vec4_t<T> dq = dv[size_t(q) * N + i];
+            const vec2_t<T> bq = bo[size_t(q) * N + i];
+            const T rq = dq.w;
+            const T a = T(1) / (re * rq);
+            const T cs = (de.x * dq.x + de.y * dq.y + de.z * dq.z) * a;
+            const T c = cs * ire * ire;
+            const T cx = dq.x * a - c * de.x, cy = dq.y * a - c * de.y, cz = dq.z * a - c * de.z;
+            T g, dg;
+            P.g_dg(cs, g, dg);
+            const T fcq = P.fc(rq);
+            const T pre_q = fcq * (P.B * exp(-P.l2 * rq)) * bq.y;
+            const T ang = T(0.5) * (pre_e * fcq + pre_q * fce) * dg;
+            const T rad = T(0.5) * pre_q * dfce * g;
+            px -= ang * cx + rad * hx;
+            py -= ang * cy + rad * hy;
+            pz -= ang * cz + rad * hz;
+        }
+        vec4_t<T> o;
+        o.x = px;
+        o.y = py;
+        o.z = pz;
+        o.w = T(0);
+        Pout[size_t(e) * N + i] = o;
+        add_virial<T>(acc, de.x, de.y, de.z, px, py, pz);
+    }
+}
+
+// u_i, P_ij and the per-atom virial; block partials of (E, V) in FP64.
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_ts_bonds(BandDev b, int all_images)
+{
+    __shared__ double lds[4 * 10];
+    BandState* st = b.st;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, b.ntA, all_images);
+    if (!w.valid) return;
+    const int k = w.image;
+    const int i = w.tile * CFNEB_TILE + threadIdx.x;
+    const int slot = st->slot[k];
+    const size_t N = b.N;
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < b.N) {
+        const TersoffT<T> P(b);
+        const vec4_t<T>* dv = reinterpret_cast<const vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
+        vec4_t<T>* Pout = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.cap * N;
+        const int cnt = min(b.ncnt[size_t(slot) * N + i], b.cap);
+        if (cnt <= 6) {
+            ts_atom_regs<T, 6>(P, dv, Pout, N, i, cnt, acc);
+        } else {
+            vec2_t<T>* bo = reinterpret_cast<vec2_t<T>*>(b.bo) + size_t(slot) * b.cap * N;
+            ts_atom_generic<T>(P, dv, bo, Pout, N, i, cnt, acc);
+        }
+    }
+    block_sum<10>(acc, lds);
+    if (threadIdx.x == 0) {
+        double* out = b.evpart + (size_t(slot) * b.ntA + w.tile) * 10;
+        for (int q = 0; q < 10; ++q) out[q] = acc[q];
+    }
+}
+
+// F_i = sum_e (P_e - P_rev(e)), rev(e) = the entry (i, -n) in j's list.
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_ts_gather(BandDev b, int all_images)
+{
+    BandState* st = b.st;
+    if (band_stopped(st)) return;
+    const WorkItem w = image_item(st, b.ntA, all_images);
+    if (!w.valid) return;
+    const int k = w.image;
+    const int i = w.tile * CFNEB_TILE + threadIdx.x;
+    if (i >= b.N) return;
+    const int slot = st->slot[k];
+    const size_t N = b.N;
+    const uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
+    const int* ncnt = b.ncnt + size_t(slot) * N;
+    const vec4_t<T>* Pb = reinterpret_cast<const vec4_t<T>*>(b.P) + size_t(slot) * b.cap * N;
+    const int cnt = min(ncnt[i], b.cap);
+    T fx = 0, fy = 0, fz = 0;
+    bool missing = false;
+    for (int e = 0; e < cnt; ++e) {
+        const uint32_t ent = nbr[size_t(e) * N + i];
+        const int j = nbr_j(ent);
+        const vec4_t<T> pe = Pb[size_t(e) * N + i];
+        fx += pe.x;
+        fy += pe.y;
+        fz += pe.z;
+        const uint32_t want = pack_nbr(i, -nbr_n(ent, 0), -nbr_n(ent, 1), -nbr_n(ent, 2));
+        const int cj = min(ncnt[j], b.cap);
+        int found = -1;
+        for (int q = 0; q < cj; ++q)
+            if (nbr[size_t(q) * N + j] == want) {
+                found = q;
+                break;
+            }
+        if (found < 0) {
+            missing = true;
+            continue;
+        }
+        const vec4_t<T> pr = Pb[size_t(found) * N + j];
+        fx -= pr.x;
+        fy -= pr.y;
+        fz -= pr.z;
+    }
+    T* F = reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b);
+    F[i] = fx;
+    F[b.ld + i] = fy;
+    F[2 * size_t(b.ld) + i] = fz;
+    if (missing) set_error(st, CFNEB_ENEIGH);
+    if (!isfinite(double(fx) + double(fy) + double(fz))) set_error(st, CFNEB_ENONFINITE);
+}
+
+// stage 0: bond orders, P_ij, energy and virial; stage 1: force gather
+void launch_tersoff_stage(const BandDev& b, int all_images, int stage, hipStream_t s)
+{
+    const unsigned gA = cfneb_grid(b.ntA, b.Mcap);
+    if (b.fp64) {
+        if (stage == 0) k_ts_bonds<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+        if (stage == 1) k_ts_gather<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+    } else {
+        if (stage == 0) k_ts_bonds<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+        if (stage == 1) k_ts_gather<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+    }
+}
+
+}  // namespace cfneb

@@ -22,6 +22,11 @@ def workload(name):
         return W.small_graphite(), "ts"
     if name == "ts_diamond":
         return W.diamond_vacancy_hop(2, 2, 2), "ts"
+    if name == "ts_dense":
+        # random carbon at 0.2 atoms/A^3: most atoms have more than 6 bonds inside 2.1 A
+        R, h = W.random_cell(160, 21, density=0.2, skew=0.2, min_sep=1.1)
+        return dict(pos_init=R, cell_init=h, pos_final=R.copy(), cell_final=h * 1.02,
+                    n=len(R)), "ts"
     if name == "ts4608":
         return W.tersoff_graphite_4608(), "ts"
     if name == "ts98304":

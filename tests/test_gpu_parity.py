@@ -44,7 +44,7 @@ def test_create_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name,rc", [("lj255", 2.5), ("lj31", 2.5), ("lj_ragged", 2.5),
-                                     ("ts_small", 2.1), ("ts_diamond", 2.1)])
+                                     ("ts_small", 2.1), ("ts_diamond", 2.1), ("ts_dense", 2.1)])
 def test_neighbour_sets_bit_exact(name, rc):
     g, _, w, kind = make_pair(name, n_images=5, max_images=5, oracle_too=False)
     for k in range(5):
@@ -56,7 +56,8 @@ def test_neighbour_sets_bit_exact(name, rc):
 
 @pytest.mark.parametrize("name,fp64", [("lj255", False), ("lj255", True), ("lj31", False),
                                        ("ts_small", False), ("ts_small", True),
-                                       ("ts_diamond", False), ("ts4608", False)])
+                                       ("ts_diamond", False), ("ts_dense", False),
+                                       ("ts_dense", True), ("ts4608", False)])
 def test_energy_force_virial_per_image(name, fp64):
     import oracle
     press = 5.0 if name.startswith("ts") else 0.0
@@ -64,11 +65,15 @@ def test_energy_force_virial_per_image(name, fp64):
                               pressure_GPa=press)
     p = oracle_params_like(kind, pressure_GPa=press)
     scale = 1e-6 if fp64 else 1.0
+    # random dense carbon (+1.8 eV/atom, bonds down to 1.1 A) cancels repulsive and
+    # attractive bond terms near 30 eV each; one FP32 rounding of such a term is
+    # about 2e-6 eV, so this far-from-equilibrium case gets ten times the energy bound
+    e_scale = 10.0 if (name == "ts_dense" and not fp64) else 1.0
     n = g.n
     for k in range(5):
         img = g.image(k)
         E, u, F, V = oracle.evaluate(p, img["R"], img["h"])
-        assert abs(img["E"] - E) / n <= TOL_E_PER_ATOM * scale, (k, img["E"], E)
+        assert abs(img["E"] - E) / n <= TOL_E_PER_ATOM * scale * e_scale, (k, img["E"], E)
         assert np.abs(img["F"] - F).max() <= TOL_F * scale, k
         assert np.abs(img["V"] - V).max() / n <= TOL_V_PER_ATOM * scale, k
     # generalized forces of the cell filter from the same coordinates
@@ -77,7 +82,7 @@ def test_energy_force_virial_per_image(name, fp64):
     for k in [0, 2, 4]:
         ref = oracle.cf_eval(p, h0, st["X"][k])
         img = g.image(k)
-        assert abs(img["H"] - ref["H"]) / n <= TOL_E_PER_ATOM * scale
+        assert abs(img["H"] - ref["H"]) / n <= TOL_E_PER_ATOM * scale * e_scale
         assert np.abs(img["Fg"][:n] - ref["Fg"][:n]).max() <= 2 * TOL_F * scale
         np.testing.assert_allclose(img["Fg"][n:], ref["Fg"][n:], rtol=0,
                                    atol=TOL_V_PER_ATOM * scale * 10)
@@ -197,3 +202,29 @@ def test_minimal_band_and_single_atom():
     o.step(5)
     np.testing.assert_allclose(g.get_state()["X"], o.get_state()["X"], rtol=0, atol=1e-9)
     del W
+
+
+def test_full_size_band_sampled_image():
+    # 98,304-atom graphite -> diamond-like band at 15 GPa, 24 images, as in the benchmark:
+    # after two steps, one moving image is checked against the oracle in full
+    import oracle
+    kw = dict(n_images=24, max_images=40, min_images=5, pressure_GPa=15.0, refine_every=20,
+              climb_after=100)
+    g, _, w, kind = make_pair("ts98304", oracle_too=False, **kw)
+    g.step(2)
+    assert g.step(1, 1e30) == (0, pytest.approx(g.step(1, 1e30)[1]), True)  # evaluate, no move
+    k = 11
+    img = g.image(k)
+    cnt, ent = g.neighbours(k)
+    ref = oracle.nlist(img["R"], img["h"], 2.1)
+    for i in range(0, g.n, 97):
+        np.testing.assert_array_equal(sort_entries(ent[i]), ref[i])
+    assert np.array_equal(cnt, [len(x) for x in ref])
+    p = oracle_params_like(kind, pressure_GPa=15.0)
+    E, u, F, V = oracle.evaluate(p, img["R"], img["h"])
+    n = g.n
+    assert abs(img["E"] - E) / n <= TOL_E_PER_ATOM
+    assert np.abs(img["F"] - F).max() <= TOL_F
+    assert np.abs(img["V"] - V).max() / n <= TOL_V_PER_ATOM
+    ref_cf = oracle.cf_eval(p, w["cell_init"], g.get_state()["X"][k])
+    assert abs(ref_cf["H"] - img["H"]) / n <= TOL_E_PER_ATOM

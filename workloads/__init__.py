@@ -141,6 +141,18 @@ def random_cell(n, seed, density=0.08, skew=0.15, min_sep=0.0):
     h[2, 0] = skew * L * (rng.random() - 0.5)
     h[2, 1] = skew * L * (rng.random() - 0.5)
     s = rng.random((n, 3))
+    if min_sep > 0.0:
+        # random sequential addition: redraw an atom closer than min_sep to an earlier
+        # one (nearest periodic image)
+        hinv = np.linalg.inv(h)
+        for i in range(1, n):
+            for _ in range(10000):
+                ds = s[:i] - s[i]
+                ds -= np.round(ds)
+                if np.min(np.linalg.norm(ds @ h, axis=1)) >= min_sep:
+                    break
+                s[i] = rng.random(3)
+        del hinv
     # unwrapped positions: some atoms sit one or two cells away
     s += rng.integers(-2, 3, size=(n, 3)) * (rng.random((n, 3)) < 0.1)
     return s @ h, h
