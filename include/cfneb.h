@@ -209,6 +209,41 @@ int cfneb_neighbours(const cfneb_band* b, int k, int32_t* cnt, int32_t* ent, int
 
 int cfneb_destroy(cfneb_band* b);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent bands stepped together.  Every phase of the step (the same
+ * computation as cfneb_step) is ONE persistent launch over the work items of all
+ * live bands, whatever their atom and image counts; the step is captured once in a
+ * hipGraph, and attaching or detaching a band only rewrites a device table.  Each
+ * band's result does not depend on its batch-mates (no shared reductions).
+ * Ownership: the caller owns the batch workspace (cfneb_batch_bytes) and the bands;
+ * a band stays owned by its creator and must outlive its membership.  While
+ * attached, a band must not be stepped on its own. */
+typedef struct cfneb_batch cfneb_batch;
+
+/* Device bytes of a batch table for up to max_bands bands (<= 128). */
+int cfneb_batch_bytes(int max_bands, size_t* bytes);
+
+/* hip_stream: the stream every batch launch goes to (NULL: null stream). */
+int cfneb_batch_create(int max_bands, void* workspace, size_t workspace_bytes, void* hip_stream,
+                       cfneb_batch** out);
+
+/* Add a band (created with cfneb_create_band); *slot receives its table index.
+ * Returns CFNEB_ECAPACITY when the table is full. */
+int cfneb_batch_attach(cfneb_batch* batch, cfneb_band* band, int* slot);
+
+/* Remove the band in table slot `slot` (the band itself is untouched). */
+int cfneb_batch_detach(cfneb_batch* batch, int slot);
+
+/* Up to max_steps steps of every attached band with the same f_tol; a band that
+ * converges or fails stops moving while the others go on, and the call returns
+ * early once no band is still relaxing.  Per table slot (arrays of max_bands
+ * entries, any may be NULL): steps taken in this call, converged flag, error code
+ * (0 or a CFNEB_E* code; the band is left at its pre-step state). */
+int cfneb_batch_step(cfneb_batch* batch, int max_steps, double f_tol, int* steps_done,
+                     uint8_t* converged, int* errors);
+
+int cfneb_batch_destroy(cfneb_batch* batch);
+
 const char* cfneb_strerror(int code);
 const char* cfneb_last_error(const cfneb_band* b);
 

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcfneb.so")
-SOURCES = ["geometry.hip", "nlist.hip", "forces.hip", "tersoff.hip", "band.hip", "refine.hip", "runtime.hip"]
+SOURCES = ["geometry.hip", "nlist.hip", "forces.hip", "tersoff.hip", "band.hip", "refine.hip", "batch.hip",
+           "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

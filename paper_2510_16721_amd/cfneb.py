@@ -24,7 +24,9 @@ SYMBOLS = ["cfneb_params_default", "cfneb_band_bytes", "cfneb_create_band", "cfn
            "cfneb_step_profiled",
            "cfneb_refine", "cfneb_energies", "cfneb_get_image", "cfneb_get_state",
            "cfneb_set_state", "cfneb_image_data", "cfneb_record_neb_force", "cfneb_neighbours",
-           "cfneb_destroy", "cfneb_strerror", "cfneb_last_error"]
+           "cfneb_destroy", "cfneb_strerror", "cfneb_last_error", "cfneb_batch_bytes",
+           "cfneb_batch_create", "cfneb_batch_attach", "cfneb_batch_detach", "cfneb_batch_step",
+           "cfneb_batch_destroy"]
 
 
 class Params(ctypes.Structure):
@@ -105,6 +107,12 @@ def _declare(L):
     L.cfneb_strerror.restype = ctypes.c_char_p
     L.cfneb_last_error.argtypes = [c_void]
     L.cfneb_last_error.restype = ctypes.c_char_p
+    L.cfneb_batch_bytes.argtypes = [c_int, ctypes.POINTER(c_size)]
+    L.cfneb_batch_create.argtypes = [c_int, c_void, c_size, c_void, ctypes.POINTER(c_void)]
+    L.cfneb_batch_attach.argtypes = [c_void, c_void, ctypes.POINTER(c_int)]
+    L.cfneb_batch_detach.argtypes = [c_void, c_int]
+    L.cfneb_batch_step.argtypes = [c_void, c_int, c_double, _ip, ctypes.POINTER(ctypes.c_uint8), _ip]
+    L.cfneb_batch_destroy.argtypes = [c_void]
 
 
 class CfnebError(RuntimeError):
@@ -286,3 +294,68 @@ class Band:
         cap = self.p.nbr_cap
         off = np.concatenate([[0], np.cumsum(np.minimum(cnt, cap))])
         return cnt, [ent[off[i]:off[i + 1]].copy() for i in range(n)]
+
+
+def batch_bytes(max_bands):
+    out = ctypes.c_size_t()
+    rc = lib().cfneb_batch_bytes(int(max_bands), ctypes.byref(out))
+    if rc != 0:
+        raise CfnebError(rc, "cfneb_batch_bytes")
+    return out.value
+
+
+class Batch:
+    """Many bands stepped together: one persistent launch per phase over all of them."""
+
+    def __init__(self, max_bands, stream=None):
+        import torch
+        self.cap = int(max_bands)
+        nbytes = batch_bytes(self.cap)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = lib().cfneb_batch_create(self.cap, ctypes.c_void_p(ptr), self._ws.numel() - (ptr - base),
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise CfnebError(rc, "cfneb_batch_create")
+        self._h = h
+        self.bands = [None] * self.cap
+
+    def attach(self, band):
+        slot = ctypes.c_int()
+        rc = lib().cfneb_batch_attach(self._h, band._h, ctypes.byref(slot))
+        if rc != 0:
+            raise CfnebError(rc, "cfneb_batch_attach")
+        self.bands[slot.value] = band
+        return slot.value
+
+    def detach(self, slot):
+        rc = lib().cfneb_batch_detach(self._h, int(slot))
+        if rc != 0:
+            raise CfnebError(rc, "cfneb_batch_detach")
+        self.bands[slot] = None
+
+    def step(self, max_steps, f_tol=0.0):
+        """Returns (steps per slot, converged per slot, error code per slot)."""
+        steps = np.zeros(self.cap, dtype=np.int32)
+        conv = np.zeros(self.cap, dtype=np.uint8)
+        errs = np.zeros(self.cap, dtype=np.int32)
+        rc = lib().cfneb_batch_step(self._h, int(max_steps), float(f_tol), steps.ctypes.data_as(_ip),
+                                    conv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                    errs.ctypes.data_as(_ip))
+        if rc != 0:
+            raise CfnebError(rc, "cfneb_batch_step")
+        return steps, conv.astype(bool), errs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cfneb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -5,9 +5,9 @@
 // because the improved tangent is a combination a tau+ + b tau-: with
 // t = (a tau+ + b tau-) / |.|, the projection Fg - (Fg.t) t + k (|tau+| - |tau-|) t
 // (or Fg - 2 (Fg.t) t for the climbing image) only needs ten dot products per image.
-// Pass 1 (k_band_dots) streams X, Fg and v once to get them; one wave then forms the
-// coefficients and the band-global FIRE quantities P = F.v, |F|, |v| from them;
-// pass 2 (k_band_update) forms F_NEB row by row, the new velocity and the row
+// Pass 1 (k_band_dots) streams X, Fg and v once to get them; one block per band then
+// forms the coefficients and the band-global FIRE quantities P = F.v, |F|, |v| from
+// them; pass 2 (k_band_update) forms F_NEB row by row, the new velocity and the row
 // maxima; pass 3 (k_band_move) moves X once fmax and the step clamp are known.
 //
 // Generalized forces are formed on the fly: atom rows F D^T from the stored
@@ -32,9 +32,12 @@ __device__ inline void gen_force_row(const BandDev& b, int slot, int r, double* 
     }
 }
 
-__global__ void k_begin_call(BandDev b, double f_tol)
+// Start of a cfneb_step / cfneb_batch_step call for every band in the table.
+__global__ void k_begin_call(BatchDev bd, double f_tol, int only)
 {
-    BandState* st = b.st;
+    const int t = threadIdx.x;
+    if (t >= bd.cap || !bd.live[t] || (only >= 0 && t != only)) return;
+    BandState* st = bd.bands[t].st;
     st->f_tol = f_tol;
     st->steps_call = 0;
     st->done = 0;
@@ -43,15 +46,9 @@ __global__ void k_begin_call(BandDev b, double f_tol)
 
 // 10 dots per moving image: |t+|^2 |t-|^2 t+.t- F.t+ F.t- F.F F.v v.v v.t+ v.t-
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BandDev b)
+__device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
-    __shared__ double lds[4 * 10];
-    const BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntR, 0);
-    if (!w.valid) return;
-    const int k = w.image;
-    const int r = w.tile * CFNEB_TILE + threadIdx.x;
+    const int r = tile * CFNEB_TILE + threadIdx.x;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (r < b.N + 3) {
@@ -80,8 +77,21 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BandDev b)
     block_sum<10>(a, lds);
     if (threadIdx.x == 0) {
         // [image][dot][tile]: the reduction reads consecutive tiles
-        double* out = b.dotpart + size_t(k) * 10 * b.ntR + w.tile;
+        double* out = b.dotpart + size_t(k) * 10 * b.ntR + tile;
         for (int q = 0; q < 10; ++q) out[size_t(q) * b.ntR] = a[q];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BatchDev bd, unsigned vmask)
+{
+    __shared__ double lds[4 * 10];
+    ItemLoop loop(bd, KIND_ROW, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (!((vmask >> band_variant(b)) & 1u) || band_stopped(b.st)) continue;  // uniform
+        dots_item<T>(b, b.st, it.image, it.tile, lds);
     }
 }
 
@@ -108,11 +118,12 @@ __device__ inline void tangent_coeffs(double Hm, double H0, double Hp, double& a
 
 // One block per band: reduce the dot partials, choose tangents and the climbing
 // image, form the projection coefficients and the FIRE proposal.
-__global__ void __launch_bounds__(1024) k_band_scalars(BandDev b)
+__device__ void scalars_item(const BandDev& b, BandState* st)
 {
     __shared__ double dots[CFNEB_MAX_IMAGES][10];
-    BandState* st = b.st;
-    if (band_stopped(st)) return;
+    __shared__ double H[CFNEB_MAX_IMAGES];
+    __shared__ double contrib[3][CFNEB_MAX_IMAGES];
+    __shared__ int ci_s;
     const int M = st->M;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int k = 1 + wid; k <= M - 2; k += int(blockDim.x) / 64) {
@@ -125,9 +136,6 @@ __global__ void __launch_bounds__(1024) k_band_scalars(BandDev b)
             for (int q = 0; q < 10; ++q) dots[k][q] = a[q];
     }
     // image enthalpies, loaded in parallel
-    __shared__ double H[CFNEB_MAX_IMAGES];
-    __shared__ double contrib[3][CFNEB_MAX_IMAGES];
-    __shared__ int ci_s;
     const int t = threadIdx.x;
     if (t < M) H[t] = b.scal[st->slot[t]].H;
     __syncthreads();
@@ -164,55 +172,62 @@ __global__ void __launch_bounds__(1024) k_band_scalars(BandDev b)
         contrib[2][k] = d[7];
     }
     __syncthreads();
-    if (t != 0) return;
-    double Pw = 0.0, FF = 0.0, VV = 0.0;
-    for (int k = 1; k <= M - 2; ++k) {
-        Pw += contrib[0][k];
-        FF += contrib[1][k];
-        VV += contrib[2][k];
-    }
-    // FIRE (Bitzek et al. 2006) proposal; committed only if the band moves.
-    double cv = 1.0, cf = 0.0, dt = st->dt, alpha = st->alpha;
-    int np = st->n_pos;
-    if (!st->fresh) {
-        if (Pw > 0.0) {
-            const double nf = sqrt(fmax(FF, 0.0)), nv = sqrt(fmax(VV, 0.0));
-            if (nf > 0.0) {
-                cv = 1.0 - alpha;
-                cf = alpha * nv / nf;
-            }
-            if (np > b.nmin) {
-                dt = fmin(dt * b.finc, b.dtmax);
-                alpha *= b.fa;
-            }
-            np += 1;
-        } else {
-            cv = 0.0;
-            cf = 0.0;
-            alpha = b.astart;
-            dt *= b.fdec;
-            np = 0;
+    if (t == 0) {
+        double Pw = 0.0, FF = 0.0, VV = 0.0;
+        for (int k = 1; k <= M - 2; ++k) {
+            Pw += contrib[0][k];
+            FF += contrib[1][k];
+            VV += contrib[2][k];
         }
+        // FIRE (Bitzek et al. 2006) proposal; committed only if the band moves.
+        double cv = 1.0, cf = 0.0, dt = st->dt, alpha = st->alpha;
+        int np = st->n_pos;
+        if (!st->fresh) {
+            if (Pw > 0.0) {
+                const double nf = sqrt(fmax(FF, 0.0)), nv = sqrt(fmax(VV, 0.0));
+                if (nf > 0.0) {
+                    cv = 1.0 - alpha;
+                    cf = alpha * nv / nf;
+                }
+                if (np > b.nmin) {
+                    dt = fmin(dt * b.finc, b.dtmax);
+                    alpha *= b.fa;
+                }
+                np += 1;
+            } else {
+                cv = 0.0;
+                cf = 0.0;
+                alpha = b.astart;
+                dt *= b.fdec;
+                np = 0;
+            }
+        }
+        st->cv = cv;
+        st->cf = cf;
+        st->dt_new = dt;
+        st->alpha_new = alpha;
+        st->n_pos_new = np;
     }
-    st->cv = cv;
-    st->cf = cf;
-    st->dt_new = dt;
-    st->alpha_new = alpha;
-    st->n_pos_new = np;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_band_scalars(BatchDev bd)
+{
+    ItemLoop loop(bd, KIND_BAND, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (band_stopped(b.st)) continue;  // uniform over the block
+        scalars_item(b, b.st);
+    }
 }
 
 // F_NEB per row, v' = (cv v + cf F_NEB) + dt' F_NEB into the other buffer, and the
 // row maxima of |F_NEB| and |dt' v'|.
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BandDev b)
+__device__ void update_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
-    __shared__ double lds[4 * 3];
-    BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntR, 0);
-    if (!w.valid) return;
-    const int k = w.image;
-    const int r = w.tile * CFNEB_TILE + threadIdx.x;
+    const int r = tile * CFNEB_TILE + threadIdx.x;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double m[3] = {0.0, 0.0, 0.0};  // max |F_NEB row|^2, max |dr row|^2, non-finite flag
     if (r < b.N + 3) {
@@ -245,22 +260,29 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BandDev b)
     }
     block_max<3>(m, lds);
     if (threadIdx.x == 0) {
-        double* out = b.maxpart + size_t(k) * 3 * b.ntR + w.tile;  // [image][q][tile]
+        double* out = b.maxpart + size_t(k) * 3 * b.ntR + tile;  // [image][q][tile]
         out[0] = m[0];
         out[b.ntR] = m[1];
         out[2 * size_t(b.ntR)] = m[2];
     }
 }
 
-// fmax, convergence, step clamp; commit the FIRE proposal when the band moves.
-__global__ void __launch_bounds__(1024) k_band_finalize(BandDev b)
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BatchDev bd, unsigned vmask)
 {
-    __shared__ double lds[16 * 3];
-    BandState* st = b.st;
-    if (band_stopped(st)) {
-        if (threadIdx.x == 0) st->move = 0;
-        return;
+    __shared__ double lds[4 * 3];
+    ItemLoop loop(bd, KIND_ROW, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (!((vmask >> band_variant(b)) & 1u) || band_stopped(b.st)) continue;  // uniform
+        update_item<T>(b, b.st, it.image, it.tile, lds);
     }
+}
+
+// fmax, convergence, step clamp; commit the FIRE proposal when the band moves.
+__device__ void finalize_item(const BandDev& b, BandState* st, double* lds)
+{
     const int M = st->M;
     double m[3] = {0.0, 0.0, 0.0};
     const int total = (M - 2) * b.ntR;
@@ -299,65 +321,76 @@ __global__ void __launch_bounds__(1024) k_band_finalize(BandDev b)
     st->refine_due = (b.refine_every > 0 && st->step % b.refine_every == 0) ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(CFNEB_TILE) k_band_move(BandDev b)
+__global__ void __launch_bounds__(1024) k_band_finalize(BatchDev bd)
 {
-    const BandState* st = b.st;
-    if (!st->move || st->err != 0) return;
-    const WorkItem w = image_item(st, b.ntR, 0);
-    if (!w.valid) return;
-    const int k = w.image;
-    const int r = w.tile * CFNEB_TILE + threadIdx.x;
-    if (r >= b.N + 3) return;
-    const int s0 = st->slot[k];
-    double* X = Xs(b, s0);
-    const double* V = Vs(b, st->vcur, s0);
-    const double sc = st->scale, dt = st->dt;
-    for (int c = 0; c < 3; ++c) {
-        const size_t o = size_t(c) * b.ld + r;
-        X[o] += sc * (dt * V[o]);
+    __shared__ double lds[16 * 3];
+    ItemLoop loop(bd, KIND_BAND, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        if (band_stopped(st)) {  // uniform over the block
+            if (threadIdx.x == 0) st->move = 0;
+            continue;
+        }
+        finalize_item(b, st, lds);
+        __syncthreads();
     }
 }
 
-void launch_begin_call(const BandDev& b, double f_tol, hipStream_t s)
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_move(BatchDev bd)
 {
-    k_begin_call<<<1, 1, 0, s>>>(b, f_tol);
+    ItemLoop loop(bd, KIND_ROW, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const BandState* st = b.st;
+        if (!st->move || st->err != 0) continue;
+        const int r = it.tile * CFNEB_TILE + threadIdx.x;
+        if (r >= b.N + 3) continue;
+        const int s0 = st->slot[it.image];
+        double* X = Xs(b, s0);
+        const double* V = Vs(b, st->vcur, s0);
+        const double sc = st->scale, dt = st->dt;
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = size_t(c) * b.ld + r;
+            X[o] += sc * (dt * V[o]);
+        }
+    }
 }
 
-void launch_dots(const BandDev& b, hipStream_t s)
+static unsigned f32_mask(unsigned variants)
 {
-    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
-    if (b.fp64)
-        k_band_dots<double><<<gR, CFNEB_TILE, 0, s>>>(b);
-    else
-        k_band_dots<float><<<gR, CFNEB_TILE, 0, s>>>(b);
+    return variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_TS32));
+}
+static unsigned f64_mask(unsigned variants)
+{
+    return variants & ((1u << VARIANT_LJ64) | (1u << VARIANT_TS64));
 }
 
-void launch_scalars(const BandDev& b, hipStream_t s) { k_band_scalars<<<1, 1024, 0, s>>>(b); }
-
-void launch_update(const BandDev& b, hipStream_t s)
+void launch_begin_call(const Launch& L, double f_tol, int only, hipStream_t s)
 {
-    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
-    if (b.fp64)
-        k_band_update<double><<<gR, CFNEB_TILE, 0, s>>>(b);
-    else
-        k_band_update<float><<<gR, CFNEB_TILE, 0, s>>>(b);
+    k_begin_call<<<1, CFNEB_MAX_BANDS, 0, s>>>(L.bd, f_tol, only);
 }
 
-void launch_finalize(const BandDev& b, hipStream_t s) { k_band_finalize<<<1, 1024, 0, s>>>(b); }
-
-void launch_move(const BandDev& b, hipStream_t s)
+void launch_dots(const Launch& L, hipStream_t s)
 {
-    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
-    k_band_move<<<gR, CFNEB_TILE, 0, s>>>(b);
+    const unsigned g = L.g[KIND_ROW];
+    if (f32_mask(L.variants)) k_band_dots<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, f32_mask(L.variants));
+    if (f64_mask(L.variants)) k_band_dots<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, f64_mask(L.variants));
 }
 
-void launch_band_update(const BandDev& b, hipStream_t s)
+void launch_scalars(const Launch& L, hipStream_t s) { k_band_scalars<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd); }
+
+void launch_update(const Launch& L, hipStream_t s)
 {
-    launch_dots(b, s);
-    launch_scalars(b, s);
-    launch_update(b, s);
-    launch_finalize(b, s);
-    launch_move(b, s);
+    const unsigned g = L.g[KIND_ROW];
+    if (f32_mask(L.variants)) k_band_update<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, f32_mask(L.variants));
+    if (f64_mask(L.variants)) k_band_update<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, f64_mask(L.variants));
 }
+
+void launch_finalize(const Launch& L, hipStream_t s) { k_band_finalize<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd); }
+
+void launch_move(const Launch& L, hipStream_t s) { k_band_move<<<L.g[KIND_ROW], CFNEB_TILE, 0, s>>>(L.bd); }
 
 }  // namespace cfneb

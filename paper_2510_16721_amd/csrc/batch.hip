@@ -1,0 +1,97 @@
+// Work plan of a band table and the order of the kernels of one step.
+//
+// A table holds up to CFNEB_MAX_BANDS bands (a single band is a table of one).  The
+// plan kernel runs first in every step: each thread counts one band's items of every
+// kind (per-atom tiles, per-row tiles, per-image, ...) from its live image count and
+// flags, and the exclusive prefix offsets go to the plan array that every persistent
+// kernel of the step walks.  A converged or failed band contributes no items, so a
+// batch keeps running the bands that are still relaxing.
+#include "cfneb_dev.h"
+
+namespace cfneb {
+
+__global__ void __launch_bounds__(CFNEB_MAX_BANDS) k_plan(BatchDev bd, int all_images, int ignore_stop)
+{
+    __shared__ int cnt[NKIND][CFNEB_MAX_BANDS];
+    const int t = threadIdx.x;
+    if (t < bd.cap) {
+        int c[NKIND];
+        for (int q = 0; q < NKIND; ++q) c[q] = 0;
+        if (bd.live[t]) {
+            const BandDev& b = bd.bands[t];
+            const BandState* st = b.st;
+            if (ignore_stop || !band_stopped(st)) {
+                const int M = st->M;
+                for (int q = 0; q < NKIND; ++q) {
+                    int first;
+                    kind_span(b, q, M, all_images, c[q], first);
+                }
+            }
+        }
+        for (int q = 0; q < NKIND; ++q) cnt[q][t] = c[q];
+    }
+    __syncthreads();
+    if (t < NKIND) {
+        int* off = bd.plan + t * (bd.cap + 1);
+        int run = 0;
+        for (int bi = 0; bi < bd.cap; ++bi) {
+            off[bi] = run;
+            run += cnt[t][bi];
+        }
+        off[bd.cap] = run;
+    }
+}
+
+// Per-band status for the host: done, err, steps of the call, M (4 ints per band).
+__global__ void k_summary(BatchDev bd, int* out)
+{
+    const int t = threadIdx.x;
+    if (t >= bd.cap) return;
+    int* o = out + 4 * t;
+    if (!bd.live[t]) {
+        o[0] = o[1] = o[2] = o[3] = 0;
+        return;
+    }
+    const BandState* st = bd.bands[t].st;
+    o[0] = st->done;
+    o[1] = st->err;
+    o[2] = st->steps_call;
+    o[3] = st->M;
+}
+
+void launch_plan(const Launch& L, int all_images, int ignore_stop, hipStream_t s)
+{
+    k_plan<<<1, CFNEB_MAX_BANDS, 0, s>>>(L.bd, all_images, ignore_stop);
+}
+
+void launch_summary(const Launch& L, int* out, hipStream_t s)
+{
+    k_summary<<<1, CFNEB_MAX_BANDS, 0, s>>>(L.bd, out);
+}
+
+// Energies, forces, virials and generalized forces of the moving images (or of every
+// image): geometry, cell lists, neighbour lists, potential, per-image reduction.
+void launch_evaluate(const Launch& L, int all_images, hipStream_t s)
+{
+    launch_plan(L, all_images, 0, s);
+    launch_geom(L, all_images, s);
+    launch_bins(L, all_images, s);
+    launch_list(L, all_images, s);
+    launch_force_stage(L, all_images, 0, s);
+    launch_force_stage(L, all_images, 1, s);
+    launch_image_reduce(L, all_images, s);
+}
+
+// One band step of every live band.
+void launch_step(const Launch& L, hipStream_t s)
+{
+    launch_evaluate(L, 0, s);
+    launch_dots(L, s);
+    launch_scalars(L, s);
+    launch_update(L, s);
+    launch_finalize(L, s);
+    launch_move(L, s);
+    launch_refine(L, 0, s);
+}
+
+}  // namespace cfneb

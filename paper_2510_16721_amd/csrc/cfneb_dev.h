@@ -157,45 +157,148 @@ __device__ inline bool image_active(const BandState* st, int k, int all_images)
 
 __device__ inline bool band_stopped(const BandState* st) { return st->done != 0 || st->err != 0; }
 
-// XCD-aware work mapping.  Workgroups of a launch go to the 8 XCDs round-robin by
-// linear id, and each XCD has its own L2.  A launch over (tile, image) items uses a
-// 1-D grid of cfneb_grid(ntiles, Mcap) blocks; block W serves item
-//     L = (W % 8) * chunk + W / 8,   chunk = ceil(nact * ntiles / 8),
-// over the nact images active now (first = first active image), so every XCD walks
-// one contiguous run of tiles of one image at a time and all 8 XCDs get equal work
-// whatever the current image count.  Blocks past the work exit at once.
+// ---------------------------------------------------------------- work plan
+// Every kernel of a step is persistent: a fixed grid walks a work plan of items
+// over all bands of a batch (a single band is a batch of one).  The plan kernel,
+// launched first, counts each band's items of every kind from the band's live
+// image count and flags and stores exclusive prefix offsets; a block maps its
+// linear item L to (band, tile, image) by binary search over the offsets.  Bands
+// of any size share one launch per phase, and the grid (captured once in a graph)
+// does not depend on how many bands or images are live.
+//
+// XCD awareness: workgroups go to the 8 XCDs round-robin by linear id and each XCD
+// has its own L2.  Block W serves items (W % 8) * chunk + W / 8 + n * (G / 8),
+// chunk = ceil(total / 8), so every XCD walks one contiguous run of items (tiles of
+// one image of one band at a time) and the XCDs get equal shares.
 #define CFNEB_XCDS 8
-struct WorkItem {
-    int tile, image;
-    bool valid;
+#define CFNEB_MAX_BANDS 128
+
+enum ItemKind {
+    KIND_ATOM = 0,  // 256-atom tiles x images
+    KIND_ROW,       // 256-row tiles (N + 3 rows) x images
+    KIND_BIN,       // 256-bin tiles x images
+    KIND_IMAGE,     // one item per image
+    KIND_IVAL,      // 256-row tiles x intervals between consecutive images
+    KIND_SLOTROW,   // 256-row tiles x every image slot of the capacity
+    KIND_BAND,      // one item per band
+    NKIND
 };
 
-__device__ inline WorkItem xcd_item(int ntiles, int first, int nact)
+struct BatchDev {
+    const BandDev* bands;  // [cap] band table
+    const int* live;       // [cap] 1 where the table holds a band
+    int* plan;             // [NKIND][cap + 1] exclusive prefix offsets
+    int cap;
+};
+
+struct Item {
+    int band, tile, image;
+};
+
+__device__ inline int kind_tiles(const BandDev& b, int kind)
 {
-    WorkItem w;
-    const int W = int(blockIdx.x);
-    const int chunk = (nact * ntiles + CFNEB_XCDS - 1) / CFNEB_XCDS;
-    const int idx = W / CFNEB_XCDS;
-    const int L = (W % CFNEB_XCDS) * chunk + idx;
-    w.valid = nact > 0 && idx < chunk && L < nact * ntiles;
-    w.tile = w.valid ? L % ntiles : 0;
-    w.image = w.valid ? first + L / ntiles : 0;
-    return w;
+    switch (kind) {
+    case KIND_ATOM: return b.ntA;
+    case KIND_BIN: return (b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE;
+    case KIND_ROW:
+    case KIND_IVAL:
+    case KIND_SLOTROW: return b.ntR;
+    default: return 1;
+    }
 }
 
-// (tile, image) item of a per-atom or per-row launch over the images of a step
-// (moving images) or of an evaluation of every image.
-__device__ inline WorkItem image_item(const BandState* st, int ntiles, int all_images)
+// Items of one band: images of a step (the moving ones) or of an evaluation of every
+// image; first image index of the walk.
+__device__ inline void kind_span(const BandDev& b, int kind, int M, int all_images, int& count, int& first)
 {
-    const int M = st->M;
-    return all_images ? xcd_item(ntiles, 0, M) : xcd_item(ntiles, 1, M - 2);
+    const int nimg = all_images ? M : M - 2;
+    first = all_images ? 0 : 1;
+    switch (kind) {
+    case KIND_IVAL:
+        count = kind_tiles(b, kind) * (M - 1);
+        first = 0;
+        break;
+    case KIND_SLOTROW:
+        count = kind_tiles(b, kind) * b.Mcap;
+        first = 0;
+        break;
+    case KIND_BAND:
+        count = 1;
+        first = 0;
+        break;
+    default: count = kind_tiles(b, kind) * (nimg > 0 ? nimg : 0); break;
+    }
 }
 
-__host__ __device__ inline unsigned cfneb_grid(int ntiles, int nimages)
+// Persistent, XCD-ordered walk over the items of one kind.
+struct ItemLoop {
+    const BatchDev* bd;
+    int kind, total, chunk, xcd, j, per, n, first_mode;
+    __device__ ItemLoop(const BatchDev& b, int k, int all_images)
+        : bd(&b), kind(k), n(0), first_mode(all_images)
+    {
+        total = b.plan[k * (b.cap + 1) + b.cap];
+        per = int(gridDim.x) / CFNEB_XCDS;
+        xcd = int(blockIdx.x) % CFNEB_XCDS;
+        j = int(blockIdx.x) / CFNEB_XCDS;
+        chunk = (total + CFNEB_XCDS - 1) / CFNEB_XCDS;
+    }
+    __device__ bool next(Item& it)
+    {
+        const int idx = j + n * per;
+        ++n;
+        if (idx >= chunk) return false;
+        const int L = xcd * chunk + idx;
+        if (L >= total) return false;
+        const int* off = bd->plan + kind * (bd->cap + 1);
+        int lo = 0, hi = bd->cap;  // off[lo] <= L < off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= L)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BandDev& b = bd->bands[lo];
+        int count, first;
+        kind_span(b, kind, b.st->M, first_mode, count, first);
+        const int local = L - off[lo];
+        const int nt = kind_tiles(b, kind);
+        it.band = lo;
+        it.tile = local % nt;
+        it.image = first + local / nt;
+        return true;
+    }
+};
+
+// Grid sizes of the persistent launches (multiples of 8).
+#define CFNEB_GRID_TILES 2048
+#define CFNEB_GRID_IMAGES 512
+#define CFNEB_GRID_BANDS CFNEB_MAX_BANDS
+
+__host__ __device__ inline unsigned grid_for(long long max_items, unsigned cap)
 {
-    const long long t = (long long)ntiles * nimages;
-    return unsigned((t + CFNEB_XCDS - 1) / CFNEB_XCDS * CFNEB_XCDS);
+    long long g = (max_items + CFNEB_XCDS - 1) / CFNEB_XCDS * CFNEB_XCDS;
+    if (g < CFNEB_XCDS) g = CFNEB_XCDS;
+    return unsigned(g < cap ? g : cap);
 }
+
+// Kernel variants by potential and force precision; a launch serves the bands of
+// the variants it is instantiated for and skips the others.
+enum { VARIANT_LJ32 = 0, VARIANT_LJ64, VARIANT_TS32, VARIANT_TS64, NVARIANT };
+
+__host__ __device__ inline int band_variant(const BandDev& b)
+{
+    return (b.potential == CFNEB_TERSOFF_C ? 2 : 0) + (b.fp64 ? 1 : 0);
+}
+
+// Launch geometry of one batch: the grid of each kind, bounded by the most items
+// the table can ever hold, and the variants present.
+struct Launch {
+    BatchDev bd;
+    unsigned g[NKIND];
+    unsigned variants;
+};
 
 __device__ inline void set_error(BandState* st, int code)
 {
@@ -284,29 +387,30 @@ __host__ __device__ inline void mm3(const double* a, const double* b, double* c)
 
 // ---------------------------------------------------------------- launchers
 // Defined in the kernel translation units, called by the host runtime.
+// One band, direct launches (construction and readout helpers):
 void launch_init_endpoints(const BandDev& b, hipStream_t s);
 void launch_init_images(const BandDev& b, int M, hipStream_t s);
 void launch_init_state(const BandDev& b, int M, hipStream_t s);
-void launch_begin_call(const BandDev& b, double f_tol, hipStream_t s);
-void launch_geom(const BandDev& b, int all_images, hipStream_t s);
-void launch_nlist(const BandDev& b, int all_images, hipStream_t s);
-void launch_forces(const BandDev& b, int all_images, hipStream_t s);
-void launch_bins(const BandDev& b, int all_images, hipStream_t s);
-void launch_list(const BandDev& b, int all_images, hipStream_t s);
-void launch_force_stage(const BandDev& b, int all_images, int stage, hipStream_t s);
-void launch_image_reduce(const BandDev& b, int all_images, hipStream_t s);
-void launch_tersoff_stage(const BandDev& b, int all_images, int stage, hipStream_t s);
-void launch_dots(const BandDev& b, hipStream_t s);
-void launch_scalars(const BandDev& b, hipStream_t s);
-void launch_update(const BandDev& b, hipStream_t s);
-void launch_finalize(const BandDev& b, hipStream_t s);
-void launch_move(const BandDev& b, hipStream_t s);
-void launch_evaluate(const BandDev& b, int all_images, hipStream_t s);
-void launch_band_update(const BandDev& b, hipStream_t s);
-void launch_refine(const BandDev& b, int forced, hipStream_t s);
-void launch_readout(const BandDev& b, hipStream_t s);
 void launch_image_positions(const BandDev& b, int k, hipStream_t s);
-void launch_set_state_fixup(const BandDev& b, int M, hipStream_t s);
+// Persistent launches over every live band of a table:
+void launch_plan(const Launch& L, int all_images, int ignore_stop, hipStream_t s);
+void launch_begin_call(const Launch& L, double f_tol, int only, hipStream_t s);
+void launch_geom(const Launch& L, int all_images, hipStream_t s);
+void launch_bins(const Launch& L, int all_images, hipStream_t s);
+void launch_list(const Launch& L, int all_images, hipStream_t s);
+void launch_force_stage(const Launch& L, int all_images, int stage, hipStream_t s);
+void launch_tersoff_stage(const Launch& L, int all_images, int stage, hipStream_t s);
+void launch_image_reduce(const Launch& L, int all_images, hipStream_t s);
+void launch_dots(const Launch& L, hipStream_t s);
+void launch_scalars(const Launch& L, hipStream_t s);
+void launch_update(const Launch& L, hipStream_t s);
+void launch_finalize(const Launch& L, hipStream_t s);
+void launch_move(const Launch& L, hipStream_t s);
+void launch_refine(const Launch& L, int forced, hipStream_t s);
+void launch_readout(const Launch& L, hipStream_t s);
+void launch_evaluate(const Launch& L, int all_images, hipStream_t s);
+void launch_step(const Launch& L, hipStream_t s);
+void launch_summary(const Launch& L, int* out, hipStream_t s);
 
 }  // namespace cfneb
 

@@ -5,7 +5,6 @@
 // pair force of Eq. (5) in the index order of the derivation leading to Eq. (6)),
 // and the virial is V_mn = -sum_ij r^ij_m P_ij,n = -1/2 sum_ij r^ij_m f^ij_n
 // (Eqs. (6)-(8)).  Lists are full, so every force is a gather: no atomics.
-//
 // Lennard-Jones lives here; the Tersoff kernels are in tersoff.hip.
 //
 // Precision: bond vectors are formed in FP64 from FP64 positions, then the pair and
@@ -21,16 +20,9 @@ namespace cfneb {
 // ------------------------------------------------------------ Lennard-Jones
 // U_i = 1/2 sum_j phi(r_ij), phi = 4 eps [(s/r)^12 - (s/r)^6] - phi(rc)
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_lj(BandDev b, int all_images)
+__device__ void lj_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
 {
-    __shared__ double lds[4 * 10];
-    BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntA, all_images);
-    if (!w.valid) return;
-    const int k = w.image;
-    const int i = w.tile * CFNEB_TILE + threadIdx.x;
-    const int slot = st->slot[k];
+    const int i = tile * CFNEB_TILE + threadIdx.x;
     const size_t N = b.N;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // u, then V row-major
     if (i < b.N) {
@@ -82,21 +74,30 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj(BandDev b, int all_images)
     }
     block_sum<10>(acc, lds);
     if (threadIdx.x == 0) {
-        double* out = b.evpart + (size_t(slot) * b.ntA + w.tile) * 10;
+        double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
         for (int q = 0; q < 10; ++q) out[q] = acc[q];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_lj(BatchDev bd, int all_images, int variant)
+{
+    __shared__ double lds[4 * 10];
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        if (band_variant(b) != variant || band_stopped(st)) continue;  // uniform over the block
+        lj_item<T>(b, st, st->slot[it.image], it.tile, lds);
     }
 }
 
 // ------------------------------------------------------------ per-image reduction
 // E and V in a fixed order; enthalpy and the rotation-free lattice force
 // G = D^-T (V - P Omega I) D^-1 / c_f (Eqs. (16)-(17)).
-__global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BandDev b, int all_images)
+__device__ void image_reduce_item(const BandDev& b, BandState* st, int slot, double* lds)
 {
-    __shared__ double lds[4 * 10];
-    BandState* st = b.st;
-    const int k = blockIdx.x;
-    if (band_stopped(st) || !image_active(st, k, all_images)) return;
-    const int slot = st->slot[k];
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const double* part = b.evpart + size_t(slot) * b.ntA * 10;
     for (int t = threadIdx.x; t < b.ntA; t += CFNEB_TILE)
@@ -125,37 +126,33 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BandDev b, int all_
     if (!finite) set_error(st, CFNEB_ENONFINITE);
 }
 
-// stage 0: LJ, or Tersoff bond orders and dU_i/dr^ij; 1: Tersoff gather; 2: unused
-void launch_force_stage(const BandDev& b, int all_images, int stage, hipStream_t s)
+__global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BatchDev bd, int all_images)
 {
-    const unsigned gA = cfneb_grid(b.ntA, b.Mcap);
-    if (b.potential == CFNEB_LJ) {
-        if (stage != 0) return;
-        if (b.fp64)
-            k_lj<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-        else
-            k_lj<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-        return;
+    __shared__ double lds[4 * 10];
+    ItemLoop loop(bd, KIND_IMAGE, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        if (band_stopped(st)) continue;  // uniform over the block
+        image_reduce_item(b, st, st->slot[it.image], lds);
     }
-    launch_tersoff_stage(b, all_images, stage, s);
 }
 
-void launch_image_reduce(const BandDev& b, int all_images, hipStream_t s)
+// stage 0: LJ, or Tersoff bond orders and dU_i/dr^ij; 1: Tersoff gather
+void launch_force_stage(const Launch& L, int all_images, int stage, hipStream_t s)
 {
-    k_image_reduce<<<b.Mcap, CFNEB_TILE, 0, s>>>(b, all_images);
+    const unsigned g = L.g[KIND_ATOM];
+    if (stage == 0) {
+        if (L.variants & (1u << VARIANT_LJ32)) k_lj<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ32);
+        if (L.variants & (1u << VARIANT_LJ64)) k_lj<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ64);
+    }
+    launch_tersoff_stage(L, all_images, stage, s);
 }
 
-void launch_forces(const BandDev& b, int all_images, hipStream_t s)
+void launch_image_reduce(const Launch& L, int all_images, hipStream_t s)
 {
-    for (int stage = 0; stage < 3; ++stage) launch_force_stage(b, all_images, stage, s);
-    launch_image_reduce(b, all_images, s);
-}
-
-void launch_evaluate(const BandDev& b, int all_images, hipStream_t s)
-{
-    launch_geom(b, all_images, s);
-    launch_nlist(b, all_images, s);
-    launch_forces(b, all_images, s);
+    k_image_reduce<<<L.g[KIND_IMAGE], CFNEB_TILE, 0, s>>>(L.bd, all_images);
 }
 
 }  // namespace cfneb

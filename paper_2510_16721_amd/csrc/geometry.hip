@@ -103,19 +103,25 @@ __device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
     return true;
 }
 
-__global__ void k_geom(BandDev b, int all_images)
+// One block per band, one thread per image.
+__global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_geom(BatchDev bd, int all_images)
 {
-    BandState* st = b.st;
-    const int k = threadIdx.x;
-    if (band_stopped(st) || k >= b.Mcap || !image_active(st, k, all_images)) return;
-    const int slot = st->slot[k];
-    ImageGeom g;
-    g.err = 0;
-    if (!image_geometry(b, Xs(b, slot), g)) {
-        g.err = 1;
-        set_error(st, CFNEB_ECELL);
+    ItemLoop loop(bd, KIND_BAND, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        const int k = threadIdx.x;
+        if (band_stopped(st) || k >= b.Mcap || !image_active(st, k, all_images)) continue;
+        const int slot = st->slot[k];
+        ImageGeom g;
+        g.err = 0;
+        if (!image_geometry(b, Xs(b, slot), g)) {
+            g.err = 1;
+            set_error(st, CFNEB_ECELL);
+        }
+        b.geom[slot] = g;
     }
-    b.geom[slot] = g;
 }
 
 // ---------------------------------------------------------------- construction
@@ -232,17 +238,6 @@ __global__ void k_image_positions(BandDev b, int k)
     for (int c = 0; c < 3; ++c) b.staging[3 * size_t(i) + c] = x * D[c] + y * D[3 + c] + z * D[6 + c];
 }
 
-// After a checkpoint restore: the slot table is the identity and v is taken as given.
-__global__ void k_set_state_fixup(BandDev b, int M)
-{
-    BandState* st = b.st;
-    st->M = M;
-    for (int k = 0; k < CFNEB_MAX_IMAGES; ++k) st->slot[k] = (k < b.Mcap) ? k : 0;
-    st->vcur = 0;
-    st->done = 0;
-    st->err = 0;
-}
-
 void launch_init_endpoints(const BandDev& b, hipStream_t s) { k_init_endpoints<<<1, 1, 0, s>>>(b); }
 
 void launch_init_images(const BandDev& b, int M, hipStream_t s)
@@ -253,20 +248,15 @@ void launch_init_images(const BandDev& b, int M, hipStream_t s)
 
 void launch_init_state(const BandDev& b, int M, hipStream_t s) { k_init_state<<<1, 1, 0, s>>>(b, M); }
 
-void launch_geom(const BandDev& b, int all_images, hipStream_t s)
+void launch_geom(const Launch& L, int all_images, hipStream_t s)
 {
-    k_geom<<<1, CFNEB_MAX_IMAGES, 0, s>>>(b, all_images);
+    k_geom<<<L.g[KIND_BAND], CFNEB_MAX_IMAGES, 0, s>>>(L.bd, all_images);
 }
 
 void launch_image_positions(const BandDev& b, int k, hipStream_t s)
 {
     k_image_geom_one<<<1, 1, 0, s>>>(b, k);
     k_image_positions<<<(b.N + CFNEB_TILE - 1) / CFNEB_TILE, CFNEB_TILE, 0, s>>>(b, k);
-}
-
-void launch_set_state_fixup(const BandDev& b, int M, hipStream_t s)
-{
-    k_set_state_fixup<<<1, 1, 0, s>>>(b, M);
 }
 
 }  // namespace cfneb

@@ -6,7 +6,7 @@
 // unwrapped positions R = R~ D.  Bins only generate candidates, so the set does not
 // depend on the binning.  This is the local environment of Sec. II.B, Eq. (4).
 //
-// Kernels, in order, one grid row per image:
+// Kernels, in order (each a persistent walk over the items of every live band):
 //   k_bin_assign   R = R~ D, wrapped fractional coordinate, bin id; the count atomic
 //                  returns the atom's rank inside its bin
 //   k_bin_scan     exclusive prefix sum of the bin counts (one block per image,
@@ -31,15 +31,8 @@ __device__ inline long long pack_info(int j, int n0, int n1, int n2)
 __device__ inline int info_j(long long v) { return int(v & 0xFFFFF); }
 __device__ inline int info_n(long long v, int k) { return int((v >> (20 + 10 * k)) & 0x3FF) - 512; }
 
-__global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BandDev b, int all_images)
+__device__ void bin_assign_item(const BandDev& b, int slot, int i)
 {
-    const BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntA, all_images);
-    const int k = w.image;
-    const int i = w.tile * CFNEB_TILE + threadIdx.x;
-    if (!w.valid || i >= b.N) return;
-    const int slot = st->slot[k];
     const ImageGeom& g = b.geom[slot];
     const double* X = Xs(b, slot);
     const double x = X[i], y = X[b.ld + i], z = X[2 * size_t(b.ld) + i];
@@ -66,15 +59,24 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BandDev b, int all_im
     b.binfo[size_t(slot) * b.N + i] = make_int4(bin, rank, packed, 0);
 }
 
-// Exclusive scan of the counts, 4 per thread and 4096 per pass, carried across passes.
-__global__ void __launch_bounds__(1024) k_bin_scan(BandDev b, int all_images)
+__global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BatchDev bd, int all_images)
+{
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const BandState* st = b.st;
+        const int i = it.tile * CFNEB_TILE + threadIdx.x;
+        if (band_stopped(st) || i >= b.N) continue;
+        bin_assign_item(b, st->slot[it.image], i);
+    }
+}
+
+// Exclusive scan of one image's counts, 4 per thread and 4096 per pass.
+__device__ void bin_scan_item(const BandDev& b, int slot)
 {
     __shared__ int wsum[16];
     __shared__ int carry_s;
-    const BandState* st = b.st;
-    const int k = blockIdx.x;
-    if (band_stopped(st) || !image_active(st, k, all_images)) return;
-    const int slot = st->slot[k];
     const int nbins = b.geom[slot].nbins;
     int* cnt = b.bcount + bin_base(b, slot);
     int* start = b.bstart + bin_base(b, slot);
@@ -115,53 +117,66 @@ __global__ void __launch_bounds__(1024) k_bin_scan(BandDev b, int all_images)
     if (t == 0) start[nbins] = carry;
 }
 
-__global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BandDev b, int all_images)
+__global__ void __launch_bounds__(1024) k_bin_scan(BatchDev bd, int all_images)
 {
-    const BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntA, all_images);
-    const int k = w.image;
-    const int i = w.tile * CFNEB_TILE + threadIdx.x;
-    if (!w.valid || i >= b.N) return;
-    const int slot = st->slot[k];
-    const int4 bi = b.binfo[size_t(slot) * b.N + i];
-    const int pos = b.bstart[bin_base(b, slot) + bi.x] + bi.y;
-    if (pos < 0 || pos >= b.N) return;
-    const double* R = Rs(b, slot);
-    BinAtom a;
-    a.x = R[i];
-    a.y = R[b.ld + i];
-    a.z = R[2 * size_t(b.ld) + i];
-    a.info = pack_info(i, (bi.z & 0x3FF) - 512, ((bi.z >> 10) & 0x3FF) - 512, ((bi.z >> 20) & 0x3FF) - 512);
-    b.bpos[size_t(slot) * b.N + pos] = a;
-}
-
-__global__ void __launch_bounds__(CFNEB_TILE) k_bin_sort(BandDev b, int all_images)
-{
-    const BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, (b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE, all_images);
-    const int k = w.image;
-    const int bin = w.tile * CFNEB_TILE + threadIdx.x;
-    if (!w.valid) return;
-    const int slot = st->slot[k];
-    if (bin >= b.geom[slot].nbins) return;
-    const int* start = b.bstart + bin_base(b, slot);
-    BinAtom* a = b.bpos + size_t(slot) * b.N;
-    const int lo = start[bin], hi = min(start[bin + 1], b.N);
-    for (int p = lo + 1; p < hi; ++p) {
-        const BinAtom v = a[p];
-        const int key = info_j(v.info);
-        int q = p - 1;
-        while (q >= lo && info_j(a[q].info) > key) {
-            a[q + 1] = a[q];
-            --q;
-        }
-        a[q + 1] = v;
+    ItemLoop loop(bd, KIND_IMAGE, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (band_stopped(b.st)) continue;  // uniform over the block
+        bin_scan_item(b, b.st->slot[it.image]);
     }
 }
 
-__device__ inline int floordiv_i(int a, int m) { return (a >= 0) ? a / m : -((-a + m - 1) / m); }
+__global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BatchDev bd, int all_images)
+{
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const BandState* st = b.st;
+        const int i = it.tile * CFNEB_TILE + threadIdx.x;
+        if (band_stopped(st) || i >= b.N) continue;
+        const int slot = st->slot[it.image];
+        const int4 bi = b.binfo[size_t(slot) * b.N + i];
+        const int pos = b.bstart[bin_base(b, slot) + bi.x] + bi.y;
+        if (pos < 0 || pos >= b.N) continue;
+        const double* R = Rs(b, slot);
+        BinAtom a;
+        a.x = R[i];
+        a.y = R[b.ld + i];
+        a.z = R[2 * size_t(b.ld) + i];
+        a.info = pack_info(i, (bi.z & 0x3FF) - 512, ((bi.z >> 10) & 0x3FF) - 512, ((bi.z >> 20) & 0x3FF) - 512);
+        b.bpos[size_t(slot) * b.N + pos] = a;
+    }
+}
+
+__global__ void __launch_bounds__(CFNEB_TILE) k_bin_sort(BatchDev bd, int all_images)
+{
+    ItemLoop loop(bd, KIND_BIN, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const BandState* st = b.st;
+        const int bin = it.tile * CFNEB_TILE + threadIdx.x;
+        if (band_stopped(st)) continue;
+        const int slot = st->slot[it.image];
+        if (bin >= b.geom[slot].nbins) continue;
+        const int* start = b.bstart + bin_base(b, slot);
+        BinAtom* a = b.bpos + size_t(slot) * b.N;
+        const int lo = start[bin], hi = min(start[bin + 1], b.N);
+        for (int p = lo + 1; p < hi; ++p) {
+            const BinAtom v = a[p];
+            const int key = info_j(v.info);
+            int q = p - 1;
+            while (q >= lo && info_j(a[q].info) > key) {
+                a[q + 1] = a[q];
+                --q;
+            }
+            a[q + 1] = v;
+        }
+    }
+}
 
 // Exact squared distance of entry (j, n); every operation rounded separately.
 __device__ inline double exact_r2(const double* ri, double xj, double yj, double zj, const double* h,
@@ -176,16 +191,24 @@ __device__ inline double exact_r2(const double* ri, double xj, double yj, double
     return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
 }
 
-template <typename T, bool STORE_BONDS>
-__global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
+__device__ inline void wrap_bin(int v, int nb, int& a, int& m)
 {
-    BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntA, all_images);
-    const int k = w.image;
-    const int i = w.tile * CFNEB_TILE + threadIdx.x;
-    if (!w.valid || i >= b.N) return;
-    const int slot = st->slot[k];
+    // periodic wrap without division (the stencil reach is small)
+    a = v;
+    m = 0;
+    while (a < 0) {
+        a += nb;
+        --m;
+    }
+    while (a >= nb) {
+        a -= nb;
+        ++m;
+    }
+}
+
+template <typename T, bool STORE_BONDS>
+__device__ void nlist_item(const BandDev& b, BandState* st, int slot, int i)
+{
     const ImageGeom& g = b.geom[slot];
     const double* R = Rs(b, slot);
     const int* start = b.bstart + bin_base(b, slot);
@@ -206,14 +229,28 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
     int cnt = 0;
     bool bad_shift = false;
     for (int dx = -r0; dx <= r0; ++dx) {
-        const int v0 = b0 + dx, m0 = floordiv_i(v0, nb0), a0 = v0 - m0 * nb0;
+        int a0, m0;
+        wrap_bin(b0 + dx, nb0, a0, m0);
         for (int dy = -r1; dy <= r1; ++dy) {
-            const int v1 = b1 + dy, m1 = floordiv_i(v1, nb1), a1 = v1 - m1 * nb1;
+            int a1, m1;
+            wrap_bin(b1 + dy, nb1, a1, m1);
             const int row = (a0 * nb1 + a1) * nb2;
-            for (int dz = -r2; dz <= r2; ++dz) {
-                const int v2 = b2 + dz, m2 = floordiv_i(v2, nb2), a2 = v2 - m2 * nb2;
-                const int bin = row + a2;
-                const int lo = start[bin], hi = min(start[bin + 1], b.N);
+            // The z bins b2-r2 .. b2+r2 of a row are one contiguous run of records
+            // unless the stencil wraps; then each bin is its own segment.
+            const bool flat = (b2 - r2 >= 0) && (b2 + r2 < nb2);
+            const int nseg = flat ? 1 : 2 * r2 + 1;
+            for (int sgi = 0; sgi < nseg; ++sgi) {
+                int lo, hi, m2 = 0;
+                if (flat) {
+                    lo = start[row + b2 - r2];
+                    hi = start[row + b2 + r2 + 1];
+                } else {
+                    int a2;
+                    wrap_bin(b2 - r2 + sgi, nb2, a2, m2);
+                    lo = start[row + a2];
+                    hi = start[row + a2 + 1];
+                }
+                hi = min(hi, b.N);
                 for (int p = lo; p < hi; ++p) {
                     const BinAtom a = bp[p];
                     const int j = info_j(a.info);
@@ -249,33 +286,39 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BandDev b, int all_images)
     if (cnt > b.cap) set_error(st, CFNEB_ENEIGH);
 }
 
-void launch_bins(const BandDev& b, int all_images, hipStream_t s)
+// vmask: the band variants (potential, force precision) this launch serves
+template <typename T, bool STORE_BONDS>
+__global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BatchDev bd, int all_images, unsigned vmask)
 {
-    const unsigned gA = cfneb_grid(b.ntA, b.Mcap);
-    k_bin_assign<<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-    k_bin_scan<<<b.Mcap, 1024, 0, s>>>(b, all_images);
-    k_bin_scatter<<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-    const unsigned gB = cfneb_grid((b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE, b.Mcap);
-    k_bin_sort<<<gB, CFNEB_TILE, 0, s>>>(b, all_images);
-}
-
-void launch_list(const BandDev& b, int all_images, hipStream_t s)
-{
-    const unsigned gA = cfneb_grid(b.ntA, b.Mcap);
-    if (b.potential == CFNEB_TERSOFF_C) {
-        if (b.fp64)
-            k_nlist<double, true><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-        else
-            k_nlist<float, true><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-    } else {
-        k_nlist<double, false><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (!((vmask >> band_variant(b)) & 1u)) continue;
+        BandState* st = b.st;
+        const int i = it.tile * CFNEB_TILE + threadIdx.x;
+        if (band_stopped(st) || i >= b.N) continue;
+        nlist_item<T, STORE_BONDS>(b, st, st->slot[it.image], i);
     }
 }
 
-void launch_nlist(const BandDev& b, int all_images, hipStream_t s)
+void launch_bins(const Launch& L, int all_images, hipStream_t s)
 {
-    launch_bins(b, all_images, s);
-    launch_list(b, all_images, s);
+    k_bin_assign<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, all_images);
+    k_bin_scan<<<L.g[KIND_IMAGE], 1024, 0, s>>>(L.bd, all_images);
+    k_bin_scatter<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, all_images);
+    k_bin_sort<<<L.g[KIND_BIN], CFNEB_TILE, 0, s>>>(L.bd, all_images);
+}
+
+void launch_list(const Launch& L, int all_images, hipStream_t s)
+{
+    const unsigned g = L.g[KIND_ATOM];
+    const unsigned lj = L.variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_LJ64));
+    if (lj) k_nlist<double, false><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj);
+    if (L.variants & (1u << VARIANT_TS32))
+        k_nlist<float, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS32);
+    if (L.variants & (1u << VARIANT_TS64))
+        k_nlist<double, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS64);
 }
 
 }  // namespace cfneb

@@ -117,17 +117,12 @@ __device__ inline U128 wave_sum128(U128 v)
     return v;
 }
 
-// mode 0: only when the step set refine_due; mode 1: always (readout / explicit call)
-__global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BandDev b, int mode)
+// Exact squared spacing of one 256-row tile of interval k (images k, k+1).
+__device__ void dist_item(const BandDev& b, BandState* st, int k, int tile)
 {
     __shared__ U128 lds[4];
     __shared__ int bad[4];
-    BandState* st = b.st;
-    if (mode == 0 && (band_stopped(st) || !st->refine_due)) return;
-    const WorkItem w = xcd_item(b.ntR, 0, st->M - 1);
-    if (!w.valid) return;
-    const int k = w.image;  // interval k: images k, k+1
-    const int r = w.tile * CFNEB_TILE + threadIdx.x;
+    const int r = tile * CFNEB_TILE + threadIdx.x;
     U128 acc = {0, 0};
     int ok = 1;
     if (r < b.N + 3) {
@@ -155,19 +150,31 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BandDev b, int mode)
         add128(s, lds[1]);
         add128(s, lds[2]);
         add128(s, lds[3]);
-        uint64_t* out = b.refpart + (size_t(k) * b.ntR + w.tile) * 2;
+        uint64_t* out = b.refpart + (size_t(k) * b.ntR + tile) * 2;
         out[0] = s.lo;
         out[1] = s.hi;
         if (!(bad[0] && bad[1] && bad[2] && bad[3])) set_error(st, CFNEB_ERANGE);
     }
+    __syncthreads();
+}
+
+// mode 0: only when the step set refine_due; mode 1: always (readout / explicit call)
+__global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BatchDev bd, int mode)
+{
+    ItemLoop loop(bd, KIND_IVAL, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        if (mode == 0 && (band_stopped(st) || !st->refine_due)) continue;  // uniform
+        dist_item(b, st, it.image, it.tile);
+    }
 }
 
 // mode 0 / 1: decide and apply to the slot table; mode 2: spacings only (readout).
-__global__ void __launch_bounds__(64) k_refine_decide(BandDev b, int mode)
+__device__ void decide_item(const BandDev& b, BandState* st, int mode)
 {
     __shared__ U128 d2[CFNEB_MAX_IMAGES];
-    BandState* st = b.st;
-    if (mode == 0 && (band_stopped(st) || !st->refine_due)) return;
     const int M = st->M;
     const int t = threadIdx.x;
     if (t < M - 1) {
@@ -181,139 +188,170 @@ __global__ void __launch_bounds__(64) k_refine_decide(BandDev b, int mode)
         st->d2[t] = double(s.hi) + double(s.lo) * 5.421010862427522e-20;  // 2^-64
     }
     __syncthreads();
-    if (t != 0 || mode == 2) return;
-    st->ins = -1;
-    st->del = -1;
-    st->changed = 0;
-    if (st->err != 0) return;
-    U256 total = {{0, 0, 0, 0}};
-    int kstar = 0;
-    for (int k = 0; k < M - 1; ++k) {
-        total = add256(total, widen(d2[k]));
-        if (less128(d2[kstar], d2[k])) kstar = k;
-    }
-    if (M < b.max_images && M < b.Mcap) {
-        const U256 lhs = mul256_small(widen(d2[kstar]), uint32_t(b.ins_den) * uint32_t(M - 1));
-        const U256 rhs = mul256_small(total, uint32_t(b.ins_num));
-        if (cmp256(lhs, rhs) > 0) {
-            bool used[CFNEB_MAX_IMAGES];
-            for (int q = 0; q < CFNEB_MAX_IMAGES; ++q) used[q] = false;
-            for (int q = 0; q < M; ++q) used[st->slot[q]] = true;
-            int fresh = 0;
-            while (fresh < b.Mcap && used[fresh]) ++fresh;
-            const int a = st->slot[kstar], c = st->slot[kstar + 1];
-            for (int q = M; q > kstar + 1; --q) st->slot[q] = st->slot[q - 1];
-            st->slot[kstar + 1] = fresh;
-            st->M = M + 1;
-            st->new_slot = fresh;
-            st->ins_a = a;
-            st->ins_b = c;
-            st->ins = kstar + 1;
-            st->changed = 1;
-            // until it is evaluated, the new image reports its neighbours' mean
-            b.scal[fresh].H = 0.5 * (b.scal[a].H + b.scal[c].H);
-            b.scal[fresh].E = 0.5 * (b.scal[a].E + b.scal[c].E);
-        }
-    }
-    if (!st->changed && M > b.min_images) {
-        int jstar = -1;
-        U128 best = {0, 0};
-        for (int j = 1; j <= M - 2; ++j) {
-            if (j == st->ci) continue;
-            const U128 m = less128(d2[j - 1], d2[j]) ? d2[j] : d2[j - 1];
-            if (jstar < 0 || less128(m, best)) {
-                jstar = j;
-                best = m;
+    if (t == 0 && mode != 2) {
+        st->ins = -1;
+        st->del = -1;
+        st->changed = 0;
+        if (st->err == 0) {
+            U256 total = {{0, 0, 0, 0}};
+            int kstar = 0;
+            for (int k = 0; k < M - 1; ++k) {
+                total = add256(total, widen(d2[k]));
+                if (less128(d2[kstar], d2[k])) kstar = k;
+            }
+            if (M < b.max_images && M < b.Mcap) {
+                const U256 lhs = mul256_small(widen(d2[kstar]), uint32_t(b.ins_den) * uint32_t(M - 1));
+                const U256 rhs = mul256_small(total, uint32_t(b.ins_num));
+                if (cmp256(lhs, rhs) > 0) {
+                    bool used[CFNEB_MAX_IMAGES];
+                    for (int q = 0; q < CFNEB_MAX_IMAGES; ++q) used[q] = false;
+                    for (int q = 0; q < M; ++q) used[st->slot[q]] = true;
+                    int fresh = 0;
+                    while (fresh < b.Mcap && used[fresh]) ++fresh;
+                    const int a = st->slot[kstar], c = st->slot[kstar + 1];
+                    for (int q = M; q > kstar + 1; --q) st->slot[q] = st->slot[q - 1];
+                    st->slot[kstar + 1] = fresh;
+                    st->M = M + 1;
+                    st->new_slot = fresh;
+                    st->ins_a = a;
+                    st->ins_b = c;
+                    st->ins = kstar + 1;
+                    st->changed = 1;
+                    // until it is evaluated, the new image reports its neighbours' mean
+                    b.scal[fresh].H = 0.5 * (b.scal[a].H + b.scal[c].H);
+                    b.scal[fresh].E = 0.5 * (b.scal[a].E + b.scal[c].E);
+                }
+            }
+            if (!st->changed && M > b.min_images) {
+                int jstar = -1;
+                U128 best = {0, 0};
+                for (int j = 1; j <= M - 2; ++j) {
+                    if (j == st->ci) continue;
+                    const U128 m = less128(d2[j - 1], d2[j]) ? d2[j] : d2[j - 1];
+                    if (jstar < 0 || less128(m, best)) {
+                        jstar = j;
+                        best = m;
+                    }
+                }
+                if (jstar >= 0) {
+                    const U256 lhs = mul256_small(widen(best), uint32_t(b.del_den) * uint32_t(M - 1));
+                    const U256 rhs = mul256_small(total, uint32_t(b.del_num));
+                    if (cmp256(lhs, rhs) < 0) {
+                        for (int q = jstar; q < M - 1; ++q) st->slot[q] = st->slot[q + 1];
+                        st->M = M - 1;
+                        st->del = jstar;
+                        st->changed = 1;
+                    }
+                }
+            }
+            if (st->changed) {
+                st->alpha = b.astart;
+                st->n_pos = 0;
+                st->fresh = 1;
+                st->ci = -1;
             }
         }
-        if (jstar >= 0) {
-            const U256 lhs = mul256_small(widen(best), uint32_t(b.del_den) * uint32_t(M - 1));
-            const U256 rhs = mul256_small(total, uint32_t(b.del_num));
-            if (cmp256(lhs, rhs) < 0) {
-                for (int q = jstar; q < M - 1; ++q) st->slot[q] = st->slot[q + 1];
-                st->M = M - 1;
-                st->del = jstar;
-                st->changed = 1;
-            }
-        }
     }
-    if (st->changed) {
-        st->alpha = b.astart;
-        st->n_pos = 0;
-        st->fresh = 1;
-        st->ci = -1;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(64) k_refine_decide(BatchDev bd, int mode)
+{
+    ItemLoop loop(bd, KIND_BAND, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        if (mode == 0 && (band_stopped(st) || !st->refine_due)) continue;  // uniform
+        decide_item(b, st, mode);
     }
 }
 
 // Midpoint X_a + (X_b - X_a) / 2 into the new slot; zero velocities after a change.
-__global__ void __launch_bounds__(CFNEB_TILE) k_refine_apply(BandDev b, int mode)
+// Walks every slot of the capacity, since the image count just changed.
+__global__ void __launch_bounds__(CFNEB_TILE) k_refine_apply(BatchDev bd, int mode)
 {
-    BandState* st = b.st;
-    if (mode == 0 && (band_stopped(st) || !st->refine_due)) return;
-    if (!st->changed || st->err != 0) return;
-    const WorkItem w = xcd_item(b.ntR, 0, st->M);
-    const int r = w.tile * CFNEB_TILE + threadIdx.x;
-    const int k = w.image;  // logical image after the change
-    if (!w.valid || r >= b.N + 3) return;
-    const int slot = st->slot[k];
-    if (st->ins >= 0 && k == st->ins) {
-        const double* Xa = Xs(b, st->ins_a);
-        const double* Xb = Xs(b, st->ins_b);
-        double* Xn = Xs(b, slot);
-        {
+    ItemLoop loop(bd, KIND_SLOTROW, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        if (mode == 0 && (band_stopped(st) || !st->refine_due)) continue;
+        if (!st->changed || st->err != 0) continue;
+        const int r = it.tile * CFNEB_TILE + threadIdx.x;
+        const int k = it.image;  // logical image after the change
+        if (r >= b.N + 3 || k >= st->M) continue;
+        const int slot = st->slot[k];
+        if (st->ins >= 0 && k == st->ins) {
+            const double* Xa = Xs(b, st->ins_a);
+            const double* Xb = Xs(b, st->ins_b);
+            double* Xn = Xs(b, slot);
+            {
 #pragma clang fp contract(off)
-            for (int c = 0; c < 3; ++c) {
-                const size_t o = size_t(c) * b.ld + r;
-                Xn[o] = Xa[o] + 0.5 * (Xb[o] - Xa[o]);
+                for (int c = 0; c < 3; ++c) {
+                    const size_t o = size_t(c) * b.ld + r;
+                    Xn[o] = Xa[o] + 0.5 * (Xb[o] - Xa[o]);
+                }
             }
         }
+        double* V = Vs(b, st->vcur, slot);
+        for (int c = 0; c < 3; ++c) V[size_t(c) * b.ld + r] = 0.0;
     }
-    double* V = Vs(b, st->vcur, slot);
-    for (int c = 0; c < 3; ++c) V[size_t(c) * b.ld + r] = 0.0;
 }
 
-__global__ void k_refine_end(BandDev b) { b.st->refine_due = 0; }
-
-__global__ void k_refine_force(BandDev b) { b.st->refine_due = 1; }
+__global__ void k_refine_end(BatchDev bd)
+{
+    ItemLoop loop(bd, KIND_BAND, 0);
+    Item it;
+    while (loop.next(it))
+        if (threadIdx.x == 0) bd.bands[it.band].st->refine_due = 0;
+}
 
 // H in logical order, barrier, path coordinate (from the exact spacings).
-__global__ void k_readout(BandDev b)
+__global__ void k_readout(BatchDev bd)
 {
-    BandState* st = b.st;
-    const int M = st->M;
-    double hmax = b.scal[st->slot[0]].H;
-    for (int k = 0; k < M; ++k) {
-        const double h = b.scal[st->slot[k]].H;
-        st->Hlog[k] = h;
-        hmax = fmax(hmax, h);
-    }
-    st->barrier = hmax - st->Hlog[0];
-    double tot = 0.0;
-    for (int k = 0; k < M - 1; ++k) tot += sqrt(st->d2[k]);
-    double acc = 0.0;
-    st->xi[0] = 0.0;
-    for (int k = 1; k < M; ++k) {
-        acc += sqrt(st->d2[k - 1]);
-        st->xi[k] = tot > 0.0 ? acc / tot : 0.0;
+    ItemLoop loop(bd, KIND_BAND, 0);
+    Item it;
+    while (loop.next(it)) {
+        if (threadIdx.x != 0) continue;
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        const int M = st->M;
+        double hmax = b.scal[st->slot[0]].H;
+        for (int k = 0; k < M; ++k) {
+            const double h = b.scal[st->slot[k]].H;
+            st->Hlog[k] = h;
+            hmax = fmax(hmax, h);
+        }
+        st->barrier = hmax - st->Hlog[0];
+        double tot = 0.0;
+        for (int k = 0; k < M - 1; ++k) tot += sqrt(st->d2[k]);
+        double acc = 0.0;
+        st->xi[0] = 0.0;
+        for (int k = 1; k < M; ++k) {
+            acc += sqrt(st->d2[k - 1]);
+            st->xi[k] = tot > 0.0 ? acc / tot : 0.0;
+        }
     }
 }
 
-void launch_refine(const BandDev& b, int forced, hipStream_t s)
+// Step-end adaptive-image check (kernels act only on bands whose step set refine_due),
+// or a forced decision (mode 1) after launch_plan(..., ignore_stop = 1).
+void launch_refine(const Launch& L, int forced, hipStream_t s)
 {
-    if (forced) k_refine_force<<<1, 1, 0, s>>>(b);
-    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
-    k_refine_dist<<<gR, CFNEB_TILE, 0, s>>>(b, forced ? 1 : 0);
-    k_refine_decide<<<1, 64, 0, s>>>(b, forced ? 1 : 0);
-    k_refine_apply<<<gR, CFNEB_TILE, 0, s>>>(b, forced ? 1 : 0);
-    k_refine_end<<<1, 1, 0, s>>>(b);
+    const int mode = forced ? 1 : 0;
+    k_refine_dist<<<L.g[KIND_IVAL], CFNEB_TILE, 0, s>>>(L.bd, mode);
+    k_refine_decide<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd, mode);
+    k_refine_apply<<<L.g[KIND_SLOTROW], CFNEB_TILE, 0, s>>>(L.bd, mode);
+    k_refine_end<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd);
 }
 
-void launch_readout(const BandDev& b, hipStream_t s)
+// Readout after launch_plan(..., ignore_stop = 1).
+void launch_readout(const Launch& L, hipStream_t s)
 {
-    const unsigned gR = cfneb_grid(b.ntR, b.Mcap);
-    k_refine_dist<<<gR, CFNEB_TILE, 0, s>>>(b, 1);
-    k_refine_decide<<<1, 64, 0, s>>>(b, 2);
-    k_readout<<<1, 1, 0, s>>>(b);
+    k_refine_dist<<<L.g[KIND_IVAL], CFNEB_TILE, 0, s>>>(L.bd, 1);
+    k_refine_decide<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd, 2);
+    k_readout<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd);
 }
 
 }  // namespace cfneb

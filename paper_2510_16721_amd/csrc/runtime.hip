@@ -24,7 +24,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     int N, ld, Mcap, ntA, ntR, nbcap, cap, fp64, tersoff;
     size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, dvec, bo, P, geom, scal,
-        evpart, dotpart, maxpart, refpart, staging, state, total;
+        evpart, dotpart, maxpart, refpart, staging, state, table, live, plan, total;
 };
 
 bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout* L)
@@ -71,8 +71,25 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->refpart = take(M * L->ntR * 2 * 8);
     L->staging = take((6 * N + 64) * 8);
     L->state = take(sizeof(BandState));
+    // the band's own one-entry table for the persistent kernels
+    L->table = take(sizeof(BandDev));
+    L->live = take(sizeof(int));
+    L->plan = take(NKIND * 2 * sizeof(int));
     L->total = off;
     return true;
+}
+
+// Grids of a band table, bounded by the most items its bands can hold.
+void size_grids(Launch& L, long long atom_tiles, long long row_tiles, long long bin_tiles, long long images,
+                int bands)
+{
+    L.g[KIND_ATOM] = grid_for(atom_tiles, CFNEB_GRID_TILES);
+    L.g[KIND_ROW] = grid_for(row_tiles, CFNEB_GRID_TILES);
+    L.g[KIND_BIN] = grid_for(bin_tiles, CFNEB_GRID_TILES);
+    L.g[KIND_IMAGE] = grid_for(images, CFNEB_GRID_IMAGES);
+    L.g[KIND_IVAL] = grid_for(row_tiles, CFNEB_GRID_TILES);
+    L.g[KIND_SLOTROW] = grid_for(row_tiles, CFNEB_GRID_TILES);
+    L.g[KIND_BAND] = grid_for(bands, CFNEB_GRID_BANDS);
 }
 
 const char* err_text(int code)
@@ -97,6 +114,7 @@ struct cfneb_band {
     cfneb_params p;
     BandDev d;
     Layout L;
+    Launch launch;  // the band as a table of one
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -228,6 +246,14 @@ void fill_dev(cfneb_band* b, void* ws)
     d.refpart = reinterpret_cast<uint64_t*>(base + L.refpart);
     d.staging = reinterpret_cast<double*>(base + L.staging);
     d.st = reinterpret_cast<BandState*>(base + L.state);
+    Launch& ln = b->launch;
+    ln.bd.bands = reinterpret_cast<const BandDev*>(base + L.table);
+    ln.bd.live = reinterpret_cast<const int*>(base + L.live);
+    ln.bd.plan = reinterpret_cast<int*>(base + L.plan);
+    ln.bd.cap = 1;
+    const long long M = L.Mcap;
+    size_grids(ln, M * L.ntA, M * L.ntR, M * ((L.nbcap + CFNEB_TILE - 1) / CFNEB_TILE), M, 1);
+    ln.variants = 1u << band_variant(d);
 }
 
 int validate(const cfneb_params* p, int64_t n_atoms)
@@ -269,9 +295,7 @@ void aos_to_soa(const double* aos, int ld, int rows, double* soa)
 
 int launch_step_direct(cfneb_band* b)
 {
-    launch_evaluate(b->d, 0, b->stream);
-    launch_band_update(b->d, b->stream);
-    launch_refine(b->d, 0, b->stream);
+    launch_step(b->launch, b->stream);
     return check_kernels(b, "step");
 }
 
@@ -279,9 +303,7 @@ int ensure_graph(cfneb_band* b)
 {
     if (b->exec || !b->use_graph) return CFNEB_OK;
     HIP_TRY(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed));
-    launch_evaluate(b->d, 0, b->capture_stream);
-    launch_band_update(b->d, b->capture_stream);
-    launch_refine(b->d, 0, b->capture_stream);
+    launch_step(b->launch, b->capture_stream);
     HIP_TRY(b, hipStreamEndCapture(b->capture_stream, &b->graph));
     HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     return CFNEB_OK;
@@ -397,10 +419,16 @@ int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* typ
     if (hipMemcpyAsync(b->d.staging, stage.data(), stage.size() * sizeof(double), hipMemcpyHostToDevice,
                        b->stream) != hipSuccess)
         return bail(CFNEB_EHIP);
+    static const int one = 1;
+    if (hipMemcpyAsync(const_cast<BandDev*>(b->launch.bd.bands), &b->d, sizeof(BandDev), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int*>(b->launch.bd.live), &one, sizeof(int), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess)
+        return bail(CFNEB_EHIP);
     launch_init_endpoints(b->d, b->stream);
     launch_init_images(b->d, p->n_images, b->stream);
     launch_init_state(b->d, p->n_images, b->stream);
-    launch_evaluate(b->d, 1, b->stream);
+    launch_evaluate(b->launch, 1, b->stream);
     if (hipGetLastError() != hipSuccess) return bail(CFNEB_EHIP);
     rc = read_state(b);
     if (rc != CFNEB_OK) return bail(rc);
@@ -413,7 +441,7 @@ int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, doub
                int* converged)
 {
     if (!b || max_steps < 0) return CFNEB_EINVAL;
-    launch_begin_call(b->d, f_tol, b->stream);
+    launch_begin_call(b->launch, f_tol, -1, b->stream);
     int rc = ensure_graph(b);
     if (rc != CFNEB_OK) return rc;
     const int check_every = 16;
@@ -445,7 +473,7 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
 {
     if (!b || max_steps < 0 || nphase < 0 || nphase > CFNEB_NPHASE || (nphase > 0 && !phase_ms))
         return CFNEB_EINVAL;
-    launch_begin_call(b->d, f_tol, b->stream);
+    launch_begin_call(b->launch, f_tol, -1, b->stream);
     const int NP = CFNEB_NPHASE;
     // one event before every phase and one after the last, for every step
     std::vector<hipEvent_t> ev(size_t(max_steps) * (NP + 1), nullptr);
@@ -455,14 +483,17 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
             rc = fail(b, CFNEB_EHIP, "hipEventCreate");
             break;
         }
-    const BandDev& d = b->d;
+    const Launch& d = b->launch;
     hipStream_t s = b->stream;
     for (int st = 0; st < max_steps && rc == CFNEB_OK; ++st) {
         hipEvent_t* e = ev.data() + size_t(st) * (NP + 1);
         for (int ph = 0; ph < NP; ++ph) {
             (void)hipEventRecord(e[ph], s);
             switch (ph) {
-            case CFNEB_PH_GEOM: launch_geom(d, 0, s); break;
+            case CFNEB_PH_GEOM:
+                launch_plan(d, 0, 0, s);
+                launch_geom(d, 0, s);
+                break;
             case CFNEB_PH_BINS: launch_bins(d, 0, s); break;
             case CFNEB_PH_NLIST: launch_list(d, 0, s); break;
             case CFNEB_PH_FORCE0: launch_force_stage(d, 0, 0, s); break;
@@ -506,8 +537,9 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
 int cfneb_refine(cfneb_band* b, int* inserted_at, int* deleted_at)
 {
     if (!b) return CFNEB_EINVAL;
-    launch_begin_call(b->d, 0.0, b->stream);
-    launch_refine(b->d, 1, b->stream);
+    launch_begin_call(b->launch, 0.0, -1, b->stream);
+    launch_plan(b->launch, 0, 1, b->stream);
+    launch_refine(b->launch, 1, b->stream);
     int rc = check_kernels(b, "refine");
     if (rc == CFNEB_OK) rc = read_state(b);
     if (rc != CFNEB_OK) return rc;
@@ -522,7 +554,8 @@ int cfneb_energies(const cfneb_band* cb, double* H, int cap, int* n_images, doub
 {
     auto* b = const_cast<cfneb_band*>(cb);
     if (!b) return CFNEB_EINVAL;
-    launch_readout(b->d, b->stream);
+    launch_plan(b->launch, 0, 1, b->stream);
+    launch_readout(b->launch, b->stream);
     int rc = check_kernels(b, "readout");
     if (rc == CFNEB_OK) rc = read_state(b);
     if (rc != CFNEB_OK) return rc;
@@ -626,7 +659,7 @@ int cfneb_set_state(cfneb_band* b, int n_images, const double* X, const double* 
     st.refine_due = 0;
     rc = write_state(b);
     if (rc != CFNEB_OK) return rc;
-    launch_evaluate(b->d, 1, b->stream);
+    launch_evaluate(b->launch, 1, b->stream);
     rc = check_kernels(b, "set_state");
     if (rc == CFNEB_OK) rc = read_state(b);
     if (rc != CFNEB_OK) return rc;
@@ -733,6 +766,212 @@ int cfneb_destroy(cfneb_band* b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     if (b->host_state) (void)hipHostFree(b->host_state);
     delete b;
+    return CFNEB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+// A batch is a table of bands stepped together: every phase of the step is one
+// persistent launch over the items of all live bands (sizes may differ), captured
+// once in a graph; attaching or detaching a band rewrites the device table only.
+struct cfneb_batch {
+    int cap = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    Launch launch;
+    BandDev* table = nullptr;
+    int* live = nullptr;
+    int* plan = nullptr;
+    int* summary = nullptr;
+    int* host_summary = nullptr;  // pinned, 4 ints per table entry
+    std::vector<cfneb_band*> bands;
+    unsigned graph_variants = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t table, live, plan, summary, total;
+};
+
+BatchLayout batch_layout(int cap)
+{
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.table = take(size_t(cap) * sizeof(BandDev));
+    L.live = take(size_t(cap) * sizeof(int));
+    L.plan = take(size_t(NKIND) * (cap + 1) * sizeof(int));
+    L.summary = take(size_t(cap) * 4 * sizeof(int));
+    L.total = off;
+    return L;
+}
+
+void drop_graph(cfneb_batch* B)
+{
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+}
+
+int read_summary(cfneb_batch* B)
+{
+    launch_summary(B->launch, B->summary, B->stream);
+    if (hipMemcpyAsync(B->host_summary, B->summary, size_t(B->cap) * 4 * sizeof(int), hipMemcpyDeviceToHost,
+                       B->stream) != hipSuccess)
+        return CFNEB_EHIP;
+    if (hipStreamSynchronize(B->stream) != hipSuccess) return CFNEB_EHIP;
+    return CFNEB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfneb_batch_bytes(int max_bands, size_t* bytes)
+{
+    if (!bytes || max_bands < 1 || max_bands > CFNEB_MAX_BANDS) return CFNEB_EINVAL;
+    *bytes = batch_layout(max_bands).total;
+    return CFNEB_OK;
+}
+
+int cfneb_batch_create(int max_bands, void* workspace, size_t workspace_bytes, void* hip_stream,
+                       cfneb_batch** out)
+{
+    if (!out || !workspace || max_bands < 1 || max_bands > CFNEB_MAX_BANDS) return CFNEB_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return CFNEB_EINVAL;
+    const BatchLayout BL = batch_layout(max_bands);
+    if (workspace_bytes < BL.total) return CFNEB_ENOMEM;
+    auto* B = new (std::nothrow) cfneb_batch();
+    if (!B) return CFNEB_ENOMEM;
+    B->cap = max_bands;
+    B->stream = static_cast<hipStream_t>(hip_stream);
+    char* base = static_cast<char*>(workspace);
+    B->table = reinterpret_cast<BandDev*>(base + BL.table);
+    B->live = reinterpret_cast<int*>(base + BL.live);
+    B->plan = reinterpret_cast<int*>(base + BL.plan);
+    B->summary = reinterpret_cast<int*>(base + BL.summary);
+    B->bands.assign(max_bands, nullptr);
+    B->launch.bd.bands = B->table;
+    B->launch.bd.live = B->live;
+    B->launch.bd.plan = B->plan;
+    B->launch.bd.cap = max_bands;
+    // any band may join later: size the persistent grids for the whole chip
+    size_grids(B->launch, 1LL << 40, 1LL << 40, 1LL << 40, 1LL << 40, max_bands);
+    B->launch.variants = 0;
+    const char* ng = std::getenv("CFNEB_NO_GRAPH");
+    B->use_graph = !(ng && ng[0] == '1');
+    if (hipHostMalloc(reinterpret_cast<void**>(&B->host_summary), size_t(max_bands) * 4 * sizeof(int),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&B->capture_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMemsetAsync(workspace, 0, BL.total, B->stream) != hipSuccess ||
+        hipStreamSynchronize(B->stream) != hipSuccess) {
+        cfneb_batch_destroy(B);
+        return CFNEB_EHIP;
+    }
+    *out = B;
+    return CFNEB_OK;
+}
+
+int cfneb_batch_attach(cfneb_batch* B, cfneb_band* band, int* slot)
+{
+    if (!B || !band) return CFNEB_EINVAL;
+    int s = -1;
+    for (int q = 0; q < B->cap; ++q) {
+        if (B->bands[q] == band) return CFNEB_EINVAL;
+        if (s < 0 && !B->bands[q]) s = q;
+    }
+    if (s < 0) return CFNEB_ECAPACITY;
+    static const int one = 1;
+    if (hipStreamSynchronize(band->stream) != hipSuccess ||
+        hipMemcpyAsync(B->table + s, &band->d, sizeof(BandDev), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+        hipMemcpyAsync(B->live + s, &one, sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+        hipStreamSynchronize(B->stream) != hipSuccess)
+        return CFNEB_EHIP;
+    B->bands[s] = band;
+    unsigned v = 0;
+    for (auto* bb : B->bands)
+        if (bb) v |= 1u << band_variant(bb->d);
+    B->launch.variants = v;
+    if (slot) *slot = s;
+    return CFNEB_OK;
+}
+
+int cfneb_batch_detach(cfneb_batch* B, int slot)
+{
+    if (!B || slot < 0 || slot >= B->cap || !B->bands[slot]) return CFNEB_EINVAL;
+    static const int zero = 0;
+    if (hipMemcpyAsync(B->live + slot, &zero, sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+        hipStreamSynchronize(B->stream) != hipSuccess)
+        return CFNEB_EHIP;
+    B->bands[slot] = nullptr;
+    unsigned v = 0;
+    for (auto* bb : B->bands)
+        if (bb) v |= 1u << band_variant(bb->d);
+    B->launch.variants = v;
+    return CFNEB_OK;
+}
+
+int cfneb_batch_step(cfneb_batch* B, int max_steps, double f_tol, int* steps_done, uint8_t* converged,
+                     int* errors)
+{
+    if (!B || max_steps < 0) return CFNEB_EINVAL;
+    launch_begin_call(B->launch, f_tol, -1, B->stream);
+    if (B->use_graph && (!B->exec || B->graph_variants != B->launch.variants)) {
+        drop_graph(B);
+        if (hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return CFNEB_EHIP;
+        launch_step(B->launch, B->capture_stream);
+        if (hipStreamEndCapture(B->capture_stream, &B->graph) != hipSuccess ||
+            hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess)
+            return CFNEB_EHIP;
+        B->graph_variants = B->launch.variants;
+    }
+    const int check_every = 16;
+    int rc = CFNEB_OK;
+    for (int s = 0; s < max_steps; ++s) {
+        if (B->exec) {
+            if (hipGraphLaunch(B->exec, B->stream) != hipSuccess) return CFNEB_EHIP;
+        } else {
+            launch_step(B->launch, B->stream);
+            if (hipGetLastError() != hipSuccess) return CFNEB_EHIP;
+        }
+        if ((s + 1) % check_every == 0 && s + 1 < max_steps) {
+            rc = read_summary(B);
+            if (rc != CFNEB_OK) return rc;
+            bool active = false;
+            for (int q = 0; q < B->cap; ++q)
+                if (B->bands[q] && !B->host_summary[4 * q] && !B->host_summary[4 * q + 1]) active = true;
+            if (!active) break;
+        }
+    }
+    rc = read_summary(B);
+    if (rc != CFNEB_OK) return rc;
+    for (int q = 0; q < B->cap; ++q) {
+        const int* o = B->host_summary + 4 * q;
+        if (steps_done) steps_done[q] = B->bands[q] ? o[2] : 0;
+        if (converged) converged[q] = B->bands[q] ? uint8_t(o[0] != 0) : 0;
+        if (errors) errors[q] = B->bands[q] ? o[1] : 0;
+    }
+    return CFNEB_OK;
+}
+
+int cfneb_batch_destroy(cfneb_batch* B)
+{
+    if (!B) return CFNEB_EINVAL;
+    (void)hipStreamSynchronize(B->stream);
+    drop_graph(B);
+    if (B->capture_stream) (void)hipStreamDestroy(B->capture_stream);
+    if (B->host_summary) (void)hipHostFree(B->host_summary);
+    delete B;
     return CFNEB_OK;
 }
 

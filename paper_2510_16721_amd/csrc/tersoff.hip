@@ -222,16 +222,9 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
 
 // u_i, P_ij and the per-atom virial; block partials of (E, V) in FP64.
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_ts_bonds(BandDev b, int all_images)
+__device__ void ts_bonds_item(const BandDev& b, int slot, int tile, double* lds)
 {
-    __shared__ double lds[4 * 10];
-    BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntA, all_images);
-    if (!w.valid) return;
-    const int k = w.image;
-    const int i = w.tile * CFNEB_TILE + threadIdx.x;
-    const int slot = st->slot[k];
+    const int i = tile * CFNEB_TILE + threadIdx.x;
     const size_t N = b.N;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < b.N) {
@@ -248,23 +241,28 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_bonds(BandDev b, int all_imag
     }
     block_sum<10>(acc, lds);
     if (threadIdx.x == 0) {
-        double* out = b.evpart + (size_t(slot) * b.ntA + w.tile) * 10;
+        double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
         for (int q = 0; q < 10; ++q) out[q] = acc[q];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_ts_bonds(BatchDev bd, int all_images, int variant)
+{
+    __shared__ double lds[4 * 10];
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (band_variant(b) != variant || band_stopped(b.st)) continue;  // uniform over the block
+        ts_bonds_item<T>(b, b.st->slot[it.image], it.tile, lds);
     }
 }
 
 // F_i = sum_e (P_e - P_rev(e)), rev(e) = the entry (i, -n) in j's list.
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_ts_gather(BandDev b, int all_images)
+__device__ void ts_gather_item(const BandDev& b, BandState* st, int slot, int i)
 {
-    BandState* st = b.st;
-    if (band_stopped(st)) return;
-    const WorkItem w = image_item(st, b.ntA, all_images);
-    if (!w.valid) return;
-    const int k = w.image;
-    const int i = w.tile * CFNEB_TILE + threadIdx.x;
-    if (i >= b.N) return;
-    const int slot = st->slot[k];
     const size_t N = b.N;
     const uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
     const int* ncnt = b.ncnt + size_t(slot) * N;
@@ -305,15 +303,30 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_gather(BandDev b, int all_ima
 }
 
 // stage 0: bond orders, P_ij, energy and virial; stage 1: force gather
-void launch_tersoff_stage(const BandDev& b, int all_images, int stage, hipStream_t s)
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_ts_gather(BatchDev bd, int all_images, int variant)
 {
-    const unsigned gA = cfneb_grid(b.ntA, b.Mcap);
-    if (b.fp64) {
-        if (stage == 0) k_ts_bonds<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-        if (stage == 1) k_ts_gather<double><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-    } else {
-        if (stage == 0) k_ts_bonds<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
-        if (stage == 1) k_ts_gather<float><<<gA, CFNEB_TILE, 0, s>>>(b, all_images);
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        const int i = it.tile * CFNEB_TILE + threadIdx.x;
+        if (band_variant(b) != variant || band_stopped(st) || i >= b.N) continue;
+        ts_gather_item<T>(b, st, st->slot[it.image], i);
+    }
+}
+
+void launch_tersoff_stage(const Launch& L, int all_images, int stage, hipStream_t s)
+{
+    const unsigned g = L.g[KIND_ATOM];
+    if (L.variants & (1u << VARIANT_TS32)) {
+        if (stage == 0) k_ts_bonds<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS32);
+        if (stage == 1) k_ts_gather<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS32);
+    }
+    if (L.variants & (1u << VARIANT_TS64)) {
+        if (stage == 0) k_ts_bonds<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS64);
+        if (stage == 1) k_ts_gather<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS64);
     }
 }
 

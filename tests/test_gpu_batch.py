@@ -1,0 +1,108 @@
+"""Batched execution: many bands of different sizes and potentials stepped by one
+persistent launch per phase.  Each band's result must not depend on its
+batch-mates: bit-identical to the same band stepped alone."""
+import numpy as np
+import pytest
+
+from gpu_cases import make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+
+
+CASES = [("lj31", dict(n_images=5, max_images=5, fp64=True, climb_after=10)),
+         ("ts_small", dict(n_images=6, max_images=8, refine_every=5, climb_after=8)),
+         ("lj_ragged", dict(n_images=7, max_images=7, climb_after=10)),
+         ("ts_diamond", dict(n_images=5, max_images=5, pressure_GPa=5.0))]
+
+
+def _bands():
+    return [make_pair(name, oracle_too=False, **kw)[0] for name, kw in CASES]
+
+
+def _same_state(a, b):
+    sa, sb = a.get_state(), b.get_state()
+    assert sa["X"].shape == sb["X"].shape
+    np.testing.assert_array_equal(sa["X"], sb["X"])
+    np.testing.assert_array_equal(sa["v"], sb["v"])
+    for key in ("dt", "alpha", "n_pos", "fresh", "step", "ci", "image_steps"):
+        assert sa[key] == sb[key], key
+    np.testing.assert_array_equal(a.energies()["H"], b.energies()["H"])
+
+
+def test_batch_equals_alone_bit_for_bit():
+    from paper_2510_16721_amd import cfneb
+    alone = _bands()
+    for b in alone:
+        assert b.step(23)[0] == 23
+    mixed = _bands()
+    batch = cfneb.Batch(8)
+    slots = [batch.attach(b) for b in mixed]
+    steps, conv, errs = batch.step(23)
+    assert list(steps[slots]) == [23] * len(mixed) and not conv.any() and not errs.any()
+    for a, b in zip(alone, mixed):
+        _same_state(a, b)
+    batch.close()
+
+
+def test_batch_attach_detach_between_calls():
+    from paper_2510_16721_amd import cfneb
+    ref = _bands()
+    for b in ref:
+        b.step(20)
+    bands = _bands()
+    batch = cfneb.Batch(4)
+    s0 = batch.attach(bands[0])
+    s1 = batch.attach(bands[1])
+    batch.step(10)
+    batch.detach(s0)
+    s2 = batch.attach(bands[2])
+    batch.step(10)
+    batch.detach(s1)
+    batch.detach(s2)
+    bands[0].step(10)  # the detached band goes on alone
+    s3 = batch.attach(bands[3])
+    batch.step(20)
+    bands[2].step(10)
+    for r, b in zip(ref, bands):
+        _same_state(r, b)
+    del s3
+    batch.close()
+
+
+def test_batch_bands_converge_independently():
+    from paper_2510_16721_amd import cfneb
+    kw = dict(n_images=5, max_images=5, climb_after=20, fp64=True)
+    fast = make_pair("lj31", oracle_too=False, **kw)[0]
+    slow = make_pair("lj_ragged", oracle_too=False, **kw)[0]
+    batch = cfneb.Batch(2)
+    sf, ss = batch.attach(fast), batch.attach(slow)
+    steps, conv, errs = batch.step(4000, 5e-3)
+    assert conv[sf] and not errs.any()
+    # the same band alone takes the same number of steps to the same barrier
+    ref = make_pair("lj31", oracle_too=False, **kw)[0]
+    nref, fref, cref = ref.step(4000, 5e-3)
+    assert cref and nref == steps[sf]
+    assert ref.energies()["barrier"] == fast.energies()["barrier"]
+    batch.close()
+
+
+def test_batch_capacity_and_errors():
+    from paper_2510_16721_amd import cfneb
+    bands = _bands()
+    batch = cfneb.Batch(2)
+    batch.attach(bands[0])
+    batch.attach(bands[1])
+    with pytest.raises(cfneb.CfnebError) as e:
+        batch.attach(bands[2])
+    assert e.value.code == -7  # CFNEB_ECAPACITY
+    with pytest.raises(cfneb.CfnebError):
+        batch.attach(bands[0])  # already attached
+    batch.close()
