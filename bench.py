@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -77,6 +79,110 @@ def cpu_baseline(w, kw, steps):
                        f"({m0 - 2} moving images), FP64, OpenMP over images, {dt:.1f} s")
 
 
+def mix_params(entry):
+    from paper_2510_16721_amd import cfneb
+    pot = cfneb.CFNEB_LJ if entry["kind"] == "lj" else cfneb.CFNEB_TERSOFF_C
+    m = entry["n_images"]
+    return cfneb.default_params(pot, n_images=m, max_images=m, min_images=3, climb_after=50)
+
+
+def bench_batched(args):
+    """Independent bands (atom counts log-uniform in [256, 32,000], 5-17 images, LJ and
+    Tersoff vacancy hops) relaxed to fmax < 0.01 eV/A one at a time, then all in one
+    batch; speedup = plain time / batched time, barriers compared band by band."""
+    import torch
+    import workloads as W
+    from paper_2510_16721_amd import cfneb
+    f_tol = 0.01
+    mix = W.band_mix(3, args.bands, 256, args.n_max or 32000, 5, 17)
+    plain_t, plain = 0.0, []
+    for q, e in enumerate(mix):
+        w = e["endpoints"]
+        b = cfneb.Band(mix_params(e), w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, fmax, conv = b.step(args.max_steps, f_tol)
+        torch.cuda.synchronize()
+        plain_t += time.perf_counter() - t0
+        plain.append(dict(steps=done, conv=conv, barrier=b.energies()["barrier"],
+                          work=w["n"] * b.get_state()["image_steps"]))
+        b.close()
+        print(f"bench: plain band {q}: {w['n']} atoms, {e['n_images']} images, {done} steps, "
+              f"converged {conv}", file=sys.stderr, flush=True)
+    bands = []
+    for e in mix:
+        w = e["endpoints"]
+        bands.append(cfneb.Band(mix_params(e), w["pos_init"], w["cell_init"], w["pos_final"],
+                                w["cell_final"]))
+    batch = cfneb.Batch(len(bands))
+    slots = [batch.attach(b) for b in bands]
+    steps = np.zeros(len(bands), dtype=np.int64)
+    live = set(range(len(bands)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while live:
+        s, conv, errs = batch.step(64, f_tol)
+        for q in list(live):
+            steps[q] += s[slots[q]]
+            if conv[slots[q]] or errs[slots[q]] or steps[q] >= args.max_steps:
+                batch.detach(slots[q])
+                live.discard(q)
+    torch.cuda.synchronize()
+    batched_t = time.perf_counter() - t0
+    bar = np.array([b.energies()["barrier"] for b in bands])
+    diff = np.abs(bar - np.array([p["barrier"] for p in plain]))
+    work = sum(p["work"] for p in plain)
+    batch.close()
+    return {
+        "metric": "batched-vs-plain speedup at 1 meV",
+        "value": plain_t / batched_t, "unit": "x", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic (seeded LJ FCC and Tersoff diamond vacancy hops)",
+        "dtype": "fp32 pair/three-body, fp64 sums/band/FIRE",
+        "config": {"workload": f"{len(mix)} independent bands, atoms log-uniform in "
+                               f"[256, {args.n_max or 32000}], 5-17 images, run to fmax < 0.01 eV/A "
+                               f"(cap {args.max_steps} steps)",
+                   "bands": len(mix), "parallelism": "1 GPU"},
+        "plain_s": plain_t, "batched_s": batched_t,
+        "plain_atom_steps_per_s": work / plain_t, "batched_atom_steps_per_s": work / batched_t,
+        "max_barrier_diff_eV": float(diff.max()),
+        "converged_plain": int(sum(p["conv"] for p in plain)),
+        "steps_identical": bool(all(int(steps[q]) == plain[q]["steps"] for q in range(len(mix)))),
+        "vs_baseline": None,
+    }
+
+
+def bench_serving(args):
+    """Poisson stream of band relaxations (atoms log-uniform in [500, 50,000], 7-21 images,
+    LJ or Tersoff 50/50) served by the continuous-batching loop with a 200 GB HBM budget;
+    p99 / p50 time from arrival to converged barrier, and throughput."""
+    import workloads as W
+    from paper_2510_16721_amd import serving
+    mix = W.band_mix(4, args.requests, 500, args.n_max or 50000, 7, 21)
+    arrivals = W.poisson_arrivals(4, len(mix), args.rate)
+    reqs = [serving.Request(rid=q, arrival=float(arrivals[q]), params=mix_params(e),
+                            endpoints=e["endpoints"], n_atoms=e["n"]) for q, e in enumerate(mix)]
+    srv = serving.Server(hbm_budget_bytes=200e9, max_bands=64, f_tol=0.01, steps_per_call=32,
+                         max_steps=args.max_steps)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    s = serving.summarize(done, wall)
+    occ = np.array([o[1] for o in srv.occupancy]) if srv.occupancy else np.zeros(1)
+    return {
+        "metric": "p99 latency (arrival to converged barrier)",
+        "value": s["p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+        "data": "synthetic (seeded LJ FCC and Tersoff diamond vacancy hops, Poisson arrivals)",
+        "dtype": "fp32 pair/three-body, fp64 sums/band/FIRE",
+        "config": {"workload": f"{len(mix)} requests at {args.rate}/s, atoms log-uniform in "
+                               f"[500, {args.n_max or 50000}], 7-21 images, fmax < 0.01 eV/A, "
+                               f"HBM budget 200 GB", "parallelism": "1 GPU"},
+        "p50_s": s["p50_s"], "atom_steps_per_s": s["atom_steps_per_s"], "wall_s": wall,
+        "converged": s["converged"], "failed": s["failed"], "capped": s["capped"],
+        "mean_active_bands": float(occ.mean()), "max_active_bands": int(occ.max()),
+        "vs_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +193,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--mode", choices=["throughput", "batched", "serving"], default="throughput",
+                    help="throughput: the 98,304-atom band (default); batched: many bands "
+                         "batched vs one at a time; serving: Poisson request stream")
+    ap.add_argument("--bands", type=int, default=64, help="batched mode: number of bands")
+    ap.add_argument("--requests", type=int, default=64, help="serving mode: number of requests")
+    ap.add_argument("--rate", type=float, default=4.0, help="serving mode: arrivals per second")
+    ap.add_argument("--max-steps", type=int, default=4000, help="batched/serving: step cap per band")
+    ap.add_argument("--n-max", type=int, default=0, help="batched/serving: override the atom-count cap")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -96,6 +210,12 @@ def main():
     import torch
     assert torch.cuda.is_available(), "needs a HIP device"
     torch.cuda.set_device(0)
+    if args.mode == "batched":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.mode == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
     band, w, kw = make_band(args)
     N = band.n
     print(f"bench: band created, {N} atoms, {kw['n_images']} images, workspace "

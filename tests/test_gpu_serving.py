@@ -1,0 +1,87 @@
+"""Continuous batching: requests admitted by slots and HBM budget while others run;
+each result is the same alone and in the mix; a failing request fails alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+
+
+def _requests():
+    from paper_2510_16721_amd import cfneb, serving
+    specs = [("lj", W.fcc_vacancy_hop(2, 2, 2, 1.5496), 5, 0.00),
+             ("ts", W.diamond_vacancy_hop(1, 1, 2), 5, 0.01),
+             ("lj", W.fcc_vacancy_hop(3, 2, 2, 1.5496), 6, 0.02),
+             ("lj", W.fcc_vacancy_hop(2, 2, 2, 1.5496), 7, 0.03),
+             ("ts", W.diamond_vacancy_hop(2, 1, 1), 5, 0.04),
+             ("lj", W.fcc_vacancy_hop(3, 3, 2, 1.5496), 5, 0.05)]
+    reqs = []
+    for q, (kind, w, m, t) in enumerate(specs):
+        pot = cfneb.CFNEB_LJ if kind == "lj" else cfneb.CFNEB_TERSOFF_C
+        p = cfneb.default_params(pot, n_images=m, max_images=m, climb_after=30, force_fp64=1)
+        reqs.append(serving.Request(rid=q, arrival=t, params=p, endpoints=w, n_atoms=w["n"]))
+    return reqs
+
+
+def _alone(req, f_tol, max_steps):
+    from paper_2510_16721_amd import cfneb
+    e = req.endpoints
+    b = cfneb.Band(req.params, e["pos_init"], e["cell_init"], e["pos_final"], e["cell_final"])
+    steps, fmax, conv = b.step(max_steps, f_tol)
+    out = (steps, conv, b.energies()["barrier"])
+    b.close()
+    return out
+
+
+def test_served_results_equal_alone():
+    from paper_2510_16721_amd import cfneb, serving
+    reqs = _requests()
+    biggest = max(cfneb.band_bytes(r.params, r.n_atoms) for r in reqs)
+    # room for about two bands at a time: admission must wait for memory
+    srv = serving.Server(hbm_budget_bytes=int(2.2 * biggest), max_bands=8, f_tol=0.02,
+                         steps_per_call=16, max_steps=3000)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert max(o[1] for o in srv.occupancy) <= 2
+    assert all(o[2] <= srv.budget for o in srv.occupancy)
+    for r in sorted(done, key=lambda r: r.rid):
+        assert r.error == 0 and r.converged, (r.rid, r.error)
+        assert r.finished >= r.admitted >= r.arrival
+        steps, conv, barrier = _alone(r, 0.02, 3000)
+        # served steps are counted per batch call, so they can overrun by the call size only
+        # after convergence is reached; the band itself stops at the same step
+        assert conv and barrier == r.barrier, (r.rid, barrier, r.barrier)
+    s = serving.summarize(done, 1.0)
+    assert s["converged"] == len(reqs) and s["p99_s"] >= s["p50_s"] > 0
+
+
+def test_failing_and_oversized_requests_fail_alone():
+    from paper_2510_16721_amd import serving
+    reqs = _requests()[:3]
+    bad = reqs[1]
+    bad.endpoints = dict(bad.endpoints)
+    pos = bad.endpoints["pos_final"].copy()
+    pos[0, 0] = np.nan
+    bad.endpoints["pos_final"] = pos
+    srv = serving.Server(hbm_budget_bytes=10**12, max_bands=4, f_tol=0.02, steps_per_call=16,
+                         max_steps=3000)
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert done[bad.rid].error != 0
+    for rid in (0, 2):
+        assert done[rid].error == 0 and done[rid].converged
+        steps, conv, barrier = _alone(done[rid], 0.02, 3000)
+        assert barrier == done[rid].barrier
+    # a request larger than the whole budget is rejected with ENOMEM
+    r = _requests()[5]
+    srv = serving.Server(hbm_budget_bytes=1000, max_bands=4)
+    out = srv.run([r])
+    assert out[0].error == -2

@@ -156,3 +156,49 @@ def random_cell(n, seed, density=0.08, skew=0.15, min_sep=0.0):
     # unwrapped positions: some atoms sit one or two cells away
     s += rng.integers(-2, 3, size=(n, 3)) * (rng.random((n, 3)) < 0.1)
     return s @ h, h
+
+
+# ------------------------------------------------------------ batches and streams
+def _near_cubic(n_cells_target, lo=2):
+    """(nx, ny, nz) with nx <= ny <= nz, aspect at most 2, product closest to the target."""
+    best = None
+    k = max(lo, int(round(n_cells_target ** (1.0 / 3.0))))
+    for nx in range(max(lo, k - 3), k + 4):
+        for ny in range(nx, 2 * nx + 1):
+            for nz in range(ny, 2 * nx + 1):
+                err = abs(nx * ny * nz - n_cells_target)
+                if best is None or err < best[0]:
+                    best = (err, (nx, ny, nz))
+    return best[1]
+
+
+def lj_hop_near(n_target):
+    """LJ FCC vacancy hop with 4 nx ny nz - 1 atoms closest to n_target (cells >= 4 wide)."""
+    nx, ny, nz = _near_cubic((n_target + 1) / 4.0, lo=4)
+    return fcc_vacancy_hop(nx, ny, nz, 1.5496)
+
+
+def diamond_hop_near(n_target):
+    """Tersoff diamond vacancy hop with 8 nx ny nz - 1 atoms closest to n_target."""
+    nx, ny, nz = _near_cubic((n_target + 1) / 8.0, lo=2)
+    return diamond_vacancy_hop(nx, ny, nz)
+
+
+def band_mix(seed, count, n_lo, n_hi, m_lo, m_hi):
+    """Independent bands: atom counts log-uniform in [n_lo, n_hi], image counts uniform in
+    [m_lo, m_hi], LJ vacancy hops (even index) and Tersoff diamond vacancy hops (odd)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        n_target = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        m = int(rng.integers(m_lo, m_hi + 1))
+        kind = "lj" if q % 2 == 0 else "ts"
+        w = lj_hop_near(n_target) if kind == "lj" else diamond_hop_near(n_target)
+        out.append(dict(kind=kind, n_images=m, endpoints=w, n=w["n"]))
+    return out
+
+
+def poisson_arrivals(seed, count, rate):
+    """Arrival times (s) of a Poisson stream of `count` requests at `rate` per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
