@@ -18,11 +18,17 @@ namespace {
 constexpr double kEvPerA3InGPa = 160.21766208;
 }
 
+double orc::cell_factor_of(const orc_params* p, int n, const double* h0)
+{
+    if (p->cell_factor > 0.0) return p->cell_factor;
+    return std::cbrt(std::fabs(orc_det3(h0))) * std::pow(double(n), 1.0 / 6.0);
+}
+
 extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const double* X,
                            double* H, double* E, double* Fg, double* V,
                            double* Fout, double* Rout, double* hout)
 {
-    const double cf = p->cell_factor > 0.0 ? p->cell_factor : double(n);
+    const double cf = orc::cell_factor_of(p, n, h0);
     double B[9], D[9], h[9], Dinv[9], DinvT[9];
     for (int k = 0; k < 9; ++k) B[k] = X[3 * n + k] / cf;
     int rc = orc_symsqrt(B, D);
@@ -76,8 +82,8 @@ extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const d
 extern "C" int orc_build_endpoints(const orc_params* p, int n, const double* RA, const double* hA,
                                    const double* RB, const double* hB, double* XA, double* XB)
 {
-    const double cf = p->cell_factor > 0.0 ? p->cell_factor : double(n);
     const double* h0 = hA;
+    const double cf = orc::cell_factor_of(p, n, h0);
     if (!(std::fabs(orc_det3(hA)) > 0.0) || !(std::fabs(orc_det3(hB)) > 0.0)) return ORC_ECELL;
     double h0inv[9], hBinv[9], Draw[9], DrawT[9], BB[9];
     orc_inv3(h0, h0inv);

@@ -31,6 +31,12 @@ int eval_with_lists(const orc_params* p, int n, const double* R, const double* h
 
 double cutoff_of(const orc_params* p);
 
+// Cell factor c_f of the generalized cell coordinate c_f B.  Default (cell_factor <= 0):
+// |det h0|^(1/3) n^(1/6), the size-consistent Jacobian of the generalized solid-state
+// NEB, so that a uniform strain of the cell and a uniform displacement of all n atoms
+// have comparable lengths in the band's metric and comparable stiffness.
+double cell_factor_of(const orc_params* p, int n, const double* h0);
+
 }  // namespace orc
 
 #endif

@@ -630,9 +630,9 @@ extern "C" int orc_relax(const orc_params* p, int n, double* R, double* h, int m
     c.M = 3;
     c.dim = 3 * (n + 3);
     c.roww = 3;
-    const double cf = p->cell_factor > 0.0 ? p->cell_factor : double(n);
     double h0[9];
     for (int k = 0; k < 9; ++k) h0[k] = h[k];
+    const double cf = orc::cell_factor_of(p, n, h0);
     c.X.assign(3, std::vector<double>(c.dim, 0.0));
     c.v.assign(3, std::vector<double>(c.dim, 0.0));
     c.Fneb.assign(3, std::vector<double>(c.dim, 0.0));

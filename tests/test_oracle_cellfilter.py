@@ -108,3 +108,33 @@ def test_non_spd_cell_rows_are_rejected(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.cf_eval(p, h0, X)
     assert e.value.code == orc.ECELL
+
+
+def test_default_cell_factor_is_size_consistent(orc):
+    # Default c_f = |det h0|^(1/3) n^(1/6) (the generalized solid-state NEB Jacobian):
+    # the stiffness of H along a cell coordinate Y = c_f B_xx, and the band-metric
+    # length of a uniform strain relative to a uniform per-atom displacement, do not
+    # depend on the supercell size.  With c_f = n both would scale as 1/n and n.
+    p = orc.default_params(orc.LJ)
+    stiff, ratio = [], []
+    for m in (2, 3):
+        R, h = W.fcc_sites(m, m, m, 1.5496)
+        n = len(R)
+        XA, _ = orc.build_endpoints(p, R, h, R, h)
+        cf = abs(np.linalg.det(h)) ** (1.0 / 3.0) * n ** (1.0 / 6.0)
+        np.testing.assert_allclose(XA[-3:], cf * np.eye(3), rtol=1e-15)
+        d = 1e-4 * cf
+        f = []
+        for s in (+1, -1):
+            X = XA.copy()
+            X[-3, 0] += s * d
+            f.append(orc.cf_eval(p, h, X)["Fg"][-3, 0])
+        stiff.append(-(f[0] - f[1]) / (2 * d))
+        # 1% uniform strain between endpoints against a 0.01 displacement of every atom
+        eps = np.diag([1.01, 1.0, 1.0])
+        _, XS = orc.build_endpoints(p, R, h, R @ eps, h @ eps)
+        _, XU = orc.build_endpoints(p, R, h, R + np.array([0.01, 0.0, 0.0]), h)
+        ratio.append(np.sum((XS - XA) ** 2) / np.sum((XU - XA) ** 2))
+    assert stiff[0] > 0
+    assert stiff[1] == pytest.approx(stiff[0], rel=1e-5)
+    assert ratio[1] == pytest.approx(ratio[0], rel=1e-9)
