@@ -65,7 +65,8 @@ typedef struct cfneb_params {
     double k_spring;        /* eV / A^2 */
     int climb_after;        /* climbing image from this step on; < 0: never */
     int cell_filter;        /* 0: cell fixed; 2: rotation-free cell filter (Eq. (17)) */
-    double cell_factor;     /* c_f, generalized cell coordinate c_f B; <= 0: n_atoms */
+    double cell_factor;     /* c_f, generalized cell coordinate c_f B;
+                               <= 0: |det h0|^(1/3) n_atoms^(1/6) */
     double b_force_scale;   /* factor on the lattice force D^-T V D^-1 / c_f (default 1) */
     double pressure_GPa;    /* hydrostatic pressure; images carry H = U + P Omega */
     /* FIRE */
@@ -174,6 +175,21 @@ int cfneb_energies(const cfneb_band* b, double* H, int cap, int* n_images, doubl
 /* Cartesian positions (n_atoms x 3) and cell (3x3) of current image k:
  * h = h0 D, R = R~ D with D = symsqrt(B). */
 int cfneb_get_image(const cfneb_band* b, int k, double* pos, double* cell);
+
+/* Relax one structure with the cell filter (Sec. II.C, which introduces the filter
+ * for relaxing lattice and positions together; band endpoints are such minima).
+ * FIRE, as in a band step, on the generalized coordinates (R~, c_f B) with the
+ * input cell as reference h0, driven by the generalized force (F D^T, G / c_f)
+ * without projection or springs, until the largest row norm is below f_tol or
+ * max_steps moves were made.  Potential, pressure, cell filter, cell factor and
+ * FIRE fields of p apply; image, spring, climbing-image and refine fields are
+ * ignored.  pos (n_atoms x 3) and cell (3x3) are host arrays, read, then
+ * overwritten with the relaxed R = R~ D and h = h0 D; on error they are left as
+ * they were.  workspace: >= cfneb_band_bytes(p, n_atoms, 3) device bytes,
+ * 256-byte aligned, free again on return.  *converged = 1 if f_tol was reached. */
+int cfneb_relax(const cfneb_params* p, int64_t n_atoms, const int32_t* types, double* pos, double* cell,
+                int max_steps, double f_tol, void* workspace, size_t workspace_bytes, void* hip_stream,
+                int* steps_done, double* fmax, int* converged);
 
 /* Checkpoint: generalized coordinates X and velocities v of the n_images images,
  * each (n_atoms + 3) x 3 row-major (rows of R~, then rows of c_f B), into arrays

@@ -158,7 +158,7 @@ __device__ void scalars_item(const BandDev& b, BandState* st)
         const double tt = a * a * d[0] + 2.0 * a * c * d[2] + c * c * d[1];
         const double nt = sqrt(fmax(tt, 0.0));
         double cp = 0.0, cm = 0.0;
-        if (nt > 0.0) {
+        if (nt > 0.0 && !b.relax) {
             const double ft = (a * d[3] + c * d[4]) / nt;
             const double s = (k == ci) ? -2.0 * ft : b.k_spring * (sqrt(d[0]) - sqrt(d[1])) - ft;
             cp = s * a / nt;

@@ -100,6 +100,7 @@ struct BandDev {
     double ts_A, ts_B, ts_l1, ts_l2, ts_bn, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
     double k_spring;
     int climb_after, cell_filter;
+    int relax;  // no tangent projection or springs: F_NEB = generalized force
     double cf, bscale, press;
     double dt0, dtmax, maxstep;
     int nmin;

@@ -162,7 +162,17 @@ int check_kernels(cfneb_band* b, const char* what)
     return CFNEB_OK;
 }
 
-void fill_dev(cfneb_band* b, void* ws)
+// Default c_f: |det h0|^(1/3) n^(1/6), the size-consistent Jacobian of the
+// generalized solid-state NEB (cell strain and atomic displacement weigh alike in
+// the band metric and have alike stiffness at every system size).
+double default_cell_factor(const double* h0, int n)
+{
+    const double det = h0[0] * (h0[4] * h0[8] - h0[5] * h0[7]) - h0[1] * (h0[3] * h0[8] - h0[5] * h0[6]) +
+                       h0[2] * (h0[3] * h0[7] - h0[4] * h0[6]);
+    return std::cbrt(std::fabs(det)) * std::pow(double(n), 1.0 / 6.0);
+}
+
+void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
 {
     const cfneb_params* p = &b->p;
     const Layout& L = b->L;
@@ -205,7 +215,9 @@ void fill_dev(cfneb_band* b, void* ws)
     d.k_spring = p->k_spring;
     d.climb_after = p->climb_after;
     d.cell_filter = p->cell_filter;
-    d.cf = p->cell_factor > 0.0 ? p->cell_factor : double(L.N);
+    for (int q = 0; q < 9; ++q) d.h0[q] = h0[q];
+    d.cf = p->cell_factor > 0.0 ? p->cell_factor : default_cell_factor(h0, L.N);
+    d.relax = relax;
     d.bscale = p->b_force_scale;
     d.press = p->pressure_GPa / kEvPerA3InGPa;
     d.dt0 = p->fire_dt0;
@@ -372,12 +384,14 @@ int cfneb_band_bytes(const cfneb_params* p, int64_t n_atoms, int max_images, siz
     return CFNEB_OK;
 }
 
-int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* types,
-                      const double* pos_init, const double* cell_init, const double* pos_final,
-                      const double* cell_final, void* workspace, size_t workspace_bytes,
-                      void* hip_stream, cfneb_band** out)
+}  // extern "C"
+
+namespace {
+
+int create_impl(const cfneb_params* p, int64_t n_atoms, const double* pos_init, const double* cell_init,
+                const double* pos_final, const double* cell_final, void* workspace,
+                size_t workspace_bytes, void* hip_stream, int relax, cfneb_band** out)
 {
-    (void)types;
     if (!out || !pos_init || !cell_init || !pos_final || !cell_final || !workspace) return CFNEB_EINVAL;
     *out = nullptr;
     int rc = validate(p, n_atoms);
@@ -397,8 +411,7 @@ int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* typ
     const char* ng = std::getenv("CFNEB_NO_GRAPH");
     b->use_graph = !(ng && ng[0] == '1');
     b->stream = static_cast<hipStream_t>(hip_stream);
-    fill_dev(b, workspace);
-    for (int q = 0; q < 9; ++q) b->d.h0[q] = cell_init[q];
+    fill_dev(b, workspace, cell_init, relax);
     auto bail = [&](int code) {
         cfneb_destroy(b);
         return code;
@@ -435,6 +448,45 @@ int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* typ
     if (b->host_state->err != 0) return bail(b->host_state->err);
     *out = b;
     return CFNEB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfneb_create_band(const cfneb_params* p, int64_t n_atoms, const int32_t* types,
+                      const double* pos_init, const double* cell_init, const double* pos_final,
+                      const double* cell_final, void* workspace, size_t workspace_bytes,
+                      void* hip_stream, cfneb_band** out)
+{
+    (void)types;
+    return create_impl(p, n_atoms, pos_init, cell_init, pos_final, cell_final, workspace, workspace_bytes,
+                       hip_stream, 0, out);
+}
+
+int cfneb_relax(const cfneb_params* p, int64_t n_atoms, const int32_t* types, double* pos, double* cell,
+                int max_steps, double f_tol, void* workspace, size_t workspace_bytes, void* hip_stream,
+                int* steps_done, double* fmax, int* converged)
+{
+    (void)types;
+    if (!p || !pos || !cell || max_steps < 0) return CFNEB_EINVAL;
+    // one moving image between two fixed copies of itself, no projection, no
+    // climbing image, no refinement: FIRE on (R~, c_f B) down the generalized force
+    cfneb_params q = *p;
+    q.n_images = 3;
+    q.max_images = 3;
+    q.min_images = 3;
+    q.climb_after = -1;
+    q.refine_every = 0;
+    cfneb_band* b = nullptr;
+    int rc = create_impl(&q, n_atoms, pos, cell, pos, cell, workspace, workspace_bytes, hip_stream, 1, &b);
+    if (rc != CFNEB_OK) return rc;
+    int conv = 0;
+    rc = cfneb_step(b, max_steps, f_tol, steps_done, fmax, &conv);
+    if (rc == CFNEB_OK) rc = cfneb_get_image(b, 1, pos, cell);
+    if (converged) *converged = conv;
+    cfneb_destroy(b);
+    return rc;
 }
 
 int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, double* fmax,

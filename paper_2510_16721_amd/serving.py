@@ -53,6 +53,7 @@ class Server:
         self.waiting = deque()
         self.done = []
         self.occupancy = []   # (time, active bands, bytes in use)
+        self.memory_waits = 0  # admissions deferred because the budget was full
 
     def _admit(self, now):
         while self.waiting and self.waiting[0].arrival <= now and len(self.active) < self.max_bands:
@@ -64,6 +65,7 @@ class Server:
                 self.done.append(req)
                 continue
             if self.in_use + req.bytes > self.budget:
+                self.memory_waits += 1
                 break
             self.waiting.popleft()
             e = req.endpoints
@@ -104,6 +106,8 @@ class Server:
             now = self.clock() - self.t0
             self._admit(now)
             if not self.active:
+                if not self.waiting:
+                    break  # the last requests were rejected at admission
                 # idle until the next arrival
                 nxt = self.waiting[0].arrival
                 while self.clock() - self.t0 < nxt:

@@ -149,6 +149,55 @@ def test_converged_barrier(fp64):
     np.testing.assert_allclose(ge["H"], ge["H"][::-1], rtol=0, atol=TOL_BARRIER)
 
 
+@pytest.mark.parametrize("name,fp64", [("lj_ragged", True), ("ts_diamond", False)])
+def test_endpoint_relaxation(name, fp64):
+    # cell-filter relaxation of both endpoints of a vacancy hop (vacancy relaxation and
+    # the cell's relaxation volume); the oracle and the device relax independently
+    import oracle
+    from paper_2510_16721_amd import cfneb
+    from gpu_cases import workload
+    w, kind = workload(name)
+    gp = cfneb.default_params(cfneb.CFNEB_LJ if kind == "lj" else cfneb.CFNEB_TERSOFF_C,
+                              force_fp64=1 if fp64 else 0)
+    op = oracle_params_like(kind)
+    n = w["n"]
+    for which in ("init", "final"):
+        pos, cell = w["pos_" + which], w["cell_" + which]
+        R, h, steps, fmax, conv = cfneb.relax(gp, pos, cell, 5000, 1e-4)
+        Ro, ho, so, fo = oracle.relax(op, pos, cell, 5000, 1e-4)
+        assert conv and fmax < 1e-4 and fo < 1e-4 and steps > 10
+        Eg = oracle.evaluate(op, R, h)[0]
+        Eo = oracle.evaluate(op, Ro, ho)[0]
+        E0 = oracle.evaluate(op, pos, cell)[0]
+        assert Eg < E0 and Eo < E0
+        assert abs(Eg - Eo) / n <= TOL_E_PER_ATOM
+        np.testing.assert_allclose(h, ho, rtol=0, atol=1e-4)
+        np.testing.assert_allclose(R, Ro, rtol=0, atol=2e-3)
+
+
+def test_converged_tersoff_barrier_from_relaxed_endpoints():
+    # Tersoff diamond vacancy hop (63 atoms), endpoints relaxed on each side, 9 images,
+    # climbing image from step 50, FP32 force arithmetic on the device
+    import oracle
+    from paper_2510_16721_amd import cfneb
+    from gpu_cases import workload
+    w, kind = workload("ts_diamond")
+    kw = dict(n_images=9, max_images=9, climb_after=50)
+    gp = cfneb.default_params(cfneb.CFNEB_TERSOFF_C, **kw)
+    op = oracle_params_like(kind, **kw)
+    ge = [cfneb.relax(gp, w["pos_" + s], w["cell_" + s], 5000, 1e-5)[:2] for s in ("init", "final")]
+    oe = [oracle.relax(op, w["pos_" + s], w["cell_" + s], 5000, 1e-5)[:2] for s in ("init", "final")]
+    g = cfneb.Band(gp, ge[0][0], ge[0][1], ge[1][0], ge[1][1])
+    o = oracle.Band(op, oe[0][0], oe[0][1], oe[1][0], oe[1][1])
+    gd, gf, gc = g.step(3000, 1e-3)
+    od, of, oc = o.step(3000, 1e-3)
+    assert gc and oc
+    gE, oE = g.energies(), o.energies()
+    assert abs(gE["barrier"] - oE["barrier"]) <= TOL_BARRIER
+    assert gE["ci"] == oE["ci"] == 4
+    np.testing.assert_allclose(gE["H"], oE["H"], rtol=0, atol=TOL_BARRIER)
+
+
 def test_refine_decision_and_midpoint_bit_exact():
     import oracle
     kw = dict(n_images=6, max_images=8, min_images=3, climb_after=-1)
