@@ -64,7 +64,11 @@ extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const d
         double T1[9], G[9];
         orc::matmul3(DinvT, Veff, T1);
         orc::matmul3(T1, Dinv, G);
-        for (int k = 0; k < 9; ++k) Fg[3 * n + k] = p->b_force_scale * G[k] / cf;
+        // B is symmetric (six coordinates), so its conjugate force is the symmetric
+        // part of D^-T V D^-1; V itself is symmetric only up to rounding
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                Fg[3 * n + 3 * r + c] = p->b_force_scale * (0.5 * (G[3 * r + c] + G[3 * c + r])) / cf;
     } else {
         for (int k = 0; k < 9; ++k) Fg[3 * n + k] = 0.0;
     }

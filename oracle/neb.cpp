@@ -23,6 +23,7 @@ struct Fire {
 
 struct NebCore {
     int M = 0, dim = 0, roww = 3;
+    int natoms = 0;  // leading atom rows of a periodic structure (0: none)
     std::vector<std::vector<double>> X, v, Fg, Fneb;
     std::vector<double> H;
     Fire fire{};
@@ -63,7 +64,22 @@ extern "C" void orc_tangent_coeffs(double Hm, double H0, double Hp, double* a, d
 
 namespace orc {
 
-// NEB forces on the moving images from X, H and the true generalized forces Fg.
+// A rigid translation of all atoms of a periodic structure changes no energy.  It is
+// removed from the atom rows of image differences and forces: each of the three
+// components has its mean over the atom rows subtracted (cell rows untouched).
+void remove_translation(std::vector<double>& a, int natoms)
+{
+    if (natoms <= 0) return;
+    for (int q = 0; q < 3; ++q) {
+        double s = 0.0;
+        for (int i = 0; i < natoms; ++i) s += a[3 * size_t(i) + q];
+        const double m = s / natoms;
+        for (int i = 0; i < natoms; ++i) a[3 * size_t(i) + q] -= m;
+    }
+}
+
+// NEB forces on the moving images from X, H and the true generalized forces Fg,
+// all taken modulo a rigid translation of the atoms.
 void neb_forces(NebCore& c, double k_spring, int climb_after)
 {
     const int M = c.M;
@@ -76,20 +92,23 @@ void neb_forces(NebCore& c, double k_spring, int climb_after)
                 best = c.H[k];
             }
     }
-    std::vector<double> tp(c.dim), tm(c.dim), tau(c.dim);
+    std::vector<double> tp(c.dim), tm(c.dim), tau(c.dim), F(c.dim);
     c.Fneb.assign(M, std::vector<double>(c.dim, 0.0));
     for (int k = 1; k <= M - 2; ++k) {
         for (int i = 0; i < c.dim; ++i) {
             tp[i] = c.X[k + 1][i] - c.X[k][i];
             tm[i] = c.X[k][i] - c.X[k - 1][i];
         }
+        F = c.Fg[k];
+        remove_translation(tp, c.natoms);
+        remove_translation(tm, c.natoms);
+        remove_translation(F, c.natoms);
         double a, b;
         orc_tangent_coeffs(c.H[k - 1], c.H[k], c.H[k + 1], &a, &b);
         for (int i = 0; i < c.dim; ++i) tau[i] = a * tp[i] + b * tm[i];
         const double nt = std::sqrt(dot(tau, tau));
         if (nt > 0.0)
             for (double& t : tau) t /= nt;
-        const auto& F = c.Fg[k];
         const double ft = dot(F, tau);
         auto& out = c.Fneb[k];
         if (k == c.ci) {
@@ -400,6 +419,7 @@ extern "C" orc_band* orc_band_create(const orc_params* p, int n, const int32_t* 
     auto& c = b->c;
     c.dim = 3 * (n + 3);
     c.roww = 3;
+    c.natoms = n;
     resize_images(b, M);
     std::vector<double> XA(c.dim), XB(c.dim);
     *err = orc_build_endpoints(p, n, pos_init, cell_init, pos_final, cell_final, XA.data(), XB.data());
@@ -630,6 +650,7 @@ extern "C" int orc_relax(const orc_params* p, int n, double* R, double* h, int m
     c.M = 3;
     c.dim = 3 * (n + 3);
     c.roww = 3;
+    c.natoms = n;
     double h0[9];
     for (int k = 0; k < 9; ++k) h0[k] = h[k];
     const double cf = orc::cell_factor_of(p, n, h0);
@@ -646,6 +667,7 @@ extern "C" int orc_relax(const orc_params* p, int n, double* R, double* h, int m
         const int rc = orc_cf_eval(p, n, h0, c.X[1].data(), &H, &E, Fg.data(), V, nullptr, nullptr, nullptr);
         if (rc != ORC_OK) return rc;
         c.Fneb[1] = Fg;
+        orc::remove_translation(c.Fneb[1], n);
         *fmax = orc::fmax_of(c);
         if (*fmax < f_tol) break;
         orc::fire_move(c, p->fire_dtmax, p->fire_maxstep, p->fire_nmin, p->fire_finc, p->fire_fdec,

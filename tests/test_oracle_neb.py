@@ -76,10 +76,19 @@ def test_projection_invariants_one_step(orc):
     H = np.array([b.image(k)["H"] for k in range(M)])
     ci = st["ci"]
     assert 0 < ci < M - 1 and H[ci] == H[1:-1].max()
+    n = b.n
+
+    def centred(a):
+        # differences and forces are taken modulo a rigid translation of the atoms
+        a = a.reshape(-1, 3).copy()
+        a[:n] -= a[:n].mean(axis=0)
+        return a.ravel()
+
     for k in range(1, M - 1):
         img = b.image(k)
-        Fg, Fn = img["Fg"].ravel(), img["Fneb"].ravel()
-        tp, tm = X[k + 1] - X[k], X[k] - X[k - 1]
+        Fg, Fn = centred(img["Fg"]), img["Fneb"].ravel()
+        np.testing.assert_allclose(Fn.reshape(-1, 3)[:n].sum(axis=0), 0.0, atol=1e-11)
+        tp, tm = centred(X[k + 1] - X[k]), centred(X[k] - X[k - 1])
         a, c = orc.tangent_coeffs(H[k - 1], H[k], H[k + 1])
         tau = a * tp + c * tm
         tau /= np.linalg.norm(tau)
@@ -94,6 +103,42 @@ def test_projection_invariants_one_step(orc):
             assert Fn @ tau == pytest.approx(spring, rel=1e-9, abs=1e-10)
             perp = Fn - (Fn @ tau) * tau
             np.testing.assert_allclose(perp, Fg - (Fg @ tau) * tau, atol=1e-10)
+
+
+def test_rigid_translation_of_an_endpoint_changes_no_neb_force(orc):
+    # a periodic band whose final endpoint is rigidly shifted is the same band: every
+    # image moves by a uniform translation, which the NEB forces ignore
+    w = W.fcc_vacancy_hop(2, 2, 2, 1.5496)
+    p = orc.default_params(orc.LJ, n_images=6, max_images=6, climb_after=0, k_spring=3.0)
+    shift = np.array([0.31, -0.17, 0.23])
+    out = []
+    for t in (np.zeros(3), shift):
+        b = orc.Band(p, w["pos_init"], w["cell_init"], w["pos_final"] + t, w["cell_final"])
+        X = b.get_state()["X"].copy()
+        # move the interior images off the straight line, identically in both bands
+        X[1:-1, :-3] += 0.05 * np.sin(np.arange(X[1:-1, :-3].size)).reshape(X[1:-1, :-3].shape)
+        b.set_state(X, np.zeros_like(X), 0.01, 0.1, 0, 1, 5)
+        assert b.step(1, f_tol=1e30)[0] == 0
+        out.append([b.image(k)["Fneb"] for k in range(1, 5)])
+        H = b.energies()["H"]
+    for f0, f1 in zip(*out):
+        np.testing.assert_allclose(f1, f0, rtol=0, atol=1e-9)
+    assert H[1:-1].max() > H[0]
+
+
+def test_cell_coordinates_stay_symmetric(orc):
+    # the lattice coordinates c_f B of every image stay an exactly symmetric matrix:
+    # the force on them has no antisymmetric part, which would be a zero-energy mode
+    w = W.graphite_to_diamond(2, 2, 3, seed=4, sigma=0.05)
+    p = orc.default_params(orc.TERSOFF, n_images=5, max_images=5, pressure_GPa=5.0)
+    b = orc.Band(p, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+    b.step(40)
+    X = b.get_state()["X"]
+    for k in range(X.shape[0]):
+        C = X[k, -3:]
+        np.testing.assert_array_equal(C, C.T)
+        Fc = b.image(k)["Fg"][-3:]
+        np.testing.assert_array_equal(Fc, Fc.T)
 
 
 def test_vacancy_hop_band_is_symmetric(orc):
