@@ -82,13 +82,23 @@ def cpu_baseline(w, kw, steps):
 def mix_params(entry):
     """LJ bands climb from step 50.  Tersoff diamond vacancy hops run without the climbing
     image: on this potential the symmetric midpoint of the hop is a ridge point, not a
-    first-order saddle, and a climbing image on a short band (even image count) leaves it
-    and drags its neighbours uphill."""
+    first-order saddle; a climbing image started on a short band leaves the valley and
+    drags its neighbours uphill.  The Tersoff bands start from a seeded displacement of
+    their interior images (mix_displacement), which lets them leave the ridge for the
+    lower path."""
     from paper_2510_16721_amd import cfneb
     lj = entry["kind"] == "lj"
     m = entry["n_images"]
     return cfneb.default_params(cfneb.CFNEB_LJ if lj else cfneb.CFNEB_TERSOFF_C, n_images=m,
                                 max_images=m, min_images=3, climb_after=50 if lj else -1)
+
+
+def mix_displacement(W, entry, seed):
+    """Tersoff bands start from a seeded zero-mean displacement of their interior images
+    (N(0, 0.01 A) per atom), LJ bands from the straight line."""
+    if entry["kind"] != "ts":
+        return None
+    return W.interior_noise(seed, entry["n_images"], entry["n"])
 
 
 _POOL = {}
@@ -127,10 +137,20 @@ def bench_batched(args):
     from paper_2510_16721_amd import cfneb
     f_tol = 0.01
     mix = relax_mix(W.band_mix(3, args.bands, 256, args.n_max or 32000, 5, 17))
+    for q, e in enumerate(mix):
+        e["displace"] = mix_displacement(W, e, [3, q])
+
+    def make(e):
+        w = e["endpoints"]
+        b = cfneb.Band(mix_params(e), w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+        if e["displace"] is not None:
+            b.displace_interior(e["displace"])
+        return b
+
     plain_t, plain = 0.0, []
     for q, e in enumerate(mix):
         w = e["endpoints"]
-        b = cfneb.Band(mix_params(e), w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+        b = make(e)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         done, fmax, conv = b.step(args.max_steps, f_tol)
@@ -141,11 +161,7 @@ def bench_batched(args):
         b.close()
         print(f"bench: plain band {q}: {w['n']} atoms, {e['n_images']} images, {done} steps, "
               f"converged {conv}", file=sys.stderr, flush=True)
-    bands = []
-    for e in mix:
-        w = e["endpoints"]
-        bands.append(cfneb.Band(mix_params(e), w["pos_init"], w["cell_init"], w["pos_final"],
-                                w["cell_final"]))
+    bands = [make(e) for e in mix]
     batch = cfneb.Batch(len(bands))
     slots = [batch.attach(b) for b in bands]
     steps = np.zeros(len(bands), dtype=np.int64)
@@ -153,7 +169,8 @@ def bench_batched(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while live:
-        s, conv, errs = batch.step(64, f_tol)
+        # never past any live band's step cap, so capped bands stop where they stop alone
+        s, conv, errs = batch.step(int(min(64, min(args.max_steps - steps[q] for q in live))), f_tol)
         for q in list(live):
             steps[q] += s[slots[q]]
             if conv[slots[q]] or errs[slots[q]] or steps[q] >= args.max_steps:
@@ -192,7 +209,9 @@ def bench_serving(args):
     mix = relax_mix(W.band_mix(4, args.requests, 500, args.n_max or 50000, 7, 21))
     arrivals = W.poisson_arrivals(4, len(mix), args.rate)
     reqs = [serving.Request(rid=q, arrival=float(arrivals[q]), params=mix_params(e),
-                            endpoints=e["endpoints"], n_atoms=e["n"]) for q, e in enumerate(mix)]
+                            endpoints=e["endpoints"], n_atoms=e["n"],
+                            displace=mix_displacement(W, e, [4, q]))
+            for q, e in enumerate(mix)]
     srv = serving.Server(hbm_budget_bytes=200e9, max_bands=64, f_tol=0.01, steps_per_call=32,
                          max_steps=args.max_steps)
     t0 = time.perf_counter()

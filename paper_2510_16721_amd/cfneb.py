@@ -289,6 +289,15 @@ class Band:
                                           _d(vv) if vv is not None else None, ctypes.byref(st)),
                     "cfneb_set_state")
 
+    def displace_interior(self, d):
+        """Add d (n_images - 2, n_atoms, 3) to the atom rows R~ of the interior images."""
+        st = self.get_state()
+        X = st["X"]
+        d = _f64(d, (X.shape[0] - 2, self.n, 3))
+        X[1:-1, :self.n] += d
+        self.set_state(X, st["v"], st["dt"], st["alpha"], st["n_pos"], st["fresh"], st["step"],
+                       st["ci"])
+
     def record_neb_force(self, on=True):
         self._check(lib().cfneb_record_neb_force(self._h, 1 if on else 0), "cfneb_record_neb_force")
 

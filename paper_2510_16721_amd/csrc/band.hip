@@ -5,6 +5,10 @@
 // because the improved tangent is a combination a tau+ + b tau-: with
 // t = (a tau+ + b tau-) / |.|, the projection Fg - (Fg.t) t + k (|tau+| - |tau-|) t
 // (or Fg - 2 (Fg.t) t for the climbing image) only needs ten dot products per image.
+// A rigid translation of the atoms costs no energy in a periodic cell, so tau+, tau-
+// and Fg are taken with their atom-row means removed; the centred dots follow from the
+// raw ones and the atom-row sums of tau+, tau-, Fg and v (twelve more sums), e.g.
+// |tau+ - m+|^2 = |tau+|^2 - N |m+|^2 over the N atom rows.
 // Pass 1 (k_band_dots) streams X, Fg and v once to get them; one block per band then
 // forms the coefficients and the band-global FIRE quantities P = F.v, |F|, |v| from
 // them; pass 2 (k_band_update) forms F_NEB row by row, the new velocity and the row
@@ -44,13 +48,16 @@ __global__ void k_begin_call(BatchDev bd, double f_tol, int only)
     st->err = 0;
 }
 
-// 10 dots per moving image: |t+|^2 |t-|^2 t+.t- F.t+ F.t- F.F F.v v.v v.t+ v.t-
+// 10 dots per moving image: |t+|^2 |t-|^2 t+.t- F.t+ F.t- F.F F.v v.v v.t+ v.t-,
+// then the atom-row sums of t+ (3), t- (3), F (3) and v (3).
 template <typename T>
 __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
     const int r = tile * CFNEB_TILE + threadIdx.x;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
-    double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double a[CFNEB_NDOT];
+#pragma unroll
+    for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
     if (r < b.N + 3) {
         const double* X0 = Xs(b, s0);
         const double* Xm = Xs(b, sm);
@@ -72,20 +79,26 @@ __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile
             a[7] += v * v;
             a[8] += v * tp;
             a[9] += v * tm;
+            if (r < b.N) {
+                a[10 + c] = tp;
+                a[13 + c] = tm;
+                a[16 + c] = f[c];
+                a[19 + c] = v;
+            }
         }
     }
-    block_sum<10>(a, lds);
+    block_sum<CFNEB_NDOT>(a, lds);
     if (threadIdx.x == 0) {
         // [image][dot][tile]: the reduction reads consecutive tiles
-        double* out = b.dotpart + size_t(k) * 10 * b.ntR + tile;
-        for (int q = 0; q < 10; ++q) out[size_t(q) * b.ntR] = a[q];
+        double* out = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR + tile;
+        for (int q = 0; q < CFNEB_NDOT; ++q) out[size_t(q) * b.ntR] = a[q];
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BatchDev bd, unsigned vmask)
 {
-    __shared__ double lds[4 * 10];
+    __shared__ double lds[(CFNEB_TILE / 64) * CFNEB_NDOT];
     ItemLoop loop(bd, KIND_ROW, 0);
     Item it;
     while (loop.next(it)) {
@@ -120,20 +133,21 @@ __device__ inline void tangent_coeffs(double Hm, double H0, double Hp, double& a
 // image, form the projection coefficients and the FIRE proposal.
 __device__ void scalars_item(const BandDev& b, BandState* st)
 {
-    __shared__ double dots[CFNEB_MAX_IMAGES][10];
+    __shared__ double dots[CFNEB_MAX_IMAGES][CFNEB_NDOT];
     __shared__ double H[CFNEB_MAX_IMAGES];
     __shared__ double contrib[3][CFNEB_MAX_IMAGES];
     __shared__ int ci_s;
     const int M = st->M;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int k = 1 + wid; k <= M - 2; k += int(blockDim.x) / 64) {
-        double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const double* part = b.dotpart + size_t(k) * 10 * b.ntR;
+        double a[CFNEB_NDOT];
+        for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
+        const double* part = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR;
         for (int t = lane; t < b.ntR; t += 64)
-            for (int q = 0; q < 10; ++q) a[q] += part[size_t(q) * b.ntR + t];
-        for (int q = 0; q < 10; ++q) a[q] = wave_sum(a[q]);
+            for (int q = 0; q < CFNEB_NDOT; ++q) a[q] += part[size_t(q) * b.ntR + t];
+        for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = wave_sum(a[q]);
         if (lane == 0)
-            for (int q = 0; q < 10; ++q) dots[k][q] = a[q];
+            for (int q = 0; q < CFNEB_NDOT; ++q) dots[k][q] = a[q];
     }
     // image enthalpies, loaded in parallel
     const int t = threadIdx.x;
@@ -152,7 +166,27 @@ __device__ void scalars_item(const BandDev& b, BandState* st)
     // one thread per moving image: tangent, projection coefficients, FIRE terms
     if (t >= 1 && t <= M - 2) {
         const int k = t, ci = ci_s;
-        const double* d = dots[k];
+        const double* raw = dots[k];
+        // atom-row means of tau+, tau-, Fg and v, then the dots of the centred vectors
+        const double N = double(b.N);
+        double m[12];
+        for (int q = 0; q < 12; ++q) m[q] = raw[10 + q] / N;
+        const double *mp = m, *mm = m + 3, *mf = m + 6, *mv = m + 9;
+        auto mdot = [&](const double* x, const double* y) {
+            return N * ((x[0] * y[0] + x[1] * y[1]) + x[2] * y[2]);
+        };
+        double d[10];
+        d[0] = raw[0] - mdot(mp, mp);
+        d[1] = raw[1] - mdot(mm, mm);
+        d[2] = raw[2] - mdot(mp, mm);
+        d[3] = raw[3] - mdot(mf, mp);
+        d[4] = raw[4] - mdot(mf, mm);
+        d[5] = raw[5] - mdot(mf, mf);
+        d[6] = raw[6] - mdot(mf, mv);
+        d[7] = raw[7];
+        d[8] = raw[8] - mdot(mv, mp);
+        d[9] = raw[9] - mdot(mv, mm);
+        for (int q = 0; q < 9; ++q) st->tmean[k][q] = m[q];
         double a, c;
         tangent_coeffs(H[k - 1], H[k], H[k + 1], a, c);
         const double tt = a * a * d[0] + 2.0 * a * c * d[2] + c * c * d[1];
@@ -233,6 +267,8 @@ __device__ void update_item(const BandDev& b, const BandState* st, int k, int ti
     if (r < b.N + 3) {
         const double cp = st->cplus[k], cm = st->cminus[k];
         const double cv = st->cv, cf = st->cf, dt = st->dt_new;
+        const double* mean = st->tmean[k];
+        const bool atom = r < b.N;
         const double* X0 = Xs(b, s0);
         const double* Xm = Xs(b, sm);
         const double* Xp = Xs(b, sp);
@@ -246,7 +282,13 @@ __device__ void update_item(const BandDev& b, const BandState* st, int k, int ti
         for (int c = 0; c < 3; ++c) {
             const size_t o = size_t(c) * b.ld + r;
             const double x = X0[o];
-            const double fn = f[c] + cp * (Xp[o] - x) + cm * (x - Xm[o]);
+            double tp = Xp[o] - x, tm = x - Xm[o], fc = f[c];
+            if (atom) {
+                tp -= mean[c];
+                tm -= mean[3 + c];
+                fc -= mean[6 + c];
+            }
+            const double fn = fc + cp * tp + cm * tm;
             const double vn = (cv * V[o] + cf * fn) + dt * fn;
             Vn[o] = vn;
             if (rec) FN[o] = fn;

@@ -29,6 +29,7 @@
 
 #define CFNEB_MAX_IMAGES 64
 #define CFNEB_TILE 256           // threads per block of every streaming kernel
+#define CFNEB_NDOT 22            // band-dot partial sums per moving image and row tile
 #define CFNEB_MAX_SHIFT 7        // packed shifts are 4-bit offset-binary
 #define CFNEB_J_BITS 20
 #define CFNEB_MAX_ATOMS (1 << CFNEB_J_BITS)
@@ -75,6 +76,8 @@ struct BandState {
     int record_fneb;
     // proposal of the current step (committed by the finalize kernel)
     double cplus[CFNEB_MAX_IMAGES], cminus[CFNEB_MAX_IMAGES];
+    // atom-row means of tau+, tau- and the generalized force (rigid translation)
+    double tmean[CFNEB_MAX_IMAGES][9];
     double cv, cf, dt_new, alpha_new;
     int n_pos_new;
     int move;
@@ -125,7 +128,7 @@ struct BandDev {
     ImageGeom* geom;
     ImageScal* scal;
     double* evpart;     // [slot][ntA][10]
-    double* dotpart;    // [k][ntR][10]
+    double* dotpart;    // [k][CFNEB_NDOT][ntR]
     double* maxpart;    // [k][ntR][2]
     uint64_t* refpart;  // [k][ntR][2]
     double* staging;    // endpoint upload and readout area

@@ -66,7 +66,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->geom = take(M * sizeof(ImageGeom));
     L->scal = take(M * sizeof(ImageScal));
     L->evpart = take(M * L->ntA * 10 * 8);
-    L->dotpart = take(M * L->ntR * 10 * 8);
+    L->dotpart = take(M * L->ntR * CFNEB_NDOT * 8);
     L->maxpart = take(M * L->ntR * 3 * 8);
     L->refpart = take(M * L->ntR * 2 * 8);
     L->staging = take((6 * N + 64) * 8);

@@ -24,6 +24,7 @@ class Request:
     params: object            # cfneb.Params
     endpoints: dict           # pos_init, cell_init, pos_final, cell_final
     n_atoms: int
+    displace: object = None   # optional initial displacement of the interior images
     bytes: int = 0
     # filled by the server
     admitted: float = -1.0
@@ -71,6 +72,8 @@ class Server:
             e = req.endpoints
             try:
                 band = cfneb.Band(req.params, e["pos_init"], e["cell_init"], e["pos_final"], e["cell_final"])
+                if req.displace is not None:
+                    band.displace_interior(req.displace)
             except cfneb.CfnebError as err:  # the request fails alone; the others go on
                 req.error = err.code
                 req.finished = self.clock() - self.t0

@@ -144,9 +144,14 @@ def test_converged_barrier(fp64):
     ge, oe = g.energies(), o.energies()
     assert abs(ge["barrier"] - oe["barrier"]) <= TOL_BARRIER
     assert ge["ci"] == oe["ci"] == 3
-    np.testing.assert_allclose(ge["H"], oe["H"], rtol=0, atol=TOL_BARRIER)
+    # the saddle (climbing image) and the fixed endpoints are unique; a non-climbing
+    # image is placed along the path only to within f_tol / k_spring = 1e-3 by the
+    # spring balance, so its enthalpy is compared to slope x 1e-3 (slope <= ~5 eV/A)
+    for k in (0, 3, 6):
+        assert abs(ge["H"][k] - oe["H"][k]) <= TOL_BARRIER, k
+    np.testing.assert_allclose(ge["H"], oe["H"], rtol=0, atol=5e-3)
     # the symmetric hop gives a symmetric profile
-    np.testing.assert_allclose(ge["H"], ge["H"][::-1], rtol=0, atol=TOL_BARRIER)
+    np.testing.assert_allclose(ge["H"], ge["H"][::-1], rtol=0, atol=5e-3)
 
 
 @pytest.mark.parametrize("name,fp64", [("lj_ragged", True), ("ts_diamond", False)])
@@ -195,7 +200,23 @@ def test_converged_tersoff_barrier_from_relaxed_endpoints():
     gE, oE = g.energies(), o.energies()
     assert abs(gE["barrier"] - oE["barrier"]) <= TOL_BARRIER
     assert gE["ci"] == oE["ci"] == 4
-    np.testing.assert_allclose(gE["H"], oE["H"], rtol=0, atol=TOL_BARRIER)
+    # non-climbing images: within slope x f_tol / k_spring (slope up to ~20 eV/A here)
+    np.testing.assert_allclose(gE["H"], oE["H"], rtol=0, atol=2e-2)
+
+
+def test_cell_rows_stay_symmetric_and_translation_free():
+    # FP32 Tersoff band under pressure: the cell block of every image stays an exactly
+    # symmetric matrix, and the NEB force has no net translation of the atoms
+    g, o, w, kind = make_pair("ts_small", n_images=6, max_images=6, pressure_GPa=5.0,
+                              oracle_too=False)
+    g.record_neb_force(True)
+    g.step(60)
+    X = g.get_state()["X"]
+    for k in range(X.shape[0]):
+        np.testing.assert_array_equal(X[k, -3:], X[k, -3:].T)
+    for k in range(1, X.shape[0] - 1):
+        Fn = g.image(k)["Fneb"]
+        assert np.abs(Fn[:-3].sum(axis=0)).max() <= 1e-9 * max(1.0, np.abs(Fn).max()) * g.n
 
 
 def test_refine_decision_and_midpoint_bit_exact():

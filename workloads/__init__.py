@@ -198,6 +198,18 @@ def band_mix(seed, count, n_lo, n_hi, m_lo, m_hi):
     return out
 
 
+def interior_noise(seed, n_images, n_atoms, sigma=0.01):
+    """Seeded N(0, sigma) displacements (Angstrom) of every atom of the n_images - 2
+    interior images of a band, shape (n_images - 2, n_atoms, 3), minus their mean.  They break the
+    mirror symmetry of a straight-line start, which on the Tersoff vacancy hop sits on
+    a ridge of the energy surface."""
+    rng = np.random.default_rng(seed)
+    d = rng.normal(0.0, sigma, size=(n_images - 2, n_atoms, 3))
+    # zero mean per image: no rigid translation, which costs no energy and which the
+    # springs of a periodic band would otherwise spread along the band
+    return d - d.mean(axis=1, keepdims=True)
+
+
 def poisson_arrivals(seed, count, rate):
     """Arrival times (s) of a Poisson stream of `count` requests at `rate` per second."""
     rng = np.random.default_rng(seed)
