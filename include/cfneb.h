@@ -80,6 +80,11 @@ typedef struct cfneb_params {
     int refine_every;
     int ins_num, ins_den, del_num, del_den;
     int nbr_cap;            /* neighbour entries per atom */
+    double nbr_skin;        /* candidate-list skin (A): pairs closer than rc + skin are kept
+                               as candidates and re-tested exactly every step; the candidates
+                               are rebuilt when atoms (relative to the affinely strained cell)
+                               or the cell moved enough that a pair could have crossed it.
+                               0: rebuild every step.  The neighbour set is the same. */
 } cfneb_params;
 
 /* Optimizer and band bookkeeping, for checkpoints and tests. */
@@ -96,8 +101,10 @@ typedef struct cfneb_fire_state {
 /* Phases of one band step, in launch order, for cfneb_step_profiled. */
 enum {
     CFNEB_PH_GEOM = 0,      /* per-image D = symsqrt(B), h, h^-1, bin grid */
-    CFNEB_PH_BINS,          /* R = R~ D, bin ids, counting sort, per-bin order */
-    CFNEB_PH_NLIST,         /* exact neighbour test, packed lists */
+    CFNEB_PH_SKIN,          /* R = R~ D, displacement since the last candidate build */
+    CFNEB_PH_BINS,          /* bin ids, counting sort, per-bin order (rebuilds only) */
+    CFNEB_PH_NLIST,         /* candidate pairs within rc + skin (rebuilds only) */
+    CFNEB_PH_FILTER,        /* exact neighbour test of the candidates, packed lists */
     CFNEB_PH_FORCE0,        /* LJ pair forces, or Tersoff zeta and bond orders */
     CFNEB_PH_FORCE1,        /* Tersoff dU_i/dr^ij per bond (unused for LJ) */
     CFNEB_PH_FORCE2,        /* Tersoff force gather (unused for LJ) */
@@ -117,7 +124,8 @@ typedef struct cfneb_band cfneb_band;
  * shifted; Tersoff 1988 carbon (R = 1.8, S = 2.1); 7 images, k = 1, climbing after
  * 50 steps, rotation-free filter, c_f = n_atoms; FIRE dt0 0.005 (LJ) / 0.05
  * (Tersoff), dtmax = 10 dt0, maxstep 0.1, Nmin 5, finc 1.1, fdec 0.5, alpha 0.1,
- * f_alpha 0.99; refine off with thresholds 9/4 and 1/4; nbr_cap 128 (LJ) / 16. */
+ * f_alpha 0.99; refine off with thresholds 9/4 and 1/4; nbr_cap 128 (LJ) / 16;
+ * nbr_skin 0.3. */
 int cfneb_params_default(int potential, cfneb_params* out);
 
 /* Device workspace bytes for a band of n_atoms atoms and up to max_images images

@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
         ("refine_every", ctypes.c_int),
         ("ins_num", ctypes.c_int), ("ins_den", ctypes.c_int),
         ("del_num", ctypes.c_int), ("del_den", ctypes.c_int),
-        ("nbr_cap", ctypes.c_int),
+        ("nbr_cap", ctypes.c_int), ("nbr_skin", ctypes.c_double),
     ]
 
 
@@ -60,8 +60,8 @@ class FireState(ctypes.Structure):
                 ("image_steps", ctypes.c_longlong)]
 
 
-PHASES = ["geom", "bins", "nlist", "force0", "force1", "force2", "reduce", "dots", "scalars",
-          "update", "finalize", "move", "refine"]
+PHASES = ["geom", "skin", "bins", "nlist", "filter", "force0", "force1", "force2", "reduce",
+          "dots", "scalars", "update", "finalize", "move", "refine"]
 
 
 _LIB = None

@@ -75,8 +75,10 @@ void launch_evaluate(const Launch& L, int all_images, hipStream_t s)
 {
     launch_plan(L, all_images, 0, s);
     launch_geom(L, all_images, s);
+    launch_skin(L, all_images, s);
     launch_bins(L, all_images, s);
     launch_list(L, all_images, s);
+    launch_filter(L, all_images, s);
     launch_force_stage(L, all_images, 0, s);
     launch_force_stage(L, all_images, 1, s);
     launch_image_reduce(L, all_images, s);

@@ -51,6 +51,19 @@ struct ImageGeom {
     int reach[3];
     int nbins;
     int err;
+    // strain since the last candidate build: h = h_ref (I + E), and |E|_F
+    double E[9];
+    double enorm;
+};
+
+// Candidate lists of one image slot (Verlet skin).  The candidates are every pair
+// closer than rc + skin at the build; a pair closer than rc now was a candidate if
+// 2 max_i |R_i - R_i,ref (I + E)| + (rc + skin) |E| < skin.
+struct SkinState {
+    double href[9], hrefinv[9];
+    unsigned long long dmax2;  // bits of max_i |R_i - R_i,ref (I + E)|^2 (>= 0 doubles order as integers)
+    int valid;                 // a candidate list exists for this slot
+    int rebuild;               // this step rebuilds it
 };
 
 struct ImageScal {
@@ -96,9 +109,10 @@ struct BandState {
 
 // Everything a kernel needs, passed by value.
 struct BandDev {
-    int N, ld, Mcap, ntA, ntR, nbcap, cap;
+    int N, ld, Mcap, ntA, ntR, nbcap, cap, ccap;
     int potential, fp64;
     double rc, rc2;
+    double skin, rcl, rcl2;  // candidate skin, list cutoff rc + skin and its square
     double lj_eps, lj_sig2, lj_eshift;
     double ts_A, ts_B, ts_l1, ts_l2, ts_bn, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
     double k_spring;
@@ -122,6 +136,10 @@ struct BandDev {
     struct BinAtom* bpos;
     uint32_t* nbr;
     int* ncnt;
+    uint32_t* cand;     // [slot][ccap][N] candidate entries, packed like nbr
+    int* ncand;         // [slot][N]
+    double* Rref;       // [slot][3][ld] positions at the candidate build
+    SkinState* skst;    // [slot]
     void* dvec;
     void* bo;
     void* P;
@@ -400,8 +418,10 @@ void launch_image_positions(const BandDev& b, int k, hipStream_t s);
 void launch_plan(const Launch& L, int all_images, int ignore_stop, hipStream_t s);
 void launch_begin_call(const Launch& L, double f_tol, int only, hipStream_t s);
 void launch_geom(const Launch& L, int all_images, hipStream_t s);
+void launch_skin(const Launch& L, int all_images, hipStream_t s);
 void launch_bins(const Launch& L, int all_images, hipStream_t s);
 void launch_list(const Launch& L, int all_images, hipStream_t s);
+void launch_filter(const Launch& L, int all_images, hipStream_t s);
 void launch_force_stage(const Launch& L, int all_images, int stage, hipStream_t s);
 void launch_tersoff_stage(const Launch& L, int all_images, int stage, hipStream_t s);
 void launch_image_reduce(const Launch& L, int all_images, hipStream_t s);

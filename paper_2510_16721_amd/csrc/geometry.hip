@@ -78,17 +78,18 @@ __device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
         const double cz = u[0] * v[1] - u[1] * v[0];
         g.w[k] = g.omega / sqrt(cx * cx + cy * cy + cz * cz);
     }
-    // Bins along fractional axis k have perpendicular width w_k / nb_k >= rc (1 + 1e-9),
-    // so a +-1 bin stencil holds every pair closer than rc.  Cells narrower than that
-    // get one bin and a stencil wide enough for all the periodic images needed.
+    // Bins along fractional axis k have perpendicular width w_k / nb_k >= rcl (1 + 1e-9),
+    // rcl = rc + skin the candidate cutoff, so a +-1 bin stencil holds every pair closer
+    // than rcl.  Cells narrower than that get one bin and a stencil wide enough for all
+    // the periodic images needed.
     for (int k = 0; k < 3; ++k) {
-        const double q = g.w[k] / (b.rc * (1.0 + 1e-9));
+        const double q = g.w[k] / (b.rcl * (1.0 + 1e-9));
         if (q >= 1.0) {
             g.nb[k] = int(fmin(floor(q), 1024.0));
             g.reach[k] = 1;
         } else {
             g.nb[k] = 1;
-            g.reach[k] = int(ceil(b.rc / g.w[k])) + 1;
+            g.reach[k] = int(ceil(b.rcl / g.w[k])) + 1;
         }
     }
     while (g.nb[0] * g.nb[1] * g.nb[2] > b.nbcap) {
@@ -119,6 +120,17 @@ __global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_geom(BatchDev bd, int all_
         if (!image_geometry(b, Xs(b, slot), g)) {
             g.err = 1;
             set_error(st, CFNEB_ECELL);
+        }
+        // strain since the candidate build: E = h_ref^-1 h - I
+        const SkinState& sk = b.skst[slot];
+        g.enorm = 0.0;
+        if (sk.valid) {
+            mm3(sk.hrefinv, g.h, g.E);
+            for (int q = 0; q < 3; ++q) g.E[4 * q] -= 1.0;
+            for (int q = 0; q < 9; ++q) g.enorm += g.E[q] * g.E[q];
+            g.enorm = sqrt(g.enorm);
+        } else {
+            for (int q = 0; q < 9; ++q) g.E[q] = 0.0;
         }
         b.geom[slot] = g;
     }

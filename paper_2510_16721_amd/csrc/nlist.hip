@@ -1,20 +1,30 @@
-// Per-image cell lists and full neighbour lists.
+// Per-image cell lists, candidate lists and full neighbour lists.
 //
 // The neighbours of atom i are every (j, n) != (i, 0) with
 //     r = (R_j - R_i) + ((n0 h_0 + n1 h_1) + n2 h_2),  (r_x r_x + r_y r_y) + r_z r_z < rc^2,
 // evaluated in FP64 with every operation rounded on its own (no contraction), on the
-// unwrapped positions R = R~ D.  Bins only generate candidates, so the set does not
-// depend on the binning.  This is the local environment of Sec. II.B, Eq. (4).
+// unwrapped positions R = R~ D.  This is the local environment of Sec. II.B, Eq. (4).
+//
+// Candidates (Verlet skin): a cell-list scan keeps every pair closer than
+// rcl = rc + skin; each step re-tests the candidates with the exact inclusion test
+// above, so the neighbour set is the one a full scan would give.  The candidates are
+// rebuilt when a pair could have come from outside rcl: with h = h_ref (I + E) and
+// d_i = |R_i - R_i,ref (I + E)|, a pair's separation at the build is at most
+// (r + d_i + d_j) / (1 - |E|), so 2 max d_i + rcl |E| < skin keeps the list complete.
 //
 // Kernels, in order (each a persistent walk over the items of every live band):
-//   k_bin_assign   R = R~ D, wrapped fractional coordinate, bin id; the count atomic
+//   k_skin_check   R = R~ D; max_i d_i^2 per image
+//   k_skin_decide  rebuild flag per image; a rebuild takes the current cell as reference
+//   k_bin_assign   (rebuilds) wrapped fractional coordinate, bin id; the count atomic
 //                  returns the atom's rank inside its bin
-//   k_bin_scan     exclusive prefix sum of the bin counts (one block per image,
-//                  4096 counts per pass, coalesced); zeroes the counts for the next step
-//   k_bin_scatter  atom -> bin-ordered 32-byte record (position, id, lattice image)
-//   k_bin_sort     sort each bin by atom id, so lists are deterministic
-//   k_nlist        stencil walk over bin-ordered records, exact inclusion test,
-//                  packed entry-major lists (entry e of atom i at [e][i])
+//   k_bin_scan     (rebuilds) exclusive prefix sum of the bin counts (one block per
+//                  image, 4096 counts per pass, coalesced); zeroes the counts
+//   k_bin_scatter  (rebuilds) atom -> bin-ordered 32-byte record (position, id, image)
+//   k_bin_sort     (rebuilds) sort each bin by atom id, so lists are deterministic
+//   k_cand         (rebuilds) stencil walk over bin-ordered records, pairs within rcl,
+//                  packed entry-major candidate lists; R_ref = R
+//   k_filter       exact test of every candidate, packed entry-major neighbour lists
+//                  (entry e of atom i at [e][i]) and, for Tersoff, the bond vectors
 #include <type_traits>
 
 #include "cfneb_dev.h"
@@ -31,7 +41,8 @@ __device__ inline long long pack_info(int j, int n0, int n1, int n2)
 __device__ inline int info_j(long long v) { return int(v & 0xFFFFF); }
 __device__ inline int info_n(long long v, int k) { return int((v >> (20 + 10 * k)) & 0x3FF) - 512; }
 
-__device__ void bin_assign_item(const BandDev& b, int slot, int i)
+// R = R~ D of atom i; d_i^2 against the strained reference when a list exists.
+__device__ double skin_check_item(const BandDev& b, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
     const double* X = Xs(b, slot);
@@ -42,6 +53,71 @@ __device__ void bin_assign_item(const BandDev& b, int slot, int i)
     R[i] = r[0];
     R[b.ld + i] = r[1];
     R[2 * size_t(b.ld) + i] = r[2];
+    if (!b.skst[slot].valid) return 0.0;
+    const double* Rr = b.Rref + size_t(slot) * slot_rows(b);
+    const double a[3] = {Rr[i], Rr[b.ld + i], Rr[2 * size_t(b.ld) + i]};
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double ref = a[c] + ((a[0] * g.E[c] + a[1] * g.E[3 + c]) + a[2] * g.E[6 + c]);
+        const double d = r[c] - ref;
+        d2 += d * d;
+    }
+    return d2;
+}
+
+__global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_images)
+{
+    __shared__ double lds[CFNEB_TILE / 64];
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const BandState* st = b.st;
+        if (band_stopped(st)) continue;  // uniform over the block
+        const int slot = st->slot[it.image];
+        const int i = it.tile * CFNEB_TILE + threadIdx.x;
+        double m[1] = {i < b.N ? skin_check_item(b, slot, i) : 0.0};
+        block_max<1>(m, lds);
+        if (threadIdx.x == 0 && m[0] > 0.0)
+            atomicMax(&b.skst[slot].dmax2, (unsigned long long)__double_as_longlong(m[0]));
+    }
+}
+
+// One block per band, one thread per image.
+__global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_skin_decide(BatchDev bd, int all_images)
+{
+    ItemLoop loop(bd, KIND_BAND, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        const int k = threadIdx.x;
+        if (band_stopped(st) || k >= b.Mcap || !image_active(st, k, all_images)) continue;
+        const int slot = st->slot[k];
+        SkinState& sk = b.skst[slot];
+        const ImageGeom& g = b.geom[slot];
+        bool rebuild = true;
+        if (b.skin > 0.0 && sk.valid) {
+            const double dmax = sqrt(__longlong_as_double((long long)sk.dmax2));
+            rebuild = !(2.0 * dmax + b.rcl * g.enorm < b.skin * (1.0 - 1e-6));
+        }
+        sk.dmax2 = 0ull;
+        sk.rebuild = rebuild ? 1 : 0;
+        if (rebuild) {
+            for (int q = 0; q < 9; ++q) {
+                sk.href[q] = g.h[q];
+                sk.hrefinv[q] = g.hinv[q];
+            }
+            sk.valid = 1;
+        }
+    }
+}
+
+__device__ void bin_assign_item(const BandDev& b, int slot, int i)
+{
+    const ImageGeom& g = b.geom[slot];
+    const double* R = Rs(b, slot);
+    const double r[3] = {R[i], R[b.ld + i], R[2 * size_t(b.ld) + i]};
     int bi[3], img[3];
     for (int q = 0; q < 3; ++q) {
         const double s = (r[0] * g.hinv[q] + r[1] * g.hinv[3 + q]) + r[2] * g.hinv[6 + q];
@@ -68,7 +144,9 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BatchDev bd, int all_
         const BandState* st = b.st;
         const int i = it.tile * CFNEB_TILE + threadIdx.x;
         if (band_stopped(st) || i >= b.N) continue;
-        bin_assign_item(b, st->slot[it.image], i);
+        const int slot = st->slot[it.image];
+        if (!b.skst[slot].rebuild) continue;
+        bin_assign_item(b, slot, i);
     }
 }
 
@@ -124,7 +202,9 @@ __global__ void __launch_bounds__(1024) k_bin_scan(BatchDev bd, int all_images)
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         if (band_stopped(b.st)) continue;  // uniform over the block
-        bin_scan_item(b, b.st->slot[it.image]);
+        const int slot = b.st->slot[it.image];
+        if (!b.skst[slot].rebuild) continue;  // uniform over the block
+        bin_scan_item(b, slot);
     }
 }
 
@@ -138,6 +218,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BatchDev bd, int all
         const int i = it.tile * CFNEB_TILE + threadIdx.x;
         if (band_stopped(st) || i >= b.N) continue;
         const int slot = st->slot[it.image];
+        if (!b.skst[slot].rebuild) continue;
         const int4 bi = b.binfo[size_t(slot) * b.N + i];
         const int pos = b.bstart[bin_base(b, slot) + bi.x] + bi.y;
         if (pos < 0 || pos >= b.N) continue;
@@ -161,7 +242,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_sort(BatchDev bd, int all_im
         const int bin = it.tile * CFNEB_TILE + threadIdx.x;
         if (band_stopped(st)) continue;
         const int slot = st->slot[it.image];
-        if (bin >= b.geom[slot].nbins) continue;
+        if (!b.skst[slot].rebuild || bin >= b.geom[slot].nbins) continue;
         const int* start = b.bstart + bin_base(b, slot);
         BinAtom* a = b.bpos + size_t(slot) * b.N;
         const int lo = start[bin], hi = min(start[bin + 1], b.N);
@@ -206,21 +287,23 @@ __device__ inline void wrap_bin(int v, int nb, int& a, int& m)
     }
 }
 
-template <typename T, bool STORE_BONDS>
-__device__ void nlist_item(const BandDev& b, BandState* st, int slot, int i)
+// Candidates of atom i: every (j, n) within rcl, in stencil order; R_ref = R.
+__device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
     const double* R = Rs(b, slot);
     const int* start = b.bstart + bin_base(b, slot);
     const BinAtom* bp = b.bpos + size_t(slot) * b.N;
     const size_t N = b.N;
-    uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
-    using T4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
-    T4* dvec = STORE_BONDS ? reinterpret_cast<T4*>(b.dvec) + size_t(slot) * b.cap * N : nullptr;
+    uint32_t* cand = b.cand + size_t(slot) * b.ccap * N;
 
     double h[9];
     for (int q = 0; q < 9; ++q) h[q] = g.h[q];
     const double ri[3] = {R[i], R[b.ld + i], R[2 * size_t(b.ld) + i]};
+    double* Rr = b.Rref + size_t(slot) * slot_rows(b);
+    Rr[i] = ri[0];
+    Rr[b.ld + i] = ri[1];
+    Rr[2 * size_t(b.ld) + i] = ri[2];
     const int4 me = b.binfo[size_t(slot) * N + i];
     const int im0 = (me.z & 0x3FF) - 512, im1 = ((me.z >> 10) & 0x3FF) - 512, im2 = ((me.z >> 20) & 0x3FF) - 512;
     const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];
@@ -260,35 +343,80 @@ __device__ void nlist_item(const BandDev& b, BandState* st, int slot, int i)
                     if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
                     double d[3];
                     const double rr = exact_r2(ri, a.x, a.y, a.z, h, n0, n1, n2, d);
-                    if (!(rr < b.rc2)) continue;
+                    if (!(rr < b.rcl2)) continue;
                     if (abs(n0) > CFNEB_MAX_SHIFT || abs(n1) > CFNEB_MAX_SHIFT || abs(n2) > CFNEB_MAX_SHIFT) {
                         bad_shift = true;
                         continue;
                     }
-                    if (cnt < b.cap) {
-                        nbr[size_t(cnt) * N + i] = pack_nbr(j, n0, n1, n2);
-                        if (STORE_BONDS) {
-                            T4 e;
-                            e.x = T(d[0]);
-                            e.y = T(d[1]);
-                            e.z = T(d[2]);
-                            e.w = T(sqrt(rr));
-                            dvec[size_t(cnt) * N + i] = e;
-                        }
-                    }
+                    if (cnt < b.ccap) cand[size_t(cnt) * N + i] = pack_nbr(j, n0, n1, n2);
                     ++cnt;
                 }
             }
         }
     }
-    b.ncnt[size_t(slot) * N + i] = cnt;
+    b.ncand[size_t(slot) * N + i] = min(cnt, b.ccap);
     if (bad_shift) set_error(st, CFNEB_ECELL);
+    if (cnt > b.ccap) set_error(st, CFNEB_ENEIGH);
+}
+
+__global__ void __launch_bounds__(CFNEB_TILE) k_cand(BatchDev bd, int all_images)
+{
+    ItemLoop loop(bd, KIND_ATOM, all_images);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        BandState* st = b.st;
+        const int i = it.tile * CFNEB_TILE + threadIdx.x;
+        if (band_stopped(st) || i >= b.N) continue;
+        const int slot = st->slot[it.image];
+        if (!b.skst[slot].rebuild) continue;
+        cand_item(b, st, slot, i);
+    }
+}
+
+// Exact test of atom i's candidates with the current R and h.
+template <typename T, bool STORE_BONDS>
+__device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
+{
+    const ImageGeom& g = b.geom[slot];
+    const double* R = Rs(b, slot);
+    const size_t N = b.N;
+    const uint32_t* cand = b.cand + size_t(slot) * b.ccap * N;
+    uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
+    using T4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+    T4* dvec = STORE_BONDS ? reinterpret_cast<T4*>(b.dvec) + size_t(slot) * b.cap * N : nullptr;
+    double h[9];
+    for (int q = 0; q < 9; ++q) h[q] = g.h[q];
+    const double ri[3] = {R[i], R[b.ld + i], R[2 * size_t(b.ld) + i]};
+    const int nc = b.ncand[size_t(slot) * N + i];
+    int cnt = 0;
+    for (int e = 0; e < nc; ++e) {
+        const uint32_t ent = cand[size_t(e) * N + i];
+        const int j = nbr_j(ent);
+        const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
+        double d[3];
+        const double rr = exact_r2(ri, R[j], R[b.ld + j], R[2 * size_t(b.ld) + j], h, n0, n1, n2, d);
+        if (!(rr < b.rc2)) continue;
+        if (cnt < b.cap) {
+            nbr[size_t(cnt) * N + i] = ent;
+            if (STORE_BONDS) {
+                T4 v;
+                v.x = T(d[0]);
+                v.y = T(d[1]);
+                v.z = T(d[2]);
+                v.w = T(sqrt(rr));
+                dvec[size_t(cnt) * N + i] = v;
+            }
+        }
+        ++cnt;
+    }
+    b.ncnt[size_t(slot) * N + i] = cnt;
     if (cnt > b.cap) set_error(st, CFNEB_ENEIGH);
 }
 
 // vmask: the band variants (potential, force precision) this launch serves
 template <typename T, bool STORE_BONDS>
-__global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BatchDev bd, int all_images, unsigned vmask)
+__global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_images, unsigned vmask)
 {
     ItemLoop loop(bd, KIND_ATOM, all_images);
     Item it;
@@ -298,8 +426,14 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_nlist(BatchDev bd, int all_image
         BandState* st = b.st;
         const int i = it.tile * CFNEB_TILE + threadIdx.x;
         if (band_stopped(st) || i >= b.N) continue;
-        nlist_item<T, STORE_BONDS>(b, st, st->slot[it.image], i);
+        filter_item<T, STORE_BONDS>(b, st, st->slot[it.image], i);
     }
+}
+
+void launch_skin(const Launch& L, int all_images, hipStream_t s)
+{
+    k_skin_check<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, all_images);
+    k_skin_decide<<<L.g[KIND_BAND], CFNEB_MAX_IMAGES, 0, s>>>(L.bd, all_images);
 }
 
 void launch_bins(const Launch& L, int all_images, hipStream_t s)
@@ -312,13 +446,18 @@ void launch_bins(const Launch& L, int all_images, hipStream_t s)
 
 void launch_list(const Launch& L, int all_images, hipStream_t s)
 {
+    k_cand<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, all_images);
+}
+
+void launch_filter(const Launch& L, int all_images, hipStream_t s)
+{
     const unsigned g = L.g[KIND_ATOM];
     const unsigned lj = L.variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_LJ64));
-    if (lj) k_nlist<double, false><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj);
+    if (lj) k_filter<double, false><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj);
     if (L.variants & (1u << VARIANT_TS32))
-        k_nlist<float, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS32);
+        k_filter<float, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS32);
     if (L.variants & (1u << VARIANT_TS64))
-        k_nlist<double, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS64);
+        k_filter<double, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS64);
 }
 
 }  // namespace cfneb

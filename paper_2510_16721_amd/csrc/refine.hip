@@ -213,6 +213,7 @@ __device__ void decide_item(const BandDev& b, BandState* st, int mode)
                     st->slot[kstar + 1] = fresh;
                     st->M = M + 1;
                     st->new_slot = fresh;
+                    b.skst[fresh].valid = 0;  // its candidate list is built at the next step
                     st->ins_a = a;
                     st->ins_b = c;
                     st->ins = kstar + 1;

@@ -22,8 +22,8 @@ constexpr double kEvPerA3InGPa = 160.21766208;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    int N, ld, Mcap, ntA, ntR, nbcap, cap, fp64, tersoff;
-    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, dvec, bo, P, geom, scal,
+    int N, ld, Mcap, ntA, ntR, nbcap, cap, ccap, fp64, tersoff;
+    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, P, geom, scal,
         evpart, dotpart, maxpart, refpart, staging, state, table, live, plan, total;
 };
 
@@ -39,6 +39,12 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->ntR = (L->N + 3 + CFNEB_TILE - 1) / CFNEB_TILE;
     L->nbcap = L->N + 64;
     L->cap = p->nbr_cap;
+    {
+        // candidates within rc + skin: the neighbour capacity scaled by the volume ratio
+        const double rc = p->potential == CFNEB_LJ ? p->lj_rc : p->ts_S;
+        const double ratio = (rc + p->nbr_skin) / rc;
+        L->ccap = int(std::ceil(1.25 * p->nbr_cap * ratio * ratio * ratio));
+    }
     L->fp64 = p->force_fp64 ? 1 : 0;
     L->tersoff = (p->potential == CFNEB_TERSOFF_C) ? 1 : 0;
     const size_t M = size_t(L->Mcap), N = size_t(L->N), rows = 3 * size_t(L->ld);
@@ -60,6 +66,10 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->bpos = take(M * N * sizeof(BinAtom));
     L->nbr = take(M * size_t(L->cap) * N * 4);
     L->ncnt = take(M * N * 4);
+    L->cand = take(M * size_t(L->ccap) * N * 4);
+    L->ncand = take(M * N * 4);
+    L->Rref = take(M * rows * 8);
+    L->skin = take(M * sizeof(SkinState));
     L->dvec = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
     L->bo = take(L->tersoff ? M * size_t(L->cap) * N * 2 * tsz : 0);
     L->P = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
@@ -185,6 +195,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.ntR = L.ntR;
     d.nbcap = L.nbcap;
     d.cap = L.cap;
+    d.ccap = L.ccap;
     d.potential = p->potential;
     d.fp64 = L.fp64;
     if (p->potential == CFNEB_LJ) {
@@ -193,6 +204,9 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
         d.rc = p->ts_S;
     }
     d.rc2 = d.rc * d.rc;
+    d.skin = p->nbr_skin;
+    d.rcl = d.rc + d.skin;
+    d.rcl2 = d.rcl * d.rcl;
     d.lj_eps = p->lj_eps;
     d.lj_sig2 = p->lj_sigma * p->lj_sigma;
     if (p->lj_shift) {
@@ -247,6 +261,10 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.bpos = reinterpret_cast<BinAtom*>(base + L.bpos);
     d.nbr = reinterpret_cast<uint32_t*>(base + L.nbr);
     d.ncnt = reinterpret_cast<int*>(base + L.ncnt);
+    d.cand = reinterpret_cast<uint32_t*>(base + L.cand);
+    d.ncand = reinterpret_cast<int*>(base + L.ncand);
+    d.Rref = reinterpret_cast<double*>(base + L.Rref);
+    d.skst = reinterpret_cast<SkinState*>(base + L.skin);
     d.dvec = L.tersoff ? base + L.dvec : nullptr;
     d.bo = L.tersoff ? base + L.bo : nullptr;
     d.P = L.tersoff ? base + L.P : nullptr;
@@ -278,6 +296,7 @@ int validate(const cfneb_params* p, int64_t n_atoms)
     if (p->min_images < 3) return CFNEB_EINVAL;
     if (p->cell_filter != 0 && p->cell_filter != 2) return CFNEB_EINVAL;
     if (p->nbr_cap < 1 || p->nbr_cap > 1024) return CFNEB_EINVAL;
+    if (!(p->nbr_skin >= 0.0) || !(p->nbr_skin <= 2.0)) return CFNEB_EINVAL;
     if (!(p->fire_dt0 > 0.0) || !(p->fire_maxstep > 0.0)) return CFNEB_EINVAL;
     if (p->refine_every < 0 || p->ins_num < 0 || p->ins_den < 1 || p->del_num < 0 || p->del_den < 1)
         return CFNEB_EINVAL;
@@ -370,6 +389,7 @@ int cfneb_params_default(int potential, cfneb_params* out)
     p.del_num = 1;
     p.del_den = 4;
     p.nbr_cap = potential == CFNEB_LJ ? 128 : 16;
+    p.nbr_skin = 0.3;
     return CFNEB_OK;
 }
 
@@ -546,8 +566,10 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
                 launch_plan(d, 0, 0, s);
                 launch_geom(d, 0, s);
                 break;
+            case CFNEB_PH_SKIN: launch_skin(d, 0, s); break;
             case CFNEB_PH_BINS: launch_bins(d, 0, s); break;
             case CFNEB_PH_NLIST: launch_list(d, 0, s); break;
+            case CFNEB_PH_FILTER: launch_filter(d, 0, s); break;
             case CFNEB_PH_FORCE0: launch_force_stage(d, 0, 0, s); break;
             case CFNEB_PH_FORCE1: launch_force_stage(d, 0, 1, s); break;
             case CFNEB_PH_FORCE2: launch_force_stage(d, 0, 2, s); break;
@@ -696,6 +718,8 @@ int cfneb_set_state(cfneb_band* b, int n_images, const double* X, const double* 
         HIP_TRY(b, hipMemcpy(b->d.V + size_t(k) * 3 * ld, slab.data(), slab.size() * 8, hipMemcpyHostToDevice));
         std::fill(slab.begin(), slab.end(), 0.0);
     }
+    // new positions: every candidate list is rebuilt at the evaluation below
+    HIP_TRY(b, hipMemset(b->d.skst, 0, size_t(b->L.Mcap) * sizeof(SkinState)));
     BandState& st = *b->host_state;
     st.M = n_images;
     for (int k = 0; k < CFNEB_MAX_IMAGES; ++k) st.slot[k] = k < b->L.Mcap ? k : 0;

@@ -34,6 +34,10 @@ def workload(name):
     raise KeyError(name)
 
 
+# parameters of the device's data structures only (no effect on the results)
+DEVICE_ONLY = ("nbr_cap", "nbr_skin")
+
+
 def make_pair(name, fp64=False, oracle_too=True, **kw):
     import oracle
     from paper_2510_16721_amd import cfneb
@@ -44,7 +48,7 @@ def make_pair(name, fp64=False, oracle_too=True, **kw):
     o = None
     if oracle_too:
         op = oracle.default_params(oracle.LJ if kind == "lj" else oracle.TERSOFF,
-                                   **{k: v for k, v in kw.items() if k != "nbr_cap"})
+                                   **{k: v for k, v in kw.items() if k not in DEVICE_ONLY})
         o = oracle.Band(op, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
     return g, o, w, kind
 
@@ -52,7 +56,7 @@ def make_pair(name, fp64=False, oracle_too=True, **kw):
 def oracle_params_like(kind, **kw):
     import oracle
     return oracle.default_params(oracle.LJ if kind == "lj" else oracle.TERSOFF,
-                                 **{k: v for k, v in kw.items() if k != "nbr_cap"})
+                                 **{k: v for k, v in kw.items() if k not in DEVICE_ONLY})
 
 
 def sort_entries(ent):

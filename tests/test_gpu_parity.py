@@ -219,6 +219,31 @@ def test_cell_rows_stay_symmetric_and_translation_free():
         assert np.abs(Fn[:-3].sum(axis=0)).max() <= 1e-9 * max(1.0, np.abs(Fn).max()) * g.n
 
 
+@pytest.mark.parametrize("name,skin", [("ts_small", 0.3), ("ts_small", 0.01), ("lj_ragged", 0.3),
+                                       ("lj_ragged", 0.02)])
+def test_candidate_lists_give_the_full_scan_sets(name, skin):
+    # Verlet-skin candidates re-tested exactly every step: after every few steps the
+    # neighbour sets equal those of a band that rebuilds from the cell list every
+    # step (skin 0), and both equal the oracle's sets; the trajectories agree to
+    # rounding (only the summation order of the forces differs)
+    import oracle
+    kw = dict(n_images=5, max_images=5, fp64=True, climb_after=5)
+    a = make_pair(name, oracle_too=False, nbr_skin=skin, **kw)[0]
+    b = make_pair(name, oracle_too=False, nbr_skin=0.0, **kw)[0]
+    rc = 2.5 if name.startswith("lj") else 2.1
+    for rnd in range(4):
+        a.step(8)
+        b.step(8)
+        for k in range(1, 4):
+            ca, ea = a.neighbours(k)
+            cb, eb = b.neighbours(k)
+            np.testing.assert_array_equal(ca, cb)
+            for i in range(a.n):
+                np.testing.assert_array_equal(sort_entries(ea[i]), sort_entries(eb[i]))
+        np.testing.assert_allclose(a.get_state()["X"], b.get_state()["X"], rtol=0, atol=1e-9)
+    _assert_lists_equal(a, 2, rc)
+
+
 def test_refine_decision_and_midpoint_bit_exact():
     import oracle
     kw = dict(n_images=6, max_images=8, min_images=3, climb_after=-1)
