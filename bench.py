@@ -325,10 +325,13 @@ def main():
     roof["mean_bonds_per_atom"] = mean_bonds
 
     if args.copy_calibration_mib > 0:
+        # one elementwise kernel that reads and writes exactly this many MiB: the
+        # scale of the FETCH_SIZE / WRITE_SIZE counters
         nb = args.copy_calibration_mib * 2**20
-        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
 

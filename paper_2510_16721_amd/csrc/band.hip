@@ -49,20 +49,22 @@ __global__ void k_begin_call(BatchDev bd, double f_tol, int only)
 }
 
 // 10 dots per moving image: |t+|^2 |t-|^2 t+.t- F.t+ F.t- F.F F.v v.v v.t+ v.t-,
-// then the atom-row sums of t+ (3), t- (3), F (3) and v (3).
+// then the atom-row sums of t+ (3), t- (3), F (3) and v (3).  An item is 1024 rows,
+// four per thread (rows tile*1024 + q*256 + thread, so every load is coalesced).
 template <typename T>
 __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
-    const int r = tile * CFNEB_TILE + threadIdx.x;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double a[CFNEB_NDOT];
 #pragma unroll
     for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
-    if (r < b.N + 3) {
-        const double* X0 = Xs(b, s0);
-        const double* Xm = Xs(b, sm);
-        const double* Xp = Xs(b, sp);
-        const double* V = Vs(b, st->vcur, s0);
+    const double* X0 = Xs(b, s0);
+    const double* Xm = Xs(b, sm);
+    const double* Xp = Xs(b, sp);
+    const double* V = Vs(b, st->vcur, s0);
+    for (int q4 = 0; q4 < CFNEB_TILE4 / CFNEB_TILE; ++q4) {
+        const int r = tile * CFNEB_TILE4 + q4 * CFNEB_TILE + threadIdx.x;
+        if (r >= b.N + 3) break;
         double f[3];
         gen_force_row<T>(b, s0, r, f);
         for (int c = 0; c < 3; ++c) {
@@ -80,18 +82,18 @@ __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile
             a[8] += v * tp;
             a[9] += v * tm;
             if (r < b.N) {
-                a[10 + c] = tp;
-                a[13 + c] = tm;
-                a[16 + c] = f[c];
-                a[19 + c] = v;
+                a[10 + c] += tp;
+                a[13 + c] += tm;
+                a[16 + c] += f[c];
+                a[19 + c] += v;
             }
         }
     }
     block_sum<CFNEB_NDOT>(a, lds);
     if (threadIdx.x == 0) {
         // [image][dot][tile]: the reduction reads consecutive tiles
-        double* out = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR + tile;
-        for (int q = 0; q < CFNEB_NDOT; ++q) out[size_t(q) * b.ntR] = a[q];
+        double* out = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4 + tile;
+        for (int q = 0; q < CFNEB_NDOT; ++q) out[size_t(q) * b.ntR4] = a[q];
     }
 }
 
@@ -99,12 +101,34 @@ template <typename T>
 __global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BatchDev bd, unsigned vmask)
 {
     __shared__ double lds[(CFNEB_TILE / 64) * CFNEB_NDOT];
-    ItemLoop loop(bd, KIND_ROW, 0);
+    ItemLoop loop(bd, KIND_ROW4, 0);
     Item it;
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         if (!((vmask >> band_variant(b)) & 1u) || band_stopped(b.st)) continue;  // uniform
         dots_item<T>(b, b.st, it.image, it.tile, lds);
+    }
+}
+
+// One block per moving image: the image's tile partials, in a fixed order.
+__global__ void __launch_bounds__(CFNEB_TILE) k_band_dots_reduce(BatchDev bd)
+{
+    __shared__ double lds[(CFNEB_TILE / 64) * CFNEB_NDOT];
+    ItemLoop loop(bd, KIND_IMAGE, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (band_stopped(b.st)) continue;  // uniform over the block
+        const int k = it.image;
+        double a[CFNEB_NDOT];
+#pragma unroll
+        for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
+        const double* part = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4;
+        for (int t = threadIdx.x; t < b.ntR4; t += CFNEB_TILE)
+            for (int q = 0; q < CFNEB_NDOT; ++q) a[q] += part[size_t(q) * b.ntR4 + t];
+        block_sum<CFNEB_NDOT>(a, lds);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < CFNEB_NDOT; ++q) b.dotred[size_t(k) * CFNEB_NDOT + q] = a[q];
     }
 }
 
@@ -138,17 +162,8 @@ __device__ void scalars_item(const BandDev& b, BandState* st)
     __shared__ double contrib[3][CFNEB_MAX_IMAGES];
     __shared__ int ci_s;
     const int M = st->M;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = 1 + wid; k <= M - 2; k += int(blockDim.x) / 64) {
-        double a[CFNEB_NDOT];
-        for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
-        const double* part = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR;
-        for (int t = lane; t < b.ntR; t += 64)
-            for (int q = 0; q < CFNEB_NDOT; ++q) a[q] += part[size_t(q) * b.ntR + t];
-        for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = wave_sum(a[q]);
-        if (lane == 0)
-            for (int q = 0; q < CFNEB_NDOT; ++q) dots[k][q] = a[q];
-    }
+    for (int e = threadIdx.x; e < (M - 2) * CFNEB_NDOT; e += int(blockDim.x))
+        dots[1 + e / CFNEB_NDOT][e % CFNEB_NDOT] = b.dotred[CFNEB_NDOT + size_t(e)];
     // image enthalpies, loaded in parallel
     const int t = threadIdx.x;
     if (t < M) H[t] = b.scal[st->slot[t]].H;
@@ -257,25 +272,26 @@ __global__ void __launch_bounds__(1024) k_band_scalars(BatchDev bd)
 }
 
 // F_NEB per row, v' = (cv v + cf F_NEB) + dt' F_NEB into the other buffer, and the
-// row maxima of |F_NEB| and |dt' v'|.
+// row maxima of |F_NEB| and |dt' v'|; 1024 rows per item, four per thread.
 template <typename T>
 __device__ void update_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
-    const int r = tile * CFNEB_TILE + threadIdx.x;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double m[3] = {0.0, 0.0, 0.0};  // max |F_NEB row|^2, max |dr row|^2, non-finite flag
-    if (r < b.N + 3) {
-        const double cp = st->cplus[k], cm = st->cminus[k];
-        const double cv = st->cv, cf = st->cf, dt = st->dt_new;
-        const double* mean = st->tmean[k];
+    const double cp = st->cplus[k], cm = st->cminus[k];
+    const double cv = st->cv, cf = st->cf, dt = st->dt_new;
+    const double* mean = st->tmean[k];
+    const double* X0 = Xs(b, s0);
+    const double* Xm = Xs(b, sm);
+    const double* Xp = Xs(b, sp);
+    const double* V = Vs(b, st->vcur, s0);
+    double* Vn = Vs(b, st->vcur ^ 1, s0);
+    double* FN = b.FN + size_t(s0) * slot_rows(b);
+    const int rec = st->record_fneb;
+    for (int q4 = 0; q4 < CFNEB_TILE4 / CFNEB_TILE; ++q4) {
+        const int r = tile * CFNEB_TILE4 + q4 * CFNEB_TILE + threadIdx.x;
+        if (r >= b.N + 3) break;
         const bool atom = r < b.N;
-        const double* X0 = Xs(b, s0);
-        const double* Xm = Xs(b, sm);
-        const double* Xp = Xs(b, sp);
-        const double* V = Vs(b, st->vcur, s0);
-        double* Vn = Vs(b, st->vcur ^ 1, s0);
-        double* FN = b.FN + size_t(s0) * slot_rows(b);
-        const int rec = st->record_fneb;
         double f[3];
         gen_force_row<T>(b, s0, r, f);
         double f2 = 0.0, v2 = 0.0;
@@ -296,16 +312,16 @@ __device__ void update_item(const BandDev& b, const BandState* st, int k, int ti
             const double dr = dt * vn;
             v2 += dr * dr;
         }
-        m[0] = f2;
-        m[1] = v2;
-        m[2] = (isfinite(f2) && isfinite(v2)) ? 0.0 : 1.0;
+        m[0] = fmax(m[0], f2);
+        m[1] = fmax(m[1], v2);
+        if (!(isfinite(f2) && isfinite(v2))) m[2] = 1.0;
     }
     block_max<3>(m, lds);
     if (threadIdx.x == 0) {
-        double* out = b.maxpart + size_t(k) * 3 * b.ntR + tile;  // [image][q][tile]
+        double* out = b.maxpart + size_t(k) * 3 * b.ntR4 + tile;  // [image][q][tile]
         out[0] = m[0];
-        out[b.ntR] = m[1];
-        out[2 * size_t(b.ntR)] = m[2];
+        out[b.ntR4] = m[1];
+        out[2 * size_t(b.ntR4)] = m[2];
     }
 }
 
@@ -313,7 +329,7 @@ template <typename T>
 __global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BatchDev bd, unsigned vmask)
 {
     __shared__ double lds[4 * 3];
-    ItemLoop loop(bd, KIND_ROW, 0);
+    ItemLoop loop(bd, KIND_ROW4, 0);
     Item it;
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
@@ -327,13 +343,13 @@ __device__ void finalize_item(const BandDev& b, BandState* st, double* lds)
 {
     const int M = st->M;
     double m[3] = {0.0, 0.0, 0.0};
-    const int total = (M - 2) * b.ntR;
+    const int total = (M - 2) * b.ntR4;
     for (int t = threadIdx.x; t < total; t += int(blockDim.x)) {
-        const int k = 1 + t / b.ntR, tile = t % b.ntR;
-        const double* p = b.maxpart + size_t(k) * 3 * b.ntR + tile;
+        const int k = 1 + t / b.ntR4, tile = t % b.ntR4;
+        const double* p = b.maxpart + size_t(k) * 3 * b.ntR4 + tile;
         m[0] = fmax(m[0], p[0]);
-        m[1] = fmax(m[1], p[b.ntR]);
-        m[2] = fmax(m[2], p[2 * size_t(b.ntR)]);
+        m[1] = fmax(m[1], p[b.ntR4]);
+        m[2] = fmax(m[2], p[2 * size_t(b.ntR4)]);
     }
     block_max<3>(m, lds);
     if (threadIdx.x != 0) return;
@@ -417,16 +433,17 @@ void launch_begin_call(const Launch& L, double f_tol, int only, hipStream_t s)
 
 void launch_dots(const Launch& L, hipStream_t s)
 {
-    const unsigned g = L.g[KIND_ROW];
+    const unsigned g = L.g[KIND_ROW4];
     if (f32_mask(L.variants)) k_band_dots<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, f32_mask(L.variants));
     if (f64_mask(L.variants)) k_band_dots<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, f64_mask(L.variants));
+    k_band_dots_reduce<<<L.g[KIND_IMAGE], CFNEB_TILE, 0, s>>>(L.bd);
 }
 
 void launch_scalars(const Launch& L, hipStream_t s) { k_band_scalars<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd); }
 
 void launch_update(const Launch& L, hipStream_t s)
 {
-    const unsigned g = L.g[KIND_ROW];
+    const unsigned g = L.g[KIND_ROW4];
     if (f32_mask(L.variants)) k_band_update<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, f32_mask(L.variants));
     if (f64_mask(L.variants)) k_band_update<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, f64_mask(L.variants));
 }

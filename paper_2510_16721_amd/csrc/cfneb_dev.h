@@ -29,6 +29,7 @@
 
 #define CFNEB_MAX_IMAGES 64
 #define CFNEB_TILE 256           // threads per block of every streaming kernel
+#define CFNEB_TILE4 1024         // rows (atoms) of a streaming item with 4 per thread
 #define CFNEB_NDOT 22            // band-dot partial sums per moving image and row tile
 #define CFNEB_MAX_SHIFT 7        // packed shifts are 4-bit offset-binary
 #define CFNEB_J_BITS 20
@@ -109,7 +110,7 @@ struct BandState {
 
 // Everything a kernel needs, passed by value.
 struct BandDev {
-    int N, ld, Mcap, ntA, ntR, nbcap, cap, ccap;
+    int N, ld, Mcap, ntA, ntR, ntR4, nbcap, cap, ccap;
     int potential, fp64;
     double rc, rc2;
     double skin, rcl, rcl2;  // candidate skin, list cutoff rc + skin and its square
@@ -146,8 +147,9 @@ struct BandDev {
     ImageGeom* geom;
     ImageScal* scal;
     double* evpart;     // [slot][ntA][10]
-    double* dotpart;    // [k][CFNEB_NDOT][ntR]
-    double* maxpart;    // [k][ntR][2]
+    double* dotpart;    // [k][CFNEB_NDOT][ntR4]
+    double* dotred;     // [k][CFNEB_NDOT] reduced band dots
+    double* maxpart;    // [k][3][ntR4]
     uint64_t* refpart;  // [k][ntR][2]
     double* staging;    // endpoint upload and readout area
     BandState* st;
@@ -161,7 +163,9 @@ __device__ inline double* Vs(const BandDev& b, int buf, int slot)
 {
     return b.V + (size_t(buf) * b.Mcap + slot) * slot_rows(b);
 }
-__device__ inline double* Rs(const BandDev& b, int slot) { return b.R + size_t(slot) * slot_rows(b); }
+// Cartesian positions R = R~ D, one 32-byte record (x, y, z, 0) per atom, so a
+// neighbour's position is one aligned load.
+__device__ inline double4* Rs(const BandDev& b, int slot) { return reinterpret_cast<double4*>(b.R) + size_t(slot) * b.ld; }
 
 __device__ inline uint32_t pack_nbr(int j, int n0, int n1, int n2)
 {
@@ -203,6 +207,8 @@ enum ItemKind {
     KIND_IVAL,      // 256-row tiles x intervals between consecutive images
     KIND_SLOTROW,   // 256-row tiles x every image slot of the capacity
     KIND_BAND,      // one item per band
+    KIND_ATOM4,     // 1024-atom tiles x images (4 atoms per thread)
+    KIND_ROW4,      // 1024-row tiles x images (4 rows per thread)
     NKIND
 };
 
@@ -213,6 +219,10 @@ struct BatchDev {
     int cap;
 };
 
+// Set by the skin decision when any image of any band rebuilds its candidates this
+// step (cleared by the plan kernel); the rebuild kernels return at once without it.
+__device__ inline int* rebuild_flag(const BatchDev& bd) { return bd.plan + NKIND * (bd.cap + 1); }
+
 struct Item {
     int band, tile, image;
 };
@@ -221,6 +231,8 @@ __device__ inline int kind_tiles(const BandDev& b, int kind)
 {
     switch (kind) {
     case KIND_ATOM: return b.ntA;
+    case KIND_ATOM4: return (b.N + CFNEB_TILE4 - 1) / CFNEB_TILE4;
+    case KIND_ROW4: return b.ntR4;
     case KIND_BIN: return (b.nbcap + CFNEB_TILE - 1) / CFNEB_TILE;
     case KIND_ROW:
     case KIND_IVAL:

@@ -26,11 +26,12 @@ __device__ void lj_item(const BandDev& b, BandState* st, int slot, int tile, dou
     const size_t N = b.N;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // u, then V row-major
     if (i < b.N) {
-        const double* R = Rs(b, slot);
+        const double4* R = Rs(b, slot);
         const ImageGeom& g = b.geom[slot];
         double h[9];
         for (int q = 0; q < 9; ++q) h[q] = g.h[q];
-        const double ri0 = R[i], ri1 = R[b.ld + i], ri2 = R[2 * size_t(b.ld) + i];
+        const double4 ri = R[i];
+        const double ri0 = ri.x, ri1 = ri.y, ri2 = ri.z;
         const uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
         const int cnt = min(b.ncnt[size_t(slot) * N + i], b.cap);
         const T eps4 = T(4.0 * b.lj_eps), eps24 = T(24.0 * b.lj_eps), sig2 = T(b.lj_sig2),
@@ -40,9 +41,10 @@ __device__ void lj_item(const BandDev& b, BandState* st, int slot, int tile, dou
             const uint32_t ent = nbr[size_t(e) * N + i];
             const int j = nbr_j(ent);
             const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
-            const double d0 = (R[j] - ri0) + ((n0 * h[0] + n1 * h[3]) + n2 * h[6]);
-            const double d1 = (R[b.ld + j] - ri1) + ((n0 * h[1] + n1 * h[4]) + n2 * h[7]);
-            const double d2 = (R[2 * size_t(b.ld) + j] - ri2) + ((n0 * h[2] + n1 * h[5]) + n2 * h[8]);
+            const double4 rj = R[j];
+            const double d0 = (rj.x - ri0) + ((n0 * h[0] + n1 * h[3]) + n2 * h[6]);
+            const double d1 = (rj.y - ri1) + ((n0 * h[1] + n1 * h[4]) + n2 * h[7]);
+            const double d2 = (rj.z - ri2) + ((n0 * h[2] + n1 * h[5]) + n2 * h[8]);
             const T dx = T(d0), dy = T(d1), dz = T(d2);
             const T r2 = dx * dx + dy * dy + dz * dz;
             const T ir2 = T(1) / r2;

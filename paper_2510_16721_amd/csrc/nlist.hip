@@ -49,10 +49,7 @@ __device__ double skin_check_item(const BandDev& b, int slot, int i)
     const double x = X[i], y = X[b.ld + i], z = X[2 * size_t(b.ld) + i];
     double r[3];
     for (int c = 0; c < 3; ++c) r[c] = (x * g.D[c] + y * g.D[3 + c]) + z * g.D[6 + c];
-    double* R = Rs(b, slot);
-    R[i] = r[0];
-    R[b.ld + i] = r[1];
-    R[2 * size_t(b.ld) + i] = r[2];
+    Rs(b, slot)[i] = make_double4(r[0], r[1], r[2], 0.0);
     if (!b.skst[slot].valid) return 0.0;
     const double* Rr = b.Rref + size_t(slot) * slot_rows(b);
     const double a[3] = {Rr[i], Rr[b.ld + i], Rr[2 * size_t(b.ld) + i]};
@@ -65,18 +62,23 @@ __device__ double skin_check_item(const BandDev& b, int slot, int i)
     return d2;
 }
 
+// 1024 atoms per item, four per thread.
 __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_images)
 {
     __shared__ double lds[CFNEB_TILE / 64];
-    ItemLoop loop(bd, KIND_ATOM, all_images);
+    ItemLoop loop(bd, KIND_ATOM4, all_images);
     Item it;
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         const BandState* st = b.st;
         if (band_stopped(st)) continue;  // uniform over the block
         const int slot = st->slot[it.image];
-        const int i = it.tile * CFNEB_TILE + threadIdx.x;
-        double m[1] = {i < b.N ? skin_check_item(b, slot, i) : 0.0};
+        double m[1] = {0.0};
+        for (int q4 = 0; q4 < CFNEB_TILE4 / CFNEB_TILE; ++q4) {
+            const int i = it.tile * CFNEB_TILE4 + q4 * CFNEB_TILE + threadIdx.x;
+            if (i >= b.N) break;
+            m[0] = fmax(m[0], skin_check_item(b, slot, i));
+        }
         block_max<1>(m, lds);
         if (threadIdx.x == 0 && m[0] > 0.0)
             atomicMax(&b.skst[slot].dmax2, (unsigned long long)__double_as_longlong(m[0]));
@@ -109,6 +111,7 @@ __global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_skin_decide(BatchDev bd, i
                 sk.hrefinv[q] = g.hinv[q];
             }
             sk.valid = 1;
+            *rebuild_flag(bd) = 1;
         }
     }
 }
@@ -116,8 +119,8 @@ __global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_skin_decide(BatchDev bd, i
 __device__ void bin_assign_item(const BandDev& b, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const double* R = Rs(b, slot);
-    const double r[3] = {R[i], R[b.ld + i], R[2 * size_t(b.ld) + i]};
+    const double4 ri = Rs(b, slot)[i];
+    const double r[3] = {ri.x, ri.y, ri.z};
     int bi[3], img[3];
     for (int q = 0; q < 3; ++q) {
         const double s = (r[0] * g.hinv[q] + r[1] * g.hinv[3 + q]) + r[2] * g.hinv[6 + q];
@@ -137,6 +140,7 @@ __device__ void bin_assign_item(const BandDev& b, int slot, int i)
 
 __global__ void __launch_bounds__(CFNEB_TILE) k_bin_assign(BatchDev bd, int all_images)
 {
+    if (*rebuild_flag(bd) == 0) return;  // no image rebuilds this step
     ItemLoop loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
@@ -197,6 +201,7 @@ __device__ void bin_scan_item(const BandDev& b, int slot)
 
 __global__ void __launch_bounds__(1024) k_bin_scan(BatchDev bd, int all_images)
 {
+    if (*rebuild_flag(bd) == 0) return;  // no image rebuilds this step
     ItemLoop loop(bd, KIND_IMAGE, all_images);
     Item it;
     while (loop.next(it)) {
@@ -210,6 +215,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan(BatchDev bd, int all_images)
 
 __global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BatchDev bd, int all_images)
 {
+    if (*rebuild_flag(bd) == 0) return;  // no image rebuilds this step
     ItemLoop loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
@@ -222,11 +228,11 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BatchDev bd, int all
         const int4 bi = b.binfo[size_t(slot) * b.N + i];
         const int pos = b.bstart[bin_base(b, slot) + bi.x] + bi.y;
         if (pos < 0 || pos >= b.N) continue;
-        const double* R = Rs(b, slot);
+        const double4 ri = Rs(b, slot)[i];
         BinAtom a;
-        a.x = R[i];
-        a.y = R[b.ld + i];
-        a.z = R[2 * size_t(b.ld) + i];
+        a.x = ri.x;
+        a.y = ri.y;
+        a.z = ri.z;
         a.info = pack_info(i, (bi.z & 0x3FF) - 512, ((bi.z >> 10) & 0x3FF) - 512, ((bi.z >> 20) & 0x3FF) - 512);
         b.bpos[size_t(slot) * b.N + pos] = a;
     }
@@ -234,6 +240,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BatchDev bd, int all
 
 __global__ void __launch_bounds__(CFNEB_TILE) k_bin_sort(BatchDev bd, int all_images)
 {
+    if (*rebuild_flag(bd) == 0) return;  // no image rebuilds this step
     ItemLoop loop(bd, KIND_BIN, all_images);
     Item it;
     while (loop.next(it)) {
@@ -291,7 +298,7 @@ __device__ inline void wrap_bin(int v, int nb, int& a, int& m)
 __device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const double* R = Rs(b, slot);
+    const double4 r4 = Rs(b, slot)[i];
     const int* start = b.bstart + bin_base(b, slot);
     const BinAtom* bp = b.bpos + size_t(slot) * b.N;
     const size_t N = b.N;
@@ -299,7 +306,7 @@ __device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
 
     double h[9];
     for (int q = 0; q < 9; ++q) h[q] = g.h[q];
-    const double ri[3] = {R[i], R[b.ld + i], R[2 * size_t(b.ld) + i]};
+    const double ri[3] = {r4.x, r4.y, r4.z};
     double* Rr = b.Rref + size_t(slot) * slot_rows(b);
     Rr[i] = ri[0];
     Rr[b.ld + i] = ri[1];
@@ -361,6 +368,7 @@ __device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
 
 __global__ void __launch_bounds__(CFNEB_TILE) k_cand(BatchDev bd, int all_images)
 {
+    if (*rebuild_flag(bd) == 0) return;  // no image rebuilds this step
     ItemLoop loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
@@ -379,7 +387,7 @@ template <typename T, bool STORE_BONDS>
 __device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const double* R = Rs(b, slot);
+    const double4* R = Rs(b, slot);
     const size_t N = b.N;
     const uint32_t* cand = b.cand + size_t(slot) * b.ccap * N;
     uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
@@ -387,7 +395,8 @@ __device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
     T4* dvec = STORE_BONDS ? reinterpret_cast<T4*>(b.dvec) + size_t(slot) * b.cap * N : nullptr;
     double h[9];
     for (int q = 0; q < 9; ++q) h[q] = g.h[q];
-    const double ri[3] = {R[i], R[b.ld + i], R[2 * size_t(b.ld) + i]};
+    const double4 r4 = R[i];
+    const double ri[3] = {r4.x, r4.y, r4.z};
     const int nc = b.ncand[size_t(slot) * N + i];
     int cnt = 0;
     for (int e = 0; e < nc; ++e) {
@@ -395,7 +404,8 @@ __device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
         const int j = nbr_j(ent);
         const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
         double d[3];
-        const double rr = exact_r2(ri, R[j], R[b.ld + j], R[2 * size_t(b.ld) + j], h, n0, n1, n2, d);
+        const double4 rj = R[j];
+        const double rr = exact_r2(ri, rj.x, rj.y, rj.z, h, n0, n1, n2, d);
         if (!(rr < b.rc2)) continue;
         if (cnt < b.cap) {
             nbr[size_t(cnt) * N + i] = ent;
@@ -432,7 +442,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_imag
 
 void launch_skin(const Launch& L, int all_images, hipStream_t s)
 {
-    k_skin_check<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, all_images);
+    k_skin_check<<<L.g[KIND_ATOM4], CFNEB_TILE, 0, s>>>(L.bd, all_images);
     k_skin_decide<<<L.g[KIND_BAND], CFNEB_MAX_IMAGES, 0, s>>>(L.bd, all_images);
 }
 

@@ -22,8 +22,8 @@ constexpr double kEvPerA3InGPa = 160.21766208;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    int N, ld, Mcap, ntA, ntR, nbcap, cap, ccap, fp64, tersoff;
-    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, P, geom, scal,
+    int N, ld, Mcap, ntA, ntR, ntR4, nbcap, cap, ccap, fp64, tersoff;
+    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, P, geom, scal, dotred,
         evpart, dotpart, maxpart, refpart, staging, state, table, live, plan, total;
 };
 
@@ -37,6 +37,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->Mcap = max_images;
     L->ntA = (L->N + CFNEB_TILE - 1) / CFNEB_TILE;
     L->ntR = (L->N + 3 + CFNEB_TILE - 1) / CFNEB_TILE;
+    L->ntR4 = (L->N + 3 + CFNEB_TILE4 - 1) / CFNEB_TILE4;
     L->nbcap = L->N + 64;
     L->cap = p->nbr_cap;
     {
@@ -57,7 +58,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     };
     L->X = take(M * rows * 8);
     L->V = take(2 * M * rows * 8);
-    L->R = take(M * rows * 8);
+    L->R = take(M * size_t(L->ld) * 32);
     L->F = take(M * rows * tsz);
     L->FN = take(M * rows * 8);
     L->binfo = take(M * N * 16);
@@ -76,23 +77,26 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->geom = take(M * sizeof(ImageGeom));
     L->scal = take(M * sizeof(ImageScal));
     L->evpart = take(M * L->ntA * 10 * 8);
-    L->dotpart = take(M * L->ntR * CFNEB_NDOT * 8);
-    L->maxpart = take(M * L->ntR * 3 * 8);
+    L->dotpart = take(M * L->ntR4 * CFNEB_NDOT * 8);
+    L->dotred = take(M * CFNEB_NDOT * 8);
+    L->maxpart = take(M * L->ntR4 * 3 * 8);
     L->refpart = take(M * L->ntR * 2 * 8);
     L->staging = take((6 * N + 64) * 8);
     L->state = take(sizeof(BandState));
     // the band's own one-entry table for the persistent kernels
     L->table = take(sizeof(BandDev));
     L->live = take(sizeof(int));
-    L->plan = take(NKIND * 2 * sizeof(int));
+    L->plan = take((NKIND * 2 + 1) * sizeof(int));
     L->total = off;
     return true;
 }
 
 // Grids of a band table, bounded by the most items its bands can hold.
 void size_grids(Launch& L, long long atom_tiles, long long row_tiles, long long bin_tiles, long long images,
-                int bands)
+                int bands, long long atom4_tiles, long long row4_tiles)
 {
+    L.g[KIND_ATOM4] = grid_for(atom4_tiles, CFNEB_GRID_TILES);
+    L.g[KIND_ROW4] = grid_for(row4_tiles, CFNEB_GRID_TILES);
     L.g[KIND_ATOM] = grid_for(atom_tiles, CFNEB_GRID_TILES);
     L.g[KIND_ROW] = grid_for(row_tiles, CFNEB_GRID_TILES);
     L.g[KIND_BIN] = grid_for(bin_tiles, CFNEB_GRID_TILES);
@@ -193,6 +197,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.Mcap = L.Mcap;
     d.ntA = L.ntA;
     d.ntR = L.ntR;
+    d.ntR4 = L.ntR4;
     d.nbcap = L.nbcap;
     d.cap = L.cap;
     d.ccap = L.ccap;
@@ -272,6 +277,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.scal = reinterpret_cast<ImageScal*>(base + L.scal);
     d.evpart = reinterpret_cast<double*>(base + L.evpart);
     d.dotpart = reinterpret_cast<double*>(base + L.dotpart);
+    d.dotred = reinterpret_cast<double*>(base + L.dotred);
     d.maxpart = reinterpret_cast<double*>(base + L.maxpart);
     d.refpart = reinterpret_cast<uint64_t*>(base + L.refpart);
     d.staging = reinterpret_cast<double*>(base + L.staging);
@@ -282,7 +288,8 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     ln.bd.plan = reinterpret_cast<int*>(base + L.plan);
     ln.bd.cap = 1;
     const long long M = L.Mcap;
-    size_grids(ln, M * L.ntA, M * L.ntR, M * ((L.nbcap + CFNEB_TILE - 1) / CFNEB_TILE), M, 1);
+    size_grids(ln, M * L.ntA, M * L.ntR, M * ((L.nbcap + CFNEB_TILE - 1) / CFNEB_TILE), M, 1,
+               M * ((L.N + CFNEB_TILE4 - 1) / CFNEB_TILE4), M * L.ntR4);
     ln.variants = 1u << band_variant(d);
 }
 
@@ -790,8 +797,10 @@ int cfneb_image_data(const cfneb_band* cb, int k, double* E, double* H, double* 
         soa_to_aos(slab.data(), ld, N + 3, Fneb);
     }
     if (R) {
-        HIP_TRY(b, hipMemcpy(slab.data(), b->d.R + size_t(slot) * 3 * ld, slab.size() * 8, hipMemcpyDeviceToHost));
-        soa_to_aos(slab.data(), ld, N, R);
+        std::vector<double> r4(4 * size_t(ld));
+        HIP_TRY(b, hipMemcpy(r4.data(), b->d.R + size_t(slot) * 4 * ld, r4.size() * 8, hipMemcpyDeviceToHost));
+        for (int i = 0; i < N; ++i)
+            for (int c = 0; c < 3; ++c) R[3 * size_t(i) + c] = r4[4 * size_t(i) + c];
     }
     return CFNEB_OK;
 }
@@ -885,7 +894,7 @@ BatchLayout batch_layout(int cap)
     };
     L.table = take(size_t(cap) * sizeof(BandDev));
     L.live = take(size_t(cap) * sizeof(int));
-    L.plan = take(size_t(NKIND) * (cap + 1) * sizeof(int));
+    L.plan = take((size_t(NKIND) * (cap + 1) + 1) * sizeof(int));
     L.summary = take(size_t(cap) * 4 * sizeof(int));
     L.total = off;
     return L;
@@ -942,7 +951,7 @@ int cfneb_batch_create(int max_bands, void* workspace, size_t workspace_bytes, v
     B->launch.bd.plan = B->plan;
     B->launch.bd.cap = max_bands;
     // any band may join later: size the persistent grids for the whole chip
-    size_grids(B->launch, 1LL << 40, 1LL << 40, 1LL << 40, 1LL << 40, max_bands);
+    size_grids(B->launch, 1LL << 40, 1LL << 40, 1LL << 40, 1LL << 40, max_bands, 1LL << 40, 1LL << 40);
     B->launch.variants = 0;
     const char* ng = std::getenv("CFNEB_NO_GRAPH");
     B->use_graph = !(ng && ng[0] == '1');

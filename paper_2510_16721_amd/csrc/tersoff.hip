@@ -17,6 +17,12 @@
 
 namespace cfneb {
 
+// Quotients of the FP32 path use the hardware reciprocal (about 1 ulp): every
+// quotient here feeds a cosine or g(cos), whose relative errors reach the bond
+// order damped by |d ln b / d ln zeta| < 0.1.  The FP64 path divides exactly.
+__device__ inline float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double qdiv(double a, double b) { return a / b; }
+
 template <typename T>
 struct TersoffT {
     T A, B, l1, l2, bn, n, c2, d2, c2d2, h, R, S, pi_w;
@@ -42,8 +48,9 @@ struct TersoffT {
         const T t = h - cs;
         const T x = t * t;
         const T den = d2 + x;
-        g = T(1) + c2d2 * x / den;
-        dg = T(-2) * c2 * t / (den * den);
+        const T iden = qdiv(T(1), den);
+        g = T(1) + c2d2 * x * iden;
+        dg = T(-2) * c2 * t * (iden * iden);
     }
     // bond order and its zeta derivative
     __device__ void bond_order(T z, T& b, T& db) const
@@ -86,6 +93,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
                              int i, int cnt, double* acc)
 {
     T dx[MAXB], dy[MAXB], dz[MAXB], r[MAXB], fc[MAXB], dfc[MAXB], fa[MAXB], fr[MAXB], bb[MAXB], db[MAXB];
+    T ir[MAXB];
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
         if (e < cnt) {
@@ -94,6 +102,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
             dy[e] = d.y;
             dz[e] = d.z;
             r[e] = d.w;
+            ir[e] = qdiv(T(1), d.w);
             fc[e] = P.fc(r[e]);
             dfc[e] = P.dfc(r[e]);
             fr[e] = P.A * exp(-P.l1 * r[e]);
@@ -101,6 +110,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
         } else {
             dx[e] = dy[e] = dz[e] = T(0);
             r[e] = T(1);
+            ir[e] = T(1);
             fc[e] = dfc[e] = fr[e] = fa[e] = T(0);
         }
     }
@@ -113,7 +123,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
 #pragma unroll
             for (int q = 0; q < MAXB; ++q) {
                 if (q == e || q >= cnt) continue;
-                const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) / (r[e] * r[q]);
+                const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) * (ir[e] * ir[q]);
                 T g, dg;
                 P.g_dg(cs, g, dg);
                 z += fc[q] * g;
@@ -125,7 +135,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
         if (e >= cnt) continue;
-        const T ire = T(1) / r[e];
+        const T ire = ir[e];
         const T hx = dx[e] * ire, hy = dy[e] * ire, hz = dz[e] * ire;
         // radial derivative at fixed bond order
         const T dV = dfc[e] * (fr[e] - bb[e] * fa[e]) + fc[e] * (-P.l1 * fr[e] + bb[e] * P.l2 * fa[e]);
@@ -134,7 +144,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
 #pragma unroll
         for (int q = 0; q < MAXB; ++q) {
             if (q == e || q >= cnt) continue;
-            const T a = T(1) / (r[e] * r[q]);
+            const T a = ir[e] * ir[q];
             const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) * a;
             const T c = cs * ire * ire;
             // d cos / d r^ie
@@ -232,7 +242,10 @@ __device__ void ts_bonds_item(const BandDev& b, int slot, int tile, double* lds)
         const vec4_t<T>* dv = reinterpret_cast<const vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
         vec4_t<T>* Pout = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.cap * N;
         const int cnt = min(b.ncnt[size_t(slot) * N + i], b.cap);
-        if (cnt <= 6) {
+        // graphite and diamond environments have 3-4 bonds: a tighter register set
+        if (cnt <= 4) {
+            ts_atom_regs<T, 4>(P, dv, Pout, N, i, cnt, acc);
+        } else if (cnt <= 6) {
             ts_atom_regs<T, 6>(P, dv, Pout, N, i, cnt, acc);
         } else {
             vec2_t<T>* bo = reinterpret_cast<vec2_t<T>*>(b.bo) + size_t(slot) * b.cap * N;
