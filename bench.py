@@ -36,10 +36,12 @@ VALU_FP32_PEAK_TFLOPS = 78.6
 #   rows = (atoms + 3) per moving image; atoms = atoms per moving image
 #   Tersoff flops: 60 per directed bond + 80 per bond pair (triplet) for energy and forces
 ALGO = {
-    # per row: read X 24 B + F 12 B + v 24 B
-    "dots": dict(bound="hbm", per="row", bytes=60),
-    # per row: read X 24 + F 12 + v 24, write v' 24
-    "update": dict(bound="hbm", per="row", bytes=84),
+    # per row: read X of the image and its two neighbours 72 B + F 12 B + v 24 B
+    "dots": dict(bound="hbm", per="row", bytes=108),
+    # per atom: read R~ 24 B and R_ref 24 B, write the 32-byte position record
+    "skin": dict(bound="hbm", per="atom", bytes=80),
+    # per row: read X of the image and its two neighbours 72 + F 12 + v 24, write v' 24
+    "update": dict(bound="hbm", per="row", bytes=132),
     # per row: read X 24 + v' 24, write X 24
     "move": dict(bound="hbm", per="row", bytes=72),
     # per atom: read R~ 24 B, write R 24 B
@@ -47,9 +49,29 @@ ALGO = {
 }
 
 
-def tersoff_flops_per_atom(mean_bonds):
-    B = mean_bonds
-    return 60.0 * B + 80.0 * B * (B - 1.0)
+def ts_bonds_flops_per_atom(B):
+    """FP32 operations of the Tersoff bond kernel for an atom with B bonds: 40 per bond
+    (two exponentials, cutoff, bond order from zeta, energy, radial derivative) and 70
+    per ordered bond pair (cosine and g, dg twice, the angular and radial terms of P),
+    counting +, -, x, /, each elementary function and each half of an FMA as one."""
+    return 40.0 * B + 70.0 * B * (B - 1.0)
+
+
+def recorded_traffic(kernel_source, moving_images):
+    """HBM bytes per dispatch of the Tersoff bond kernel from the committed counter
+    summary, scaled to the current number of moving images; None if the kernel's source
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tersoff_graphite_98304_hbm_counters.md")
+    try:
+        text = open(path).read()
+        blob = json.loads(text.split("```json")[1].split("```")[0])
+        src = open(os.path.join(ROOT, blob["source"]), "rb").read()
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+    if blob["kernel"] != kernel_source or hashlib.sha256(src).hexdigest() != blob["source_sha256"]:
+        return None
+    return blob["hbm_bytes_per_dispatch"] * moving_images / blob["moving_images"]
 
 
 def make_band(args):
@@ -302,13 +324,14 @@ def main():
     dom = max(per_launch, key=per_launch.get)
     rows = (N + 3) * mean_moving
     atoms = N * mean_moving
-    if dom in ("force0", "force1", "force2"):
-        flops = tersoff_flops_per_atom(mean_bonds) * atoms
-        fms = per_launch["force0"] + per_launch["force1"] + per_launch["force2"]
-        achieved = flops / (fms * 1e-3) / 1e12
-        roof = dict(bound="alu", kernel="tersoff force (3 kernels)", achieved=achieved,
+    if dom == "force0":
+        # the Tersoff bond kernel (bond orders, energies, dU_i/dr^ij, virial)
+        flops = ts_bonds_flops_per_atom(mean_bonds) * atoms
+        achieved = flops / (per_launch["force0"] * 1e-3) / 1e12
+        roof = dict(bound="alu", kernel="k_ts_bonds<float>", achieved=achieved,
                     peak=VALU_FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / VALU_FP32_PEAK_TFLOPS,
-                    traffic=None)
+                    traffic=recorded_traffic("k_ts_bonds<float>", mean_moving),
+                    algorithmic_bytes=(32.0 * mean_bonds + 4.0) * atoms)
     elif dom in ALGO:
         m = ALGO[dom]
         units = rows if m["per"] == "row" else atoms
