@@ -399,26 +399,36 @@ __device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
     const double ri[3] = {r4.x, r4.y, r4.z};
     const int nc = b.ncand[size_t(slot) * N + i];
     int cnt = 0;
-    for (int e = 0; e < nc; ++e) {
-        const uint32_t ent = cand[size_t(e) * N + i];
-        const int j = nbr_j(ent);
-        const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
-        double d[3];
-        const double4 rj = R[j];
-        const double rr = exact_r2(ri, rj.x, rj.y, rj.z, h, n0, n1, n2, d);
-        if (!(rr < b.rc2)) continue;
-        if (cnt < b.cap) {
-            nbr[size_t(cnt) * N + i] = ent;
-            if (STORE_BONDS) {
-                T4 v;
-                v.x = T(d[0]);
-                v.y = T(d[1]);
-                v.z = T(d[2]);
-                v.w = T(sqrt(rr));
-                dvec[size_t(cnt) * N + i] = v;
+    // four candidates at a time: their entries, then their positions, are in flight
+    // together before any test
+    constexpr int U = 4;
+    for (int e0 = 0; e0 < nc; e0 += U) {
+        uint32_t ent[U];
+        double4 rj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ent[u] = (e0 + u < nc) ? cand[size_t(e0 + u) * N + i] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u) rj[u] = (e0 + u < nc) ? R[nbr_j(ent[u])] : r4;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (e0 + u >= nc) break;
+            const int n0 = nbr_n(ent[u], 0), n1 = nbr_n(ent[u], 1), n2 = nbr_n(ent[u], 2);
+            double d[3];
+            const double rr = exact_r2(ri, rj[u].x, rj[u].y, rj[u].z, h, n0, n1, n2, d);
+            if (!(rr < b.rc2)) continue;
+            if (cnt < b.cap) {
+                nbr[size_t(cnt) * N + i] = ent[u];
+                if (STORE_BONDS) {
+                    T4 v;
+                    v.x = T(d[0]);
+                    v.y = T(d[1]);
+                    v.z = T(d[2]);
+                    v.w = T(sqrt(rr));
+                    dvec[size_t(cnt) * N + i] = v;
+                }
             }
+            ++cnt;
         }
-        ++cnt;
     }
     b.ncnt[size_t(slot) * N + i] = cnt;
     if (cnt > b.cap) set_error(st, CFNEB_ENEIGH);
