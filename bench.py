@@ -51,10 +51,11 @@ ALGO = {
 
 def ts_bonds_flops_per_atom(B):
     """FP32 operations of the Tersoff bond kernel for an atom with B bonds: 40 per bond
-    (two exponentials, cutoff, bond order from zeta, energy, radial derivative) and 70
-    per ordered bond pair (cosine and g, dg twice, the angular and radial terms of P),
-    counting +, -, x, /, each elementary function and each half of an FMA as one."""
-    return 40.0 * B + 70.0 * B * (B - 1.0)
+    (two exponentials, cutoff, bond order from zeta, energy, radial derivative) and 65
+    per unordered bond pair (cosine, g and g' once; both zeta terms; the angular and
+    radial terms of both P's), counting +, -, x, /, each elementary function and each
+    half of an FMA as one."""
+    return 40.0 * B + 65.0 * B * (B - 1.0) / 2.0
 
 
 def recorded_traffic(kernel_source, moving_images):

@@ -87,13 +87,15 @@ __device__ inline void add_virial(double* acc, T dx, T dy, T dz, T px, T py, T p
     acc[9] -= z * double(pz);
 }
 
-// Atoms with at most MAXB bonds: every bond quantity lives in registers.
+// Atoms with at most MAXB bonds: every bond quantity lives in registers.  cos,
+// g(cos) and g'(cos) are symmetric in the two bonds, so each unordered bond pair is
+// evaluated once: it adds to both zetas, and its derivative to both P's.
 template <typename T, int MAXB>
 __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T>* Pout, size_t N,
                              int i, int cnt, double* acc)
 {
-    T dx[MAXB], dy[MAXB], dz[MAXB], r[MAXB], fc[MAXB], dfc[MAXB], fa[MAXB], fr[MAXB], bb[MAXB], db[MAXB];
-    T ir[MAXB];
+    constexpr int NP = MAXB * (MAXB - 1) / 2;
+    T dx[MAXB], dy[MAXB], dz[MAXB], ir[MAXB], fc[MAXB], dfc[MAXB], fr[MAXB], fa[MAXB];
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
         if (e < cnt) {
@@ -101,71 +103,102 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
             dx[e] = d.x;
             dy[e] = d.y;
             dz[e] = d.z;
-            r[e] = d.w;
             ir[e] = qdiv(T(1), d.w);
-            fc[e] = P.fc(r[e]);
-            dfc[e] = P.dfc(r[e]);
-            fr[e] = P.A * exp(-P.l1 * r[e]);
-            fa[e] = P.B * exp(-P.l2 * r[e]);
+            fc[e] = P.fc(d.w);
+            dfc[e] = P.dfc(d.w);
+            fr[e] = P.A * exp(-P.l1 * d.w);
+            fa[e] = P.B * exp(-P.l2 * d.w);
         } else {
             dx[e] = dy[e] = dz[e] = T(0);
-            r[e] = T(1);
             ir[e] = T(1);
             fc[e] = dfc[e] = fr[e] = fa[e] = T(0);
         }
     }
+    // pass 1: zeta of every bond from the unordered pairs (each zeta sums its pairs in
+    // increasing order of the other bond)
+    T csp[NP], gp[NP], dgp[NP], z[MAXB];
+#pragma unroll
+    for (int e = 0; e < MAXB; ++e) z[e] = T(0);
+    {
+        int p = 0;
+#pragma unroll
+        for (int e = 0; e < MAXB; ++e) {
+#pragma unroll
+            for (int q = e + 1; q < MAXB; ++q, ++p) {
+                csp[p] = gp[p] = dgp[p] = T(0);
+                if (q < cnt) {
+                    const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) * (ir[e] * ir[q]);
+                    T g, dg;
+                    P.g_dg(cs, g, dg);
+                    csp[p] = cs;
+                    gp[p] = g;
+                    dgp[p] = dg;
+                    z[e] += fc[q] * g;
+                    z[q] += fc[e] * g;
+                }
+            }
+        }
+    }
+    // bond orders, energy, radial derivative at fixed bond order, prefactor of zeta
+    T dV[MAXB], pre[MAXB];
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
-        bb[e] = T(1);
-        db[e] = T(0);
+        dV[e] = pre[e] = T(0);
         if (e < cnt) {
-            T z = T(0);
+            T bb, db;
+            P.bond_order(z[e], bb, db);
+            acc[0] += double(T(0.5) * fc[e] * (fr[e] - bb * fa[e]));
+            dV[e] = dfc[e] * (fr[e] - bb * fa[e]) + fc[e] * (-P.l1 * fr[e] + bb * P.l2 * fa[e]);
+            pre[e] = fc[e] * fa[e] * db;
+        }
+    }
+    // pass 2: P_e = dU_i/dr^e
+    T px[MAXB], py[MAXB], pz[MAXB], hx[MAXB], hy[MAXB], hz[MAXB];
 #pragma unroll
-            for (int q = 0; q < MAXB; ++q) {
-                if (q == e || q >= cnt) continue;
-                const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) * (ir[e] * ir[q]);
-                T g, dg;
-                P.g_dg(cs, g, dg);
-                z += fc[q] * g;
+    for (int e = 0; e < MAXB; ++e) {
+        hx[e] = dx[e] * ir[e];
+        hy[e] = dy[e] * ir[e];
+        hz[e] = dz[e] * ir[e];
+        px[e] = T(0.5) * dV[e] * hx[e];
+        py[e] = T(0.5) * dV[e] * hy[e];
+        pz[e] = T(0.5) * dV[e] * hz[e];
+    }
+    {
+        int p = 0;
+#pragma unroll
+        for (int e = 0; e < MAXB; ++e) {
+#pragma unroll
+            for (int q = e + 1; q < MAXB; ++q, ++p) {
+                if (q >= cnt) continue;
+                const T a = ir[e] * ir[q];
+                const T cs = csp[p];
+                // zeta_e holds fc(r_q) g(cos), zeta_q holds fc(r_e) g(cos)
+                const T ang = T(0.5) * (pre[e] * fc[q] + pre[q] * fc[e]) * dgp[p];
+                // d cos / d r^e and d cos / d r^q
+                const T ce = cs * ir[e] * ir[e], cq = cs * ir[q] * ir[q];
+                const T ex = dx[q] * a - ce * dx[e], ey = dy[q] * a - ce * dy[e], ez = dz[q] * a - ce * dz[e];
+                const T qx = dx[e] * a - cq * dx[q], qy = dy[e] * a - cq * dy[q], qz = dz[e] * a - cq * dz[q];
+                const T rad_e = T(0.5) * pre[q] * dfc[e] * gp[p];
+                const T rad_q = T(0.5) * pre[e] * dfc[q] * gp[p];
+                px[e] -= ang * ex + rad_e * hx[e];
+                py[e] -= ang * ey + rad_e * hy[e];
+                pz[e] -= ang * ez + rad_e * hz[e];
+                px[q] -= ang * qx + rad_q * hx[q];
+                py[q] -= ang * qy + rad_q * hy[q];
+                pz[q] -= ang * qz + rad_q * hz[q];
             }
-            P.bond_order(z, bb[e], db[e]);
-            acc[0] += double(T(0.5) * fc[e] * (fr[e] - bb[e] * fa[e]));
         }
     }
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
         if (e >= cnt) continue;
-        const T ire = ir[e];
-        const T hx = dx[e] * ire, hy = dy[e] * ire, hz = dz[e] * ire;
-        // radial derivative at fixed bond order
-        const T dV = dfc[e] * (fr[e] - bb[e] * fa[e]) + fc[e] * (-P.l1 * fr[e] + bb[e] * P.l2 * fa[e]);
-        T px = T(0.5) * dV * hx, py = T(0.5) * dV * hy, pz = T(0.5) * dV * hz;
-        const T pre_e = fc[e] * fa[e] * db[e];
-#pragma unroll
-        for (int q = 0; q < MAXB; ++q) {
-            if (q == e || q >= cnt) continue;
-            const T a = ir[e] * ir[q];
-            const T cs = (dx[e] * dx[q] + dy[e] * dy[q] + dz[e] * dz[q]) * a;
-            const T c = cs * ire * ire;
-            // d cos / d r^ie
-            const T cx = dx[q] * a - c * dx[e], cy = dy[q] * a - c * dy[e], cz = dz[q] * a - c * dz[e];
-            T g, dg;
-            P.g_dg(cs, g, dg);
-            const T pre_q = fc[q] * fa[q] * db[q];
-            // zeta_ie holds fc(r_q) g(cos); zeta_iq holds fc(r_e) g(cos)
-            const T ang = T(0.5) * (pre_e * fc[q] + pre_q * fc[e]) * dg;
-            const T rad = T(0.5) * pre_q * dfc[e] * g;
-            px -= ang * cx + rad * hx;
-            py -= ang * cy + rad * hy;
-            pz -= ang * cz + rad * hz;
-        }
         vec4_t<T> o;
-        o.x = px;
-        o.y = py;
-        o.z = pz;
+        o.x = px[e];
+        o.y = py[e];
+        o.z = pz[e];
         o.w = T(0);
         Pout[size_t(e) * N + i] = o;
-        add_virial<T>(acc, dx[e], dy[e], dz[e], px, py, pz);
+        add_virial<T>(acc, dx[e], dy[e], dz[e], px[e], py[e], pz[e]);
     }
 }
 
@@ -242,11 +275,9 @@ __device__ void ts_bonds_item(const BandDev& b, int slot, int tile, double* lds)
         const vec4_t<T>* dv = reinterpret_cast<const vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
         vec4_t<T>* Pout = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.cap * N;
         const int cnt = min(b.ncnt[size_t(slot) * N + i], b.cap);
-        // graphite and diamond environments have 3-4 bonds: a tighter register set
+        // graphite and diamond environments have 3-4 bonds
         if (cnt <= 4) {
             ts_atom_regs<T, 4>(P, dv, Pout, N, i, cnt, acc);
-        } else if (cnt <= 6) {
-            ts_atom_regs<T, 6>(P, dv, Pout, N, i, cnt, acc);
         } else {
             vec2_t<T>* bo = reinterpret_cast<vec2_t<T>*>(b.bo) + size_t(slot) * b.cap * N;
             ts_atom_generic<T>(P, dv, bo, Pout, N, i, cnt, acc);
