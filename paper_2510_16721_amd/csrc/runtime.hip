@@ -223,6 +223,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.ts_B = p->ts_B;
     d.ts_l1 = p->ts_lambda1;
     d.ts_l2 = p->ts_lambda2;
+    d.ts_beta = p->ts_beta;
     d.ts_bn = std::pow(p->ts_beta, p->ts_n);
     d.ts_n = p->ts_n;
     d.ts_c2 = p->ts_c * p->ts_c;

@@ -23,13 +23,29 @@ namespace cfneb {
 __device__ inline float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ inline double qdiv(double a, double b) { return a / b; }
 
+// Bond order b = (1 + x)^(-1/2n), x = beta^n zeta^n.  Both powers keep the accurately
+// rounded pow: the energy of a perfect crystal adds every bond's rounding of b
+// coherently, and a cheaper exp2(n log2(beta zeta)) form misses 1e-6 eV/atom there.
+__device__ inline void bond_order_pow(float z, float beta, float n, float bn, float& x)
+{
+    (void)beta;
+    x = bn * powf(z, n);
+}
+__device__ inline float bond_order_b(float base, float n) { return powf(base, -0.5f / n); }
+__device__ inline void bond_order_pow(double z, double beta, double n, double bn, double& x)
+{
+    (void)beta;
+    x = bn * pow(z, n);
+}
+__device__ inline double bond_order_b(double base, double n) { return pow(base, -0.5 / n); }
+
 template <typename T>
 struct TersoffT {
-    T A, B, l1, l2, bn, n, c2, d2, c2d2, h, R, S, pi_w;
+    T A, B, l1, l2, beta, bn, n, c2, d2, c2d2, h, R, S, pi_w;
     __device__ explicit TersoffT(const BandDev& b)
-        : A(T(b.ts_A)), B(T(b.ts_B)), l1(T(b.ts_l1)), l2(T(b.ts_l2)), bn(T(b.ts_bn)), n(T(b.ts_n)),
-          c2(T(b.ts_c2)), d2(T(b.ts_d2)), c2d2(T(b.ts_c2d2)), h(T(b.ts_h)), R(T(b.ts_R)), S(T(b.ts_S)),
-          pi_w(T(3.14159265358979323846 / (b.ts_S - b.ts_R)))
+        : A(T(b.ts_A)), B(T(b.ts_B)), l1(T(b.ts_l1)), l2(T(b.ts_l2)), beta(T(b.ts_beta)), bn(T(b.ts_bn)),
+          n(T(b.ts_n)), c2(T(b.ts_c2)), d2(T(b.ts_d2)), c2d2(T(b.ts_c2d2)), h(T(b.ts_h)), R(T(b.ts_R)),
+          S(T(b.ts_S)), pi_w(T(3.14159265358979323846 / (b.ts_S - b.ts_R)))
     {
     }
     __device__ T fc(T r) const
@@ -58,10 +74,11 @@ struct TersoffT {
         b = T(1);
         db = T(0);
         if (z > T(0)) {
-            const T zn = pow(z, n);
-            const T base = T(1) + bn * zn;
-            b = pow(base, T(-0.5) / n);
-            db = T(-0.5) * bn * (zn / z) * (b / base);
+            T x;
+            bond_order_pow(z, beta, n, bn, x);
+            const T base = T(1) + x;
+            b = bond_order_b(base, n);
+            db = T(-0.5) * qdiv(x, z) * qdiv(b, base);
         }
     }
 };
