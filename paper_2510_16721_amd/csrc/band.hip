@@ -58,13 +58,14 @@ __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile
     double a[CFNEB_NDOT];
 #pragma unroll
     for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
-    const double* X0 = Xs(b, s0);
-    const double* Xm = Xs(b, sm);
-    const double* Xp = Xs(b, sp);
-    const double* V = Vs(b, st->vcur, s0);
+    const double* __restrict__ X0 = Xs(b, s0);
+    const double* __restrict__ Xm = Xs(b, sm);
+    const double* __restrict__ Xp = Xs(b, sp);
+    const double* __restrict__ V = Vs(b, st->vcur, s0);
+#pragma unroll
     for (int q4 = 0; q4 < CFNEB_TILE4 / CFNEB_TILE; ++q4) {
         const int r = tile * CFNEB_TILE4 + q4 * CFNEB_TILE + threadIdx.x;
-        if (r >= b.N + 3) break;
+        if (r >= b.N + 3) continue;
         double f[3];
         gen_force_row<T>(b, s0, r, f);
         for (int c = 0; c < 3; ++c) {
@@ -379,6 +380,11 @@ __device__ void finalize_item(const BandDev& b, BandState* st, double* lds)
     st->refine_due = (b.refine_every > 0 && st->step % b.refine_every == 0) ? 1 : 0;
 }
 
+__device__ inline void note_refine(const BatchDev& bd, const BandState* st)
+{
+    if (st->refine_due) *refine_flag(bd) = 1;
+}
+
 __global__ void __launch_bounds__(1024) k_band_finalize(BatchDev bd)
 {
     __shared__ double lds[16 * 3];
@@ -393,6 +399,7 @@ __global__ void __launch_bounds__(1024) k_band_finalize(BatchDev bd)
         }
         finalize_item(b, st, lds);
         __syncthreads();
+        if (threadIdx.x == 0) note_refine(bd, st);
     }
 }
 

@@ -14,7 +14,10 @@ __global__ void __launch_bounds__(CFNEB_MAX_BANDS) k_plan(BatchDev bd, int all_i
 {
     __shared__ int cnt[NKIND][CFNEB_MAX_BANDS];
     const int t = threadIdx.x;
-    if (t == 0) *rebuild_flag(bd) = 0;
+    if (t == 0) {
+        *rebuild_flag(bd) = 0;
+        *refine_flag(bd) = 0;
+    }
     if (t < bd.cap) {
         int c[NKIND];
         for (int q = 0; q < NKIND; ++q) c[q] = 0;

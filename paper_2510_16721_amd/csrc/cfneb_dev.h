@@ -174,6 +174,19 @@ __device__ inline uint32_t pack_nbr(int j, int n0, int n1, int n2)
 __device__ inline int nbr_j(uint32_t e) { return int(e & 0xFFFFFu); }
 __device__ inline int nbr_n(uint32_t e, int k) { return int((e >> (20 + 4 * k)) & 0xFu) - 8; }
 
+// Exact squared distance of entry (j, n); every operation rounded separately.
+__device__ inline double exact_r2(const double* ri, double xj, double yj, double zj, const double* h,
+                                  int n0, int n1, int n2, double* d)
+{
+#pragma clang fp contract(off)
+    const double rj[3] = {xj, yj, zj};
+    for (int c = 0; c < 3; ++c) {
+        const double sh = (double(n0) * h[c] + double(n1) * h[3 + c]) + double(n2) * h[6 + c];
+        d[c] = (rj[c] - ri[c]) + sh;
+    }
+    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
 // Logical image range of a per-image launch: all images, or the moving ones.
 __device__ inline bool image_active(const BandState* st, int k, int all_images)
 {
@@ -222,6 +235,9 @@ struct BatchDev {
 // Set by the skin decision when any image of any band rebuilds its candidates this
 // step (cleared by the plan kernel); the rebuild kernels return at once without it.
 __device__ inline int* rebuild_flag(const BatchDev& bd) { return bd.plan + NKIND * (bd.cap + 1); }
+// Set by the finalize kernel when any band's step is due for the adaptive-image check
+// (cleared by the plan kernel); the step-end refine kernels return at once without it.
+__device__ inline int* refine_flag(const BatchDev& bd) { return bd.plan + NKIND * (bd.cap + 1) + 1; }
 
 struct Item {
     int band, tile, image;

@@ -41,31 +41,13 @@ __device__ inline long long pack_info(int j, int n0, int n1, int n2)
 __device__ inline int info_j(long long v) { return int(v & 0xFFFFF); }
 __device__ inline int info_n(long long v, int k) { return int((v >> (20 + 10 * k)) & 0x3FF) - 512; }
 
-// R = R~ D of atom i; d_i^2 against the strained reference when a list exists.
-__device__ double skin_check_item(const BandDev& b, int slot, int i)
-{
-    const ImageGeom& g = b.geom[slot];
-    const double* X = Xs(b, slot);
-    const double x = X[i], y = X[b.ld + i], z = X[2 * size_t(b.ld) + i];
-    double r[3];
-    for (int c = 0; c < 3; ++c) r[c] = (x * g.D[c] + y * g.D[3 + c]) + z * g.D[6 + c];
-    Rs(b, slot)[i] = make_double4(r[0], r[1], r[2], 0.0);
-    if (!b.skst[slot].valid) return 0.0;
-    const double* Rr = b.Rref + size_t(slot) * slot_rows(b);
-    const double a[3] = {Rr[i], Rr[b.ld + i], Rr[2 * size_t(b.ld) + i]};
-    double d2 = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        const double ref = a[c] + ((a[0] * g.E[c] + a[1] * g.E[3 + c]) + a[2] * g.E[6 + c]);
-        const double d = r[c] - ref;
-        d2 += d * d;
-    }
-    return d2;
-}
-
-// 1024 atoms per item, four per thread.
+// 1024 atoms per item, four per thread: all loads of the four atoms are issued before
+// any position is stored.  R = R~ D; d_i^2 against the strained reference when a list
+// exists (block maximum, then an integer atomic max per image).
 __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_images)
 {
     __shared__ double lds[CFNEB_TILE / 64];
+    constexpr int Q = CFNEB_TILE4 / CFNEB_TILE;
     ItemLoop loop(bd, KIND_ATOM4, all_images);
     Item it;
     while (loop.next(it)) {
@@ -73,11 +55,39 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
         const BandState* st = b.st;
         if (band_stopped(st)) continue;  // uniform over the block
         const int slot = st->slot[it.image];
+        const ImageGeom& g = b.geom[slot];
+        const bool valid = b.skst[slot].valid != 0;
+        const double* __restrict__ X = Xs(b, slot);
+        const double* __restrict__ Rr = b.Rref + size_t(slot) * slot_rows(b);
+        double x[Q][3], a[Q][3];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
+            const bool in = i < b.N;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x[q][c] = in ? X[size_t(c) * b.ld + i] : 0.0;
+                a[q][c] = (in && valid) ? Rr[size_t(c) * b.ld + i] : 0.0;
+            }
+        }
         double m[1] = {0.0};
-        for (int q4 = 0; q4 < CFNEB_TILE4 / CFNEB_TILE; ++q4) {
-            const int i = it.tile * CFNEB_TILE4 + q4 * CFNEB_TILE + threadIdx.x;
-            if (i >= b.N) break;
-            m[0] = fmax(m[0], skin_check_item(b, slot, i));
+        double4* __restrict__ R = Rs(b, slot);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
+            if (i >= b.N) continue;
+            double r[3];
+            for (int c = 0; c < 3; ++c) r[c] = (x[q][0] * g.D[c] + x[q][1] * g.D[3 + c]) + x[q][2] * g.D[6 + c];
+            R[i] = make_double4(r[0], r[1], r[2], 0.0);
+            if (valid) {
+                double d2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double ref = a[q][c] + ((a[q][0] * g.E[c] + a[q][1] * g.E[3 + c]) + a[q][2] * g.E[6 + c]);
+                    const double d = r[c] - ref;
+                    d2 += d * d;
+                }
+                m[0] = fmax(m[0], d2);
+            }
         }
         block_max<1>(m, lds);
         if (threadIdx.x == 0 && m[0] > 0.0)
@@ -264,19 +274,6 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_sort(BatchDev bd, int all_im
             a[q + 1] = v;
         }
     }
-}
-
-// Exact squared distance of entry (j, n); every operation rounded separately.
-__device__ inline double exact_r2(const double* ri, double xj, double yj, double zj, const double* h,
-                                  int n0, int n1, int n2, double* d)
-{
-#pragma clang fp contract(off)
-    const double rj[3] = {xj, yj, zj};
-    for (int c = 0; c < 3; ++c) {
-        const double sh = (double(n0) * h[c] + double(n1) * h[3 + c]) + double(n2) * h[6 + c];
-        d[c] = (rj[c] - ri[c]) + sh;
-    }
-    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
 }
 
 __device__ inline void wrap_bin(int v, int nb, int& a, int& m)
@@ -469,15 +466,12 @@ void launch_list(const Launch& L, int all_images, hipStream_t s)
     k_cand<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, all_images);
 }
 
+// LJ bands; Tersoff bands test their candidates inside the bond kernel.
 void launch_filter(const Launch& L, int all_images, hipStream_t s)
 {
     const unsigned g = L.g[KIND_ATOM];
     const unsigned lj = L.variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_LJ64));
     if (lj) k_filter<double, false><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj);
-    if (L.variants & (1u << VARIANT_TS32))
-        k_filter<float, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS32);
-    if (L.variants & (1u << VARIANT_TS64))
-        k_filter<double, true><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, 1u << VARIANT_TS64);
 }
 
 }  // namespace cfneb

@@ -161,6 +161,7 @@ __device__ void dist_item(const BandDev& b, BandState* st, int k, int tile)
 // mode 0: only when the step set refine_due; mode 1: always (readout / explicit call)
 __global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BatchDev bd, int mode)
 {
+    if (mode == 0 && *refine_flag(bd) == 0) return;  // no band is due this step
     ItemLoop loop(bd, KIND_IVAL, 0);
     Item it;
     while (loop.next(it)) {
@@ -258,6 +259,7 @@ __device__ void decide_item(const BandDev& b, BandState* st, int mode)
 
 __global__ void __launch_bounds__(64) k_refine_decide(BatchDev bd, int mode)
 {
+    if (mode == 0 && *refine_flag(bd) == 0) return;  // no band is due this step
     ItemLoop loop(bd, KIND_BAND, 0);
     Item it;
     while (loop.next(it)) {
@@ -272,6 +274,7 @@ __global__ void __launch_bounds__(64) k_refine_decide(BatchDev bd, int mode)
 // Walks every slot of the capacity, since the image count just changed.
 __global__ void __launch_bounds__(CFNEB_TILE) k_refine_apply(BatchDev bd, int mode)
 {
+    if (mode == 0 && *refine_flag(bd) == 0) return;  // no band is due this step
     ItemLoop loop(bd, KIND_SLOTROW, 0);
     Item it;
     while (loop.next(it)) {
@@ -302,6 +305,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_apply(BatchDev bd, int mo
 
 __global__ void k_refine_end(BatchDev bd)
 {
+    if (*refine_flag(bd) == 0) return;  // no band was due this step
     ItemLoop loop(bd, KIND_BAND, 0);
     Item it;
     while (loop.next(it))

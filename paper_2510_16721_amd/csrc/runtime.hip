@@ -86,7 +86,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     // the band's own one-entry table for the persistent kernels
     L->table = take(sizeof(BandDev));
     L->live = take(sizeof(int));
-    L->plan = take((NKIND * 2 + 1) * sizeof(int));
+    L->plan = take((NKIND * 2 + 2) * sizeof(int));
     L->total = off;
     return true;
 }
@@ -895,7 +895,7 @@ BatchLayout batch_layout(int cap)
     };
     L.table = take(size_t(cap) * sizeof(BandDev));
     L.live = take(size_t(cap) * sizeof(int));
-    L.plan = take((size_t(NKIND) * (cap + 1) + 1) * sizeof(int));
+    L.plan = take((size_t(NKIND) * (cap + 1) + 2) * sizeof(int));
     L.summary = take(size_t(cap) * 4 * sizeof(int));
     L.total = off;
     return L;

@@ -3,10 +3,10 @@
 //   U_i = 1/2 sum_j fc(r_ij) [A exp(-l1 r_ij) - b_ij B exp(-l2 r_ij)],
 //   b_ij = (1 + beta^n zeta_ij^n)^(-1/2n),  zeta_ij = sum_{k != j} fc(r_ik) g(cos theta_ijk),
 //   fc = 1 below R, 1/2 + 1/2 cos(pi (r - R)/(S - R)) between R and S, 0 beyond.
-// U_i depends only on i's bond vectors, so one thread per atom forms every
-// P_ij = dU_i/dr^ij from its own list (bond vectors were written by the list
-// kernel), and a second kernel gathers F_i = sum_j (P_ij - P_ji) through the
-// reverse entry (i, -n) of j's list.  No atomics: the result is deterministic.
+// U_i depends only on i's bond vectors, so one thread per atom finds its neighbours
+// among its candidates (exact test), keeps the bond vectors in registers and forms
+// every P_ij = dU_i/dr^ij; a second kernel gathers F_i = sum_j (P_ij - P_ji) through
+// the reverse entry (i, -n) of j's list.  No atomics: the result is deterministic.
 //
 // g is evaluated as 1 + (c^2/d^2) x / (d^2 + x), x = (h - cos)^2: the textbook form
 // 1 + c^2/d^2 - c^2/(d^2 + x) cancels two numbers near 7.7e7 and loses about four
@@ -108,7 +108,7 @@ __device__ inline void add_virial(double* acc, T dx, T dy, T dz, T px, T py, T p
 // g(cos) and g'(cos) are symmetric in the two bonds, so each unordered bond pair is
 // evaluated once: it adds to both zetas, and its derivative to both P's.
 template <typename T, int MAXB>
-__device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T>* Pout, size_t N,
+__device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB], vec4_t<T>* Pout, size_t N,
                              int i, int cnt, double* acc)
 {
     constexpr int NP = MAXB * (MAXB - 1) / 2;
@@ -116,7 +116,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T>* dv, vec4_t<T
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
         if (e < cnt) {
-            const vec4_t<T> d = dv[size_t(e) * N + i];
+            const vec4_t<T> d = bond[e];
             dx[e] = d.x;
             dy[e] = d.y;
             dz[e] = d.z;
@@ -280,24 +280,74 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
     }
 }
 
-// u_i, P_ij and the per-atom virial; block partials of (E, V) in FP64.
+// Neighbours of atom i by the exact test of its candidates (as the candidate filter
+// does for LJ), then u_i, P_ij and the per-atom virial from the bond vectors; block
+// partials of (E, V) in FP64.  Up to four bonds never leave registers; an atom with
+// more writes its bond vectors and takes the general path.
 template <typename T>
-__device__ void ts_bonds_item(const BandDev& b, int slot, int tile, double* lds)
+__device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
 {
+    constexpr int MB = 4;
     const int i = tile * CFNEB_TILE + threadIdx.x;
     const size_t N = b.N;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < b.N) {
+        const ImageGeom& g = b.geom[slot];
+        const double4* R = Rs(b, slot);
+        const uint32_t* cand = b.cand + size_t(slot) * b.ccap * N;
+        uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
+        vec4_t<T>* dv = reinterpret_cast<vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
+        double h[9];
+        for (int q = 0; q < 9; ++q) h[q] = g.h[q];
+        const double4 r4 = R[i];
+        const double ri[3] = {r4.x, r4.y, r4.z};
+        const int nc = b.ncand[size_t(slot) * N + i];
+        vec4_t<T> bond[MB];
+#pragma unroll
+        for (int s2 = 0; s2 < MB; ++s2) bond[s2] = vec4_t<T>{};
+        int cnt = 0;
+        constexpr int U = 4;
+        for (int e0 = 0; e0 < nc; e0 += U) {
+            uint32_t ent[U];
+            double4 rj[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) ent[u] = (e0 + u < nc) ? cand[size_t(e0 + u) * N + i] : 0u;
+#pragma unroll
+            for (int u = 0; u < U; ++u) rj[u] = (e0 + u < nc) ? R[nbr_j(ent[u])] : r4;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (e0 + u >= nc) break;
+                double d[3];
+                const double rr = exact_r2(ri, rj[u].x, rj[u].y, rj[u].z, h, nbr_n(ent[u], 0), nbr_n(ent[u], 1),
+                                           nbr_n(ent[u], 2), d);
+                if (!(rr < b.rc2)) continue;
+                if (cnt < b.cap) {
+                    nbr[size_t(cnt) * N + i] = ent[u];
+                    vec4_t<T> v;
+                    v.x = T(d[0]);
+                    v.y = T(d[1]);
+                    v.z = T(d[2]);
+                    v.w = T(sqrt(rr));
+#pragma unroll
+                    for (int s2 = 0; s2 < MB; ++s2)
+                        if (s2 == cnt) bond[s2] = v;
+                    if (cnt >= MB) dv[size_t(cnt) * N + i] = v;
+                }
+                ++cnt;
+            }
+        }
+        b.ncnt[size_t(slot) * N + i] = cnt;
+        if (cnt > b.cap) set_error(st, CFNEB_ENEIGH);
+        const int nb = min(cnt, b.cap);
         const TersoffT<T> P(b);
-        const vec4_t<T>* dv = reinterpret_cast<const vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
         vec4_t<T>* Pout = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.cap * N;
-        const int cnt = min(b.ncnt[size_t(slot) * N + i], b.cap);
-        // graphite and diamond environments have 3-4 bonds
-        if (cnt <= 4) {
-            ts_atom_regs<T, 4>(P, dv, Pout, N, i, cnt, acc);
+        if (nb <= MB) {
+            ts_atom_regs<T, MB>(P, bond, Pout, N, i, nb, acc);
         } else {
+#pragma unroll
+            for (int s2 = 0; s2 < MB; ++s2) dv[size_t(s2) * N + i] = bond[s2];
             vec2_t<T>* bo = reinterpret_cast<vec2_t<T>*>(b.bo) + size_t(slot) * b.cap * N;
-            ts_atom_generic<T>(P, dv, bo, Pout, N, i, cnt, acc);
+            ts_atom_generic<T>(P, dv, bo, Pout, N, i, nb, acc);
         }
     }
     block_sum<10>(acc, lds);
@@ -308,7 +358,7 @@ __device__ void ts_bonds_item(const BandDev& b, int slot, int tile, double* lds)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_ts_bonds(BatchDev bd, int all_images, int variant)
+__global__ void __launch_bounds__(CFNEB_TILE) k_ts_filter_bonds(BatchDev bd, int all_images, int variant)
 {
     __shared__ double lds[4 * 10];
     ItemLoop loop(bd, KIND_ATOM, all_images);
@@ -316,7 +366,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_bonds(BatchDev bd, int all_im
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         if (band_variant(b) != variant || band_stopped(b.st)) continue;  // uniform over the block
-        ts_bonds_item<T>(b, b.st->slot[it.image], it.tile, lds);
+        ts_filter_bonds_item<T>(b, b.st, b.st->slot[it.image], it.tile, lds);
     }
 }
 
@@ -382,11 +432,11 @@ void launch_tersoff_stage(const Launch& L, int all_images, int stage, hipStream_
 {
     const unsigned g = L.g[KIND_ATOM];
     if (L.variants & (1u << VARIANT_TS32)) {
-        if (stage == 0) k_ts_bonds<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS32);
+        if (stage == 0) k_ts_filter_bonds<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS32);
         if (stage == 1) k_ts_gather<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS32);
     }
     if (L.variants & (1u << VARIANT_TS64)) {
-        if (stage == 0) k_ts_bonds<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS64);
+        if (stage == 0) k_ts_filter_bonds<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS64);
         if (stage == 1) k_ts_gather<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS64);
     }
 }
