@@ -24,6 +24,16 @@ double orc::cell_factor_of(const orc_params* p, int n, const double* h0)
     return std::cbrt(std::fabs(orc_det3(h0))) * std::pow(double(n), 1.0 / 6.0);
 }
 
+int orc::cell_gauge(const orc_params* p, const double* C, double* D)
+{
+    if (p->cell_filter == 1) {
+        for (int k = 0; k < 9; ++k) D[k] = C[k];
+        const double det = orc_det3(D);
+        return (det > 0.0 && std::isfinite(det)) ? ORC_OK : ORC_ECELL;
+    }
+    return orc_symsqrt(C, D);
+}
+
 extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const double* X,
                            double* H, double* E, double* Fg, double* V,
                            double* Fout, double* Rout, double* hout)
@@ -31,7 +41,7 @@ extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const d
     const double cf = orc::cell_factor_of(p, n, h0);
     double B[9], D[9], h[9], Dinv[9], DinvT[9];
     for (int k = 0; k < 9; ++k) B[k] = X[3 * n + k] / cf;
-    int rc = orc_symsqrt(B, D);
+    int rc = orc::cell_gauge(p, B, D);
     if (rc != ORC_OK) return rc;
     orc::matmul3(h0, D, h);
     std::vector<double> R(3 * size_t(n)), F(3 * size_t(n));
@@ -69,6 +79,16 @@ extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const d
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c)
                 Fg[3 * n + 3 * r + c] = p->b_force_scale * (0.5 * (G[3 * r + c] + G[3 * c + r])) / cf;
+    } else if (p->cell_filter == 1) {
+        // D-variant (Sec. II.C, Eq. (13)): coordinates D, conjugate force D^-T V
+        double Veff[9];
+        for (int k = 0; k < 9; ++k) Veff[k] = vir[k];
+        for (int k = 0; k < 3; ++k) Veff[4 * k] -= P * omega;
+        orc_inv3(D, Dinv);
+        orc::transpose3(Dinv, DinvT);
+        double G[9];
+        orc::matmul3(DinvT, Veff, G);
+        for (int k = 0; k < 9; ++k) Fg[3 * n + k] = G[k] / cf;
     } else {
         for (int k = 0; k < 9; ++k) Fg[3 * n + k] = 0.0;
     }
@@ -112,7 +132,8 @@ extern "C" int orc_build_endpoints(const orc_params* p, int n, const double* RA,
     }
     for (int k = 0; k < 9; ++k) {
         XA[3 * n + k] = (k % 4 == 0) ? cf : 0.0;
-        XB[3 * n + k] = cf * BB[k];
+        // D-variant: the deformation gradient itself; rotation-free: B = D D^T
+        XB[3 * n + k] = cf * (p->cell_filter == 1 ? Draw[k] : BB[k]);
     }
     return ORC_OK;
 }

@@ -37,6 +37,11 @@ double cutoff_of(const orc_params* p);
 // have comparable lengths in the band's metric and comparable stiffness.
 double cell_factor_of(const orc_params* p, int n, const double* h0);
 
+// Deformation gradient D of an image from its cell coordinates C = (cell rows of X)/c_f:
+// the rotation-free filter stores C = B = D D^T and takes D = symsqrt(B); the D-variant
+// stores C = D itself (det D > 0 required).  ECELL otherwise.
+int cell_gauge(const orc_params* p, const double* C, double* D);
+
 }  // namespace orc
 
 #endif

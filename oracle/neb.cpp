@@ -676,7 +676,7 @@ extern "C" int orc_relax(const orc_params* p, int n, double* R, double* h, int m
     }
     double B[9], D[9];
     for (int k = 0; k < 9; ++k) B[k] = c.X[1][3 * n + k] / cf;
-    if (orc_symsqrt(B, D) != ORC_OK) return ORC_ECELL;
+    if (orc::cell_gauge(p, B, D) != ORC_OK) return ORC_ECELL;
     orc::rows_times(n, c.X[1].data(), D, R);
     orc::matmul3(h0, D, h);
     return ORC_OK;

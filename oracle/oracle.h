@@ -64,7 +64,7 @@ typedef struct orc_params {
     int max_images, min_images;
     double k_spring;         /* eV / A^2 */
     int climb_after;         /* climbing image from this step index on; <0 never */
-    int cell_filter;         /* 0: cell fixed; 2: rotation-free filter */
+    int cell_filter;         /* 0: cell fixed; 1: D-variant; 2: rotation-free filter */
     double cell_factor;      /* c_f; <= 0 means |det h0|^(1/3) n^(1/6) */
     double b_force_scale;    /* multiplies the printed lattice force D^-T V D^-1 */
     double pressure_GPa;     /* hydrostatic pressure, enthalpy H = U + P Omega */

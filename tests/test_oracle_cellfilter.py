@@ -138,3 +138,73 @@ def test_default_cell_factor_is_size_consistent(orc):
     assert stiff[0] > 0
     assert stiff[1] == pytest.approx(stiff[0], rel=1e-5)
     assert ratio[1] == pytest.approx(ratio[0], rel=1e-9)
+
+
+def _image_dvariant(orc, kind, pressure=0.0):
+    rng = np.random.default_rng(6)
+    if kind == "lj":
+        w = W.fcc_vacancy_hop(2, 2, 2, 1.5496)
+        p = orc.default_params(orc.LJ, pressure_GPa=pressure, cell_filter=1)
+    else:
+        w = W.graphite_to_diamond(2, 2, 3, seed=4, sigma=0.05)
+        p = orc.default_params(orc.TERSOFF, pressure_GPa=pressure, cell_filter=1)
+    # a final cell that is strained and rigidly rotated: the D-variant keeps the rotation
+    Q = _rot(11)
+    XA, XB = orc.build_endpoints(p, w["pos_init"], w["cell_init"], w["pos_final"] @ Q,
+                                 (w["cell_final"] @ np.diag([1.02, 0.99, 1.01])) @ Q)
+    X = 0.6 * XA + 0.4 * XB
+    X[:-3] += rng.normal(0, 0.02, X[:-3].shape)
+    return p, w["cell_init"], X
+
+
+@pytest.mark.parametrize("kind,pressure", [("lj", 0.0), ("ts", 15.0)])
+def test_d_variant_forces_by_finite_differences(orc, kind, pressure):
+    # D-variant of the filter (Sec. II.C, Eq. (13)): coordinates (R~, c_f D) with the
+    # full 3x3 D, forces (F D^T, D^-T V_eff / c_f); the lattice force is the exact
+    # conjugate of D, with no factor 1/2 and for all nine entries
+    p, h0, X = _image_dvariant(orc, kind, pressure)
+    out = orc.cf_eval(p, h0, X)
+    n = X.shape[0] - 3
+    delta = 1e-6
+    for i in [0, n // 2]:
+        for c in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, c] += delta
+            Xm[i, c] -= delta
+            fd = -(orc.cf_eval(p, h0, Xp)["H"] - orc.cf_eval(p, h0, Xm)["H"]) / (2 * delta)
+            assert out["Fg"][i, c] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+    dcell = delta * n
+    for m in range(3):
+        for k in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[n + m, k] += dcell
+            Xm[n + m, k] -= dcell
+            fd = -(orc.cf_eval(p, h0, Xp)["H"] - orc.cf_eval(p, h0, Xm)["H"]) / (2 * dcell)
+            assert out["Fg"][n + m, k] == pytest.approx(fd, rel=2e-5, abs=1e-8)
+
+
+def test_d_variant_keeps_rotations(orc):
+    # the rotation-free filter maps a rotated final cell to the same coordinates; the
+    # D-variant does not (its three extra coordinates are the rotation), while the
+    # enthalpy of the final image is the same either way
+    w = W.fcc_vacancy_hop(2, 2, 2, 1.5496)
+    Q = _rot(12)
+    for filt, same in ((2, True), (1, False)):
+        p = orc.default_params(orc.LJ, cell_filter=filt)
+        _, XB = orc.build_endpoints(p, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+        _, XBr = orc.build_endpoints(p, w["pos_init"], w["cell_init"], w["pos_final"] @ Q, w["cell_final"] @ Q)
+        assert np.allclose(XBr, XB, atol=1e-9) == same
+        a, b = orc.cf_eval(p, w["cell_init"], XB), orc.cf_eval(p, w["cell_init"], XBr)
+        assert b["H"] == pytest.approx(a["H"], rel=1e-12)
+    # a relaxation under either filter reaches the same enthalpy and cell metric h h^T
+    # from a strained start
+    R0, h0 = W.fcc_sites(2, 2, 2, 1.5496)
+    strain = np.array([[1.03, 0.01, 0.0], [0.0, 0.98, 0.0], [0.0, 0.0, 1.01]])
+    res = []
+    for filt in (1, 2):
+        p = orc.default_params(orc.LJ, cell_filter=filt, fire_dt0=0.01)
+        R, h, steps, fmax = orc.relax(p, R0 @ strain, h0 @ strain, 20000, 1e-7)
+        assert fmax < 1e-7
+        res.append((orc.evaluate(p, R, h)[0], h @ h.T))
+    assert res[0][0] == pytest.approx(res[1][0], abs=1e-9)
+    np.testing.assert_allclose(res[0][1], res[1][1], atol=1e-6)
