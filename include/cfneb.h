@@ -64,7 +64,9 @@ typedef struct cfneb_params {
     int min_images;         /* deletion never goes below this */
     double k_spring;        /* eV / A^2 */
     int climb_after;        /* climbing image from this step on; < 0: never */
-    int cell_filter;        /* 0: cell fixed; 2: rotation-free cell filter (Eq. (17)) */
+    int cell_filter;        /* 0: cell fixed; 1: D-variant, coordinates c_f D and force
+                               D^-T V / c_f (Eq. (13)); 2: rotation-free filter, c_f B
+                               and D^-T V D^-1 / c_f (Eq. (17)) */
     double cell_factor;     /* c_f, generalized cell coordinate c_f B;
                                <= 0: |det h0|^(1/3) n_atoms^(1/6) */
     double b_force_scale;   /* factor on the lattice force D^-T V D^-1 / c_f (default 1) */

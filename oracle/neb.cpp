@@ -410,7 +410,7 @@ extern "C" orc_band* orc_band_create(const orc_params* p, int n, const int32_t* 
     *err = ORC_EINVAL;
     if (n < 1 || p->n_images < 3 || p->max_images < p->n_images) return nullptr;
     if (p->potential != ORC_LJ && p->potential != ORC_TERSOFF) return nullptr;
-    if (p->cell_filter != 0 && p->cell_filter != 2) return nullptr;
+    if (p->cell_filter < 0 || p->cell_filter > 2) return nullptr;
     auto* b = new orc_band();
     b->p = *p;
     b->n = n;

@@ -122,13 +122,18 @@ __device__ void image_reduce_item(const BandDev& b, BandState* st, int slot, dou
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) DinvT[3 * r + c] = g.Dinv[3 * c + r];
     mm3(DinvT, Veff, T1);
-    mm3(T1, g.Dinv, G);
-    const double sc = (b.cell_filter == 2) ? b.bscale / b.cf : 0.0;
-    // the force conjugate to the symmetric B is the symmetric part of G (the FP32
-    // virial is symmetric only to rounding; an antisymmetric rest would move the
-    // cell rows along a direction the energy does not see)
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) s.Fcell[3 * r + c] = sc * (0.5 * (G[3 * r + c] + G[3 * c + r]));
+    if (b.cell_filter == 1) {
+        // D-variant (Eq. (13)): the conjugate of D is D^-T V_eff, all nine entries
+        for (int q = 0; q < 9; ++q) s.Fcell[q] = T1[q] / b.cf;
+    } else {
+        mm3(T1, g.Dinv, G);
+        const double sc = (b.cell_filter == 2) ? b.bscale / b.cf : 0.0;
+        // the force conjugate to the symmetric B is the symmetric part of G (the FP32
+        // virial is symmetric only to rounding; an antisymmetric rest would move the
+        // cell rows along a direction the energy does not see)
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) s.Fcell[3 * r + c] = sc * (0.5 * (G[3 * r + c] + G[3 * c + r]));
+    }
     if (!finite) set_error(st, CFNEB_ENONFINITE);
 }
 

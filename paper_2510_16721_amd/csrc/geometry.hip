@@ -64,7 +64,14 @@ __device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
     const double icf = 1.0 / b.cf;
     for (int q = 0; q < 3; ++q)
         for (int c = 0; c < 3; ++c) B[3 * q + c] = X[size_t(c) * b.ld + b.N + q] * icf;
-    if (!sym_sqrt(B, g.D)) return false;
+    if (b.cell_filter == 1) {
+        // D-variant: the cell rows hold c_f D itself (rotations included)
+        for (int q = 0; q < 9; ++q) g.D[q] = B[q];
+        const double det = det3(g.D);
+        if (!(det > 0.0) || !isfinite(det)) return false;
+    } else if (!sym_sqrt(B, g.D)) {
+        return false;
+    }
     inv3(g.D, g.Dinv);
     mm3(b.h0, g.D, g.h);
     inv3(g.h, g.hinv);
@@ -138,6 +145,7 @@ __global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_geom(BatchDev bd, int all_
 
 // ---------------------------------------------------------------- construction
 // staging: RA (3N, row-major) | RB (3N) | hA (9) | hB (9) | BB (9) | h0inv (9) | hBinv (9)
+//          | D_B (9)
 __global__ void k_init_endpoints(BandDev b)
 {
     double* sg = b.staging + 6 * size_t(b.N);
@@ -145,9 +153,10 @@ __global__ void k_init_endpoints(BandDev b)
     double* BB = sg + 18;
     double* h0inv = sg + 27;
     double* hBinv = sg + 36;
+    double* Dr = sg + 45;
     inv3(b.h0, h0inv);
     inv3(hB, hBinv);
-    double Dr[9], DrT[9];
+    double DrT[9];
     mm3(h0inv, hB, Dr);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) DrT[3 * i + j] = Dr[3 * j + i];
@@ -165,6 +174,7 @@ __global__ void k_init_images(BandDev b, int M)
     const double* BB = sg + 18;
     const double* h0inv = sg + 27;
     const double* hBinv = sg + 36;
+    const double* Dr = sg + 45;
     double xa[3], xb[3];
     if (r < b.N) {
         const double* a = RA + 3 * size_t(r);
@@ -184,7 +194,8 @@ __global__ void k_init_images(BandDev b, int M)
         const int row = r - b.N;
         for (int q = 0; q < 3; ++q) {
             xa[q] = (row == q) ? b.cf : 0.0;
-            xb[q] = b.cf * BB[3 * row + q];
+            // rotation-free filter: B of the final cell; D-variant: its D = h0^-1 h_B
+            xb[q] = b.cf * (b.cell_filter == 1 ? Dr[3 * row + q] : BB[3 * row + q]);
         }
     }
     double* X = Xs(b, k);

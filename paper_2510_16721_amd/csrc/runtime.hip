@@ -302,7 +302,7 @@ int validate(const cfneb_params* p, int64_t n_atoms)
     if (p->n_images < 3 || p->max_images < p->n_images || p->max_images > CFNEB_MAX_IMAGES)
         return CFNEB_EINVAL;
     if (p->min_images < 3) return CFNEB_EINVAL;
-    if (p->cell_filter != 0 && p->cell_filter != 2) return CFNEB_EINVAL;
+    if (p->cell_filter < 0 || p->cell_filter > 2) return CFNEB_EINVAL;
     if (p->nbr_cap < 1 || p->nbr_cap > 1024) return CFNEB_EINVAL;
     if (!(p->nbr_skin >= 0.0) || !(p->nbr_skin <= 2.0)) return CFNEB_EINVAL;
     if (!(p->fire_dt0 > 0.0) || !(p->fire_maxstep > 0.0)) return CFNEB_EINVAL;

@@ -323,3 +323,62 @@ def test_full_size_band_sampled_image():
     assert np.abs(img["V"] - V).max() / n <= TOL_V_PER_ATOM
     ref_cf = oracle.cf_eval(p, w["cell_init"], g.get_state()["X"][k])
     assert abs(ref_cf["H"] - img["H"]) / n <= TOL_E_PER_ATOM
+
+
+def _rotated_strained(name):
+    from gpu_cases import workload
+    w, kind = workload(name)
+    # a rotation by 0.15 rad about a seeded axis: linear interpolation of D between I
+    # and a rotation shrinks the middle images by about (1 - cos(angle/2)) in each
+    # direction (the reason for the rotation-free variant), so the angle is kept small
+    ax = np.random.default_rng(11).normal(size=3)
+    ax /= np.linalg.norm(ax)
+    Kx = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    ang = 0.15
+    Qm = np.eye(3) + np.sin(ang) * Kx + (1 - np.cos(ang)) * (Kx @ Kx)
+    w = dict(w)
+    w["pos_final"] = w["pos_final"] @ Qm
+    w["cell_final"] = (w["cell_final"] @ np.diag([1.02, 0.99, 1.01])) @ Qm
+    return w, kind
+
+
+@pytest.mark.parametrize("name,fp64", [("lj31", True), ("ts_small", False)])
+def test_d_variant_generalized_forces(name, fp64):
+    # D-variant filter (cell_filter 1) with a strained, rigidly rotated final cell: the
+    # coordinates keep the rotation; E, V and the generalized forces (F D^T, D^-T V/c_f)
+    # per image match the oracle's from the same coordinates
+    import oracle
+    from paper_2510_16721_amd import cfneb
+    w, kind = _rotated_strained(name)
+    press = 5.0 if kind == "ts" else 0.0
+    gp = cfneb.default_params(cfneb.CFNEB_LJ if kind == "lj" else cfneb.CFNEB_TERSOFF_C, n_images=5,
+                              max_images=5, cell_filter=1, pressure_GPa=press, force_fp64=1 if fp64 else 0)
+    op = oracle_params_like(kind, cell_filter=1, pressure_GPa=press)
+    g = cfneb.Band(gp, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+    XA, XB = oracle.build_endpoints(op, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+    st = g.get_state()
+    np.testing.assert_allclose(st["X"][-1], XB, rtol=0, atol=1e-9 * max(1.0, np.abs(XB).max()))
+    n = g.n
+    scale = 1e-6 if fp64 else 1.0
+    for k in range(5):
+        ref = oracle.cf_eval(op, w["cell_init"], st["X"][k])
+        img = g.image(k)
+        assert abs(img["H"] - ref["H"]) / n <= TOL_E_PER_ATOM * scale
+        np.testing.assert_allclose(img["h"], ref["h"], rtol=0, atol=1e-12)
+        assert np.abs(img["Fg"][:n] - ref["Fg"][:n]).max() <= 2 * TOL_F * scale
+        np.testing.assert_allclose(img["Fg"][n:], ref["Fg"][n:], rtol=0, atol=TOL_V_PER_ATOM * scale * 10)
+
+
+def test_d_variant_converged_barrier():
+    # the barrier does not depend on the filter variant: a D-variant LJ band converges
+    # to the oracle's barrier and to the rotation-free band's barrier within 1 meV
+    kw = dict(n_images=7, max_images=7, climb_after=50, k_spring=1.0, fire_dt0=0.005)
+    gd, od, w, kind = make_pair("lj31", fp64=True, cell_filter=1, **kw)
+    gb, _, _, _ = make_pair("lj31", fp64=True, oracle_too=False, cell_filter=2, **kw)
+    for band in (gd, od, gb):
+        steps, fmax, conv = band.step(6000, 1e-3)
+        assert conv
+    bd, bo, bb = gd.energies(), od.energies(), gb.energies()
+    assert abs(bd["barrier"] - bo["barrier"]) <= TOL_BARRIER
+    assert abs(bd["barrier"] - bb["barrier"]) <= TOL_BARRIER
+    assert bd["ci"] == bo["ci"] == 3
