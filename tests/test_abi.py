@@ -58,3 +58,22 @@ def test_band_bytes_and_argument_checks(L):
     with pytest.raises(cfneb.CfnebError):
         cfneb.band_bytes(bad, 10)
     assert L.cfneb_strerror(-5) == b"neighbour list capacity exceeded"
+
+
+def test_size_limits_are_rejected_on_the_host(L):
+    # atom indices are 20-bit: 2^20 - 1 atoms is the largest band, 2^20 is refused;
+    # an empty structure and an unknown filter are refused
+    from paper_2510_16721_amd import cfneb
+    p = cfneb.default_params(cfneb.CFNEB_TERSOFF_C, n_images=3, max_images=3)
+    assert cfneb.band_bytes(p, 2**20 - 1) > 0
+    for n in (0, -1, 2**20):
+        with pytest.raises(cfneb.CfnebError) as e:
+            cfneb.band_bytes(p, n)
+        assert e.value.code == -1
+    for filt in (-1, 3):
+        q = cfneb.default_params(cfneb.CFNEB_LJ, cell_filter=filt)
+        with pytest.raises(cfneb.CfnebError):
+            cfneb.band_bytes(q, 10)
+    q = cfneb.default_params(cfneb.CFNEB_LJ, nbr_skin=-0.1)
+    with pytest.raises(cfneb.CfnebError):
+        cfneb.band_bytes(q, 10)

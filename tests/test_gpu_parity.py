@@ -382,3 +382,34 @@ def test_d_variant_converged_barrier():
     assert abs(bd["barrier"] - bo["barrier"]) <= TOL_BARRIER
     assert abs(bd["barrier"] - bb["barrier"]) <= TOL_BARRIER
     assert bd["ci"] == bo["ci"] == 3
+
+
+def test_maximum_image_count():
+    # 64 images (the capacity of a band): construction and ten FP64 steps agree with
+    # the oracle
+    kw = dict(n_images=64, max_images=64, climb_after=5, fire_dt0=0.005)
+    g, o, w, kind = make_pair("lj31", fp64=True, **kw)
+    assert g.step(10)[0] == o.step(10)[0] == 10
+    np.testing.assert_allclose(g.get_state()["X"], o.get_state()["X"], rtol=0, atol=1e-9)
+    assert g.energies()["ci"] == o.energies()["ci"]
+
+
+def test_maximum_atom_count_sampled():
+    # 1,047,552 atoms (just under the 2^20 limit of the packed atom index): Tersoff
+    # graphite -> diamond-like band of three images, evaluated once; the moving image's
+    # energy per atom, virial and 256 sampled forces against the oracle
+    import oracle
+    import workloads as W
+    from paper_2510_16721_amd import cfneb
+    w = W.graphite_to_diamond(64, 62, 33, seed=5)
+    assert w["n"] == 1047552 < 2**20
+    p = cfneb.default_params(cfneb.CFNEB_TERSOFF_C, n_images=3, max_images=3)
+    g = cfneb.Band(p, w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+    img = g.image(1)
+    E, u, F, V = oracle.evaluate(oracle_params_like("ts"), img["R"], img["h"])
+    n = w["n"]
+    assert abs(img["E"] - E) / n <= TOL_E_PER_ATOM
+    assert np.abs(img["V"] - V).max() / n <= TOL_V_PER_ATOM
+    idx = np.random.default_rng(0).choice(n, 256, replace=False)
+    assert np.abs(img["F"][idx] - F[idx]).max() <= TOL_F
+    g.close()
