@@ -315,8 +315,16 @@ struct ItemLoop {
         const int local = L - off[lo];
         const int nt = kind_tiles(b, kind);
         it.band = lo;
-        it.tile = local % nt;
-        it.image = first + local / nt;
+        if (kind == KIND_ROW4) {
+            // tile-major: the same rows of consecutive images are neighbouring items,
+            // so the neighbour images' X read by the band passes come from L2
+            const int nimg = count / nt;
+            it.tile = local / nimg;
+            it.image = first + local % nimg;
+        } else {
+            it.tile = local % nt;
+            it.image = first + local / nt;
+        }
         return true;
     }
 };
