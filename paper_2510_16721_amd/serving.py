@@ -135,7 +135,9 @@ class Server:
 
 
 def summarize(done, wall):
-    lat = np.array([r.finished - r.arrival for r in done if r.error == 0])
+    """Latency percentiles over the requests that reached a converged barrier; requests
+    that failed or hit the step cap are counted apart."""
+    lat = np.array([r.finished - r.arrival for r in done if r.error == 0 and r.converged])
     work = sum(r.n_atoms * r.moving_image_steps for r in done)
     return dict(
         requests=len(done),
