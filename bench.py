@@ -60,6 +60,22 @@ def ts_bonds_flops_per_atom(B):
     return 26.0 * B + 40.0 * B + 65.0 * B * (B - 1.0) / 2.0
 
 
+def recorded_valu(kernel_source):
+    """VALU issue utilisation of the Tersoff kernel from the committed instruction-counter
+    summary; None if the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tersoff_graphite_98304_valu_counters.md")
+    try:
+        text = open(path).read()
+        blob = json.loads(text.split("```json")[1].split("```")[0])
+        src = open(os.path.join(ROOT, blob["source"]), "rb").read()
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+    if blob["kernel"] != kernel_source or hashlib.sha256(src).hexdigest() != blob["source_sha256"]:
+        return None
+    return blob["valu_issue_util"]
+
+
 def recorded_traffic(kernel_source, moving_images):
     """HBM bytes per dispatch of the Tersoff neighbour-and-bond kernel from the committed counter
     summary, scaled to the current number of moving images; None if the kernel's source
@@ -335,7 +351,8 @@ def main():
         roof = dict(bound="alu", kernel="k_ts_filter_bonds<float>", achieved=achieved,
                     peak=VALU_FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / VALU_FP32_PEAK_TFLOPS,
                     traffic=recorded_traffic("k_ts_filter_bonds<float>", mean_moving),
-                    algorithmic_bytes=(20.0 * mean_bonds + 40.0) * atoms)
+                    algorithmic_bytes=(20.0 * mean_bonds + 40.0) * atoms,
+                    valu_issue_util=recorded_valu("k_ts_filter_bonds<float>"))
     elif dom in ALGO:
         m = ALGO[dom]
         units = rows if m["per"] == "row" else atoms
