@@ -271,6 +271,8 @@ def bench_serving(args):
         "p50_s": s["p50_s"], "atom_steps_per_s": s["atom_steps_per_s"], "wall_s": wall,
         "converged": s["converged"], "failed": s["failed"], "capped": s["capped"],
         "mean_active_bands": float(occ.mean()), "max_active_bands": int(occ.max()),
+        "capped_requests": [[r.rid, mix[r.rid]["kind"], r.n_atoms, mix[r.rid]["n_images"]]
+                            for r in done if r.error == 0 and not r.converged],
         "vs_baseline": None,
     }
 

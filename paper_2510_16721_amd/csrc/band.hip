@@ -394,7 +394,10 @@ __global__ void __launch_bounds__(1024) k_band_finalize(BatchDev bd)
         const BandDev& b = bd.bands[it.band];
         BandState* st = b.st;
         if (band_stopped(st)) {  // uniform over the block
-            if (threadIdx.x == 0) st->move = 0;
+            if (threadIdx.x == 0) {
+                st->move = 0;
+                st->refine_due = 0;  // finalize sets it afresh on every step that runs
+            }
             continue;
         }
         finalize_item(b, st, lds);

@@ -303,15 +303,6 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_apply(BatchDev bd, int mo
     }
 }
 
-__global__ void k_refine_end(BatchDev bd)
-{
-    if (*refine_flag(bd) == 0) return;  // no band was due this step
-    ItemLoop loop(bd, KIND_BAND, 0);
-    Item it;
-    while (loop.next(it))
-        if (threadIdx.x == 0) bd.bands[it.band].st->refine_due = 0;
-}
-
 // H in logical order, barrier, path coordinate (from the exact spacings).
 __global__ void k_readout(BatchDev bd)
 {
@@ -348,7 +339,6 @@ void launch_refine(const Launch& L, int forced, hipStream_t s)
     k_refine_dist<<<L.g[KIND_IVAL], CFNEB_TILE, 0, s>>>(L.bd, mode);
     k_refine_decide<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd, mode);
     k_refine_apply<<<L.g[KIND_SLOTROW], CFNEB_TILE, 0, s>>>(L.bd, mode);
-    k_refine_end<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd);
 }
 
 // Readout after launch_plan(..., ignore_stop = 1).
