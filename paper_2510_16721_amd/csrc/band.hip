@@ -49,45 +49,94 @@ __global__ void k_begin_call(BatchDev bd, double f_tol, int only)
 }
 
 // 10 dots per moving image: |t+|^2 |t-|^2 t+.t- F.t+ F.t- F.F F.v v.v v.t+ v.t-,
-// then the atom-row sums of t+ (3), t- (3), F (3) and v (3).  An item is 1024 rows,
-// four per thread (rows tile*1024 + q*256 + thread, so every load is coalesced).
+// then the atom-row sums of t+ (3), t- (3), F (3) and v (3).
+__device__ inline void dots_row(double* a, const double (&x0)[3], const double (&xm)[3], const double (&xp)[3],
+                                const double (&v)[3], const double (&f)[3], bool atom)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double tp = xp[c] - x0[c], tm = x0[c] - xm[c];
+        a[0] += tp * tp;
+        a[1] += tm * tm;
+        a[2] += tp * tm;
+        a[3] += f[c] * tp;
+        a[4] += f[c] * tm;
+        a[5] += f[c] * f[c];
+        a[6] += f[c] * v[c];
+        a[7] += v[c] * v[c];
+        a[8] += v[c] * tp;
+        a[9] += v[c] * tm;
+        if (atom) {
+            a[10 + c] += tp;
+            a[13 + c] += tm;
+            a[16 + c] += f[c];
+            a[19 + c] += v[c];
+        }
+    }
+}
+
+// Generalized force of an atom row from its Cartesian force: F D^T.
+template <typename T, typename DP>
+__device__ inline void atom_gen_force(const DP D, const T (&fr)[3], double (&f)[3])
+{
+    const double fx = double(fr[0]), fy = double(fr[1]), fz = double(fr[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f[c] = fx * D[3 * c] + fy * D[3 * c + 1] + fz * D[3 * c + 2];
+}
+
+// An item is 1024 rows, four per thread (rows tile*1024 + q*256 + thread, so every
+// load is coalesced).  A tile of atom rows only issues all loads of its four rows
+// before any arithmetic; the image's last tile (cell rows, ragged end) goes row by row.
 template <typename T>
 __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
+    constexpr int Q = CFNEB_TILE4 / CFNEB_TILE;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double a[CFNEB_NDOT];
 #pragma unroll
     for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
-    const double* __restrict__ X0 = Xs(b, s0);
-    const double* __restrict__ Xm = Xs(b, sm);
-    const double* __restrict__ Xp = Xs(b, sp);
-    const double* __restrict__ V = Vs(b, st->vcur, s0);
+    const gmem<const double>* __restrict__ X0 = gp<const double>(Xs(b, s0));
+    const gmem<const double>* __restrict__ Xm = gp<const double>(Xs(b, sm));
+    const gmem<const double>* __restrict__ Xp = gp<const double>(Xs(b, sp));
+    const gmem<const double>* __restrict__ V = gp<const double>(Vs(b, st->vcur, s0));
+    const gmem<const T>* __restrict__ F = gp<const T>(reinterpret_cast<const T*>(b.F) + size_t(s0) * slot_rows(b));
+    const size_t ld = b.ld;
+    const int r0 = tile * CFNEB_TILE4 + int(threadIdx.x);
+    if ((tile + 1) * CFNEB_TILE4 <= b.N) {  // uniform over the block
+        double x0[Q][3], xm[Q][3], xp[Q][3], v[Q][3];
+        T fr[Q][3];
 #pragma unroll
-    for (int q4 = 0; q4 < CFNEB_TILE4 / CFNEB_TILE; ++q4) {
-        const int r = tile * CFNEB_TILE4 + q4 * CFNEB_TILE + threadIdx.x;
-        if (r >= b.N + 3) continue;
-        double f[3];
-        gen_force_row<T>(b, s0, r, f);
-        for (int c = 0; c < 3; ++c) {
-            const size_t o = size_t(c) * b.ld + r;
-            const double x = X0[o];
-            const double tp = Xp[o] - x, tm = x - Xm[o], v = V[o];
-            a[0] += tp * tp;
-            a[1] += tm * tm;
-            a[2] += tp * tm;
-            a[3] += f[c] * tp;
-            a[4] += f[c] * tm;
-            a[5] += f[c] * f[c];
-            a[6] += f[c] * v;
-            a[7] += v * v;
-            a[8] += v * tp;
-            a[9] += v * tm;
-            if (r < b.N) {
-                a[10 + c] += tp;
-                a[13 + c] += tm;
-                a[16 + c] += f[c];
-                a[19 + c] += v;
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * ld + (r0 + q * CFNEB_TILE);
+                x0[q][c] = X0[o];
+                xm[q][c] = Xm[o];
+                xp[q][c] = Xp[o];
+                v[q][c] = V[o];
+                fr[q][c] = F[o];
             }
+        const gmem<const double>* D = gp<const double>(b.geom[s0].D);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            double f[3];
+            atom_gen_force<T>(D, fr[q], f);
+            dots_row(a, x0[q], xm[q], xp[q], v[q], f, true);
+        }
+    } else {
+        for (int q = 0; q < Q; ++q) {
+            const int r = r0 + q * CFNEB_TILE;
+            if (r >= b.N + 3) break;
+            double x0[3], xm[3], xp[3], v[3], f[3];
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * ld + r;
+                x0[c] = X0[o];
+                xm[c] = Xm[o];
+                xp[c] = Xp[o];
+                v[c] = V[o];
+            }
+            gen_force_row<T>(b, s0, r, f);
+            dots_row(a, x0, xm, xp, v, f, r < b.N);
         }
     }
     block_sum<CFNEB_NDOT>(a, lds);
@@ -272,50 +321,113 @@ __global__ void __launch_bounds__(1024) k_band_scalars(BatchDev bd)
     }
 }
 
-// F_NEB per row, v' = (cv v + cf F_NEB) + dt' F_NEB into the other buffer, and the
-// row maxima of |F_NEB| and |dt' v'|; 1024 rows per item, four per thread.
+// One row of F_NEB = Fg - mean + cp (tau+ - mean) + cm (tau- - mean) (means for atom
+// rows only), v' = (cv v + cf F_NEB) + dt' F_NEB; returns |F_NEB|^2 and |dt' v'|^2.
+struct UpdateCoef {
+    double cp, cm, cv, cf, dt;
+    const double* mean;
+};
+__device__ inline void update_row(const UpdateCoef& u, const double (&x0)[3], const double (&xm)[3],
+                                  const double (&xp)[3], const double (&v)[3], const double (&f)[3], bool atom,
+                                  double (&fn)[3], double (&vn)[3], double& f2, double& v2)
+{
+    f2 = 0.0;
+    v2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double tp = xp[c] - x0[c], tm = x0[c] - xm[c], fc = f[c];
+        if (atom) {
+            tp -= u.mean[c];
+            tm -= u.mean[3 + c];
+            fc -= u.mean[6 + c];
+        }
+        fn[c] = fc + u.cp * tp + u.cm * tm;
+        vn[c] = (u.cv * v[c] + u.cf * fn[c]) + u.dt * fn[c];
+        f2 += fn[c] * fn[c];
+        const double dr = u.dt * vn[c];
+        v2 += dr * dr;
+    }
+}
+
+// F_NEB per row, the new velocity into the other buffer, and the row maxima of
+// |F_NEB| and |dt' v'|; 1024 rows per item, four per thread, loads of atom-row tiles
+// all issued before the first store.
 template <typename T>
 __device__ void update_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
+    constexpr int Q = CFNEB_TILE4 / CFNEB_TILE;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
     double m[3] = {0.0, 0.0, 0.0};  // max |F_NEB row|^2, max |dr row|^2, non-finite flag
-    const double cp = st->cplus[k], cm = st->cminus[k];
-    const double cv = st->cv, cf = st->cf, dt = st->dt_new;
-    const double* mean = st->tmean[k];
-    const double* X0 = Xs(b, s0);
-    const double* Xm = Xs(b, sm);
-    const double* Xp = Xs(b, sp);
-    const double* V = Vs(b, st->vcur, s0);
-    double* Vn = Vs(b, st->vcur ^ 1, s0);
-    double* FN = b.FN + size_t(s0) * slot_rows(b);
+    UpdateCoef u;
+    u.cp = st->cplus[k];
+    u.cm = st->cminus[k];
+    u.cv = st->cv;
+    u.cf = st->cf;
+    u.dt = st->dt_new;
+    u.mean = st->tmean[k];
+    const gmem<const double>* __restrict__ X0 = gp<const double>(Xs(b, s0));
+    const gmem<const double>* __restrict__ Xm = gp<const double>(Xs(b, sm));
+    const gmem<const double>* __restrict__ Xp = gp<const double>(Xs(b, sp));
+    const gmem<const double>* __restrict__ V = gp<const double>(Vs(b, st->vcur, s0));
+    const gmem<const T>* __restrict__ F = gp<const T>(reinterpret_cast<const T*>(b.F) + size_t(s0) * slot_rows(b));
+    gmem<double>* __restrict__ Vn = gp(Vs(b, st->vcur ^ 1, s0));
+    gmem<double>* __restrict__ FN = gp(b.FN + size_t(s0) * slot_rows(b));
     const int rec = st->record_fneb;
-    for (int q4 = 0; q4 < CFNEB_TILE4 / CFNEB_TILE; ++q4) {
-        const int r = tile * CFNEB_TILE4 + q4 * CFNEB_TILE + threadIdx.x;
-        if (r >= b.N + 3) break;
-        const bool atom = r < b.N;
-        double f[3];
-        gen_force_row<T>(b, s0, r, f);
-        double f2 = 0.0, v2 = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            const size_t o = size_t(c) * b.ld + r;
-            const double x = X0[o];
-            double tp = Xp[o] - x, tm = x - Xm[o], fc = f[c];
-            if (atom) {
-                tp -= mean[c];
-                tm -= mean[3 + c];
-                fc -= mean[6 + c];
+    const size_t ld = b.ld;
+    const int r0 = tile * CFNEB_TILE4 + int(threadIdx.x);
+    if ((tile + 1) * CFNEB_TILE4 <= b.N) {  // uniform over the block
+        double x0[Q][3], xm[Q][3], xp[Q][3], v[Q][3];
+        T fr[Q][3];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * ld + (r0 + q * CFNEB_TILE);
+                x0[q][c] = X0[o];
+                xm[q][c] = Xm[o];
+                xp[q][c] = Xp[o];
+                v[q][c] = V[o];
+                fr[q][c] = F[o];
             }
-            const double fn = fc + cp * tp + cm * tm;
-            const double vn = (cv * V[o] + cf * fn) + dt * fn;
-            Vn[o] = vn;
-            if (rec) FN[o] = fn;
-            f2 += fn * fn;
-            const double dr = dt * vn;
-            v2 += dr * dr;
+        const gmem<const double>* D = gp<const double>(b.geom[s0].D);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            double f[3], fn[3], vn[3], f2, v2;
+            atom_gen_force<T>(D, fr[q], f);
+            update_row(u, x0[q], xm[q], xp[q], v[q], f, true, fn, vn, f2, v2);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * ld + (r0 + q * CFNEB_TILE);
+                Vn[o] = vn[c];
+                if (rec) FN[o] = fn[c];
+            }
+            m[0] = fmax(m[0], f2);
+            m[1] = fmax(m[1], v2);
+            if (!(isfinite(f2) && isfinite(v2))) m[2] = 1.0;
         }
-        m[0] = fmax(m[0], f2);
-        m[1] = fmax(m[1], v2);
-        if (!(isfinite(f2) && isfinite(v2))) m[2] = 1.0;
+    } else {
+        for (int q = 0; q < Q; ++q) {
+            const int r = r0 + q * CFNEB_TILE;
+            if (r >= b.N + 3) break;
+            double x0[3], xm[3], xp[3], v[3], f[3], fn[3], vn[3], f2, v2;
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * ld + r;
+                x0[c] = X0[o];
+                xm[c] = Xm[o];
+                xp[c] = Xp[o];
+                v[c] = V[o];
+            }
+            gen_force_row<T>(b, s0, r, f);
+            update_row(u, x0, xm, xp, v, f, r < b.N, fn, vn, f2, v2);
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * ld + r;
+                Vn[o] = vn[c];
+                if (rec) FN[o] = fn[c];
+            }
+            m[0] = fmax(m[0], f2);
+            m[1] = fmax(m[1], v2);
+            if (!(isfinite(f2) && isfinite(v2))) m[2] = 1.0;
+        }
     }
     block_max<3>(m, lds);
     if (threadIdx.x == 0) {
@@ -417,8 +529,8 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_move(BatchDev bd)
         const int r = it.tile * CFNEB_TILE + threadIdx.x;
         if (r >= b.N + 3) continue;
         const int s0 = st->slot[it.image];
-        double* X = Xs(b, s0);
-        const double* V = Vs(b, st->vcur, s0);
+        gmem<double>* __restrict__ X = gp(Xs(b, s0));
+        const gmem<const double>* __restrict__ V = gp<const double>(Vs(b, st->vcur, s0));
         const double sc = st->scale, dt = st->dt;
         for (int c = 0; c < 3; ++c) {
             const size_t o = size_t(c) * b.ld + r;

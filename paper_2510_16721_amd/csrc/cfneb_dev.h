@@ -141,9 +141,15 @@ struct BandDev {
     int* ncand;         // [slot][N]
     double* Rref;       // [slot][3][ld] positions at the candidate build
     SkinState* skst;    // [slot]
+    // Tersoff bond scratch: bond vectors and bond orders past the fourth bond
+    // ([slot][cap][N]), the candidate slot of each such bond, the per-candidate
+    // derivatives P ([slot][ccap][N], zero for candidates that are not bonds) and the
+    // reverse candidate of each candidate (the slot of (i, -n) in j's list).
     void* dvec;
     void* bo;
+    uint16_t* bcid;
     void* P;
+    uint16_t* crev;
     ImageGeom* geom;
     ImageScal* scal;
     double* evpart;     // [slot][ntA][10]
@@ -156,6 +162,45 @@ struct BandDev {
 };
 
 // ---------------------------------------------------------------- helpers
+// Global-memory views of device pointers.  A pointer read out of a struct is generic
+// to the compiler, which then emits flat accesses (counted against the LDS/scalar
+// counter as well, so waits are coarser and loads cannot go through the scalar
+// cache); accesses through these views compile to global (or scalar) loads.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ inline gmem<T>* gp(T* p)
+{
+    return (gmem<T>*)p;
+}
+// HIP's vector structs cannot be copied through such a view; these move them as
+// native 4-vectors.
+template <typename T>
+using nvec4 = T __attribute__((ext_vector_type(4)));
+template <typename V>
+__device__ inline V load4(const gmem<const V>* p, size_t i)
+{
+    using E = decltype(V().x);
+    const nvec4<E> v = reinterpret_cast<const gmem<const nvec4<E>>*>(p)[i];
+    V o;
+    o.x = v.x;
+    o.y = v.y;
+    o.z = v.z;
+    o.w = v.w;
+    return o;
+}
+template <typename V>
+__device__ inline void store4(gmem<V>* p, size_t i, const V& o)
+{
+    using E = decltype(V().x);
+    nvec4<E> v;
+    v.x = o.x;
+    v.y = o.y;
+    v.z = o.z;
+    v.w = o.w;
+    reinterpret_cast<gmem<nvec4<E>>*>(p)[i] = v;
+}
+
 __host__ __device__ inline size_t slot_rows(const BandDev& b) { return size_t(3) * b.ld; }
 
 __device__ inline double* Xs(const BandDev& b, int slot) { return b.X + size_t(slot) * slot_rows(b); }
@@ -458,6 +503,7 @@ void launch_skin(const Launch& L, int all_images, hipStream_t s);
 void launch_bins(const Launch& L, int all_images, hipStream_t s);
 void launch_list(const Launch& L, int all_images, hipStream_t s);
 void launch_filter(const Launch& L, int all_images, hipStream_t s);
+void launch_neighbour_lists(const Launch& L, hipStream_t s);
 void launch_force_stage(const Launch& L, int all_images, int stage, hipStream_t s);
 void launch_tersoff_stage(const Launch& L, int all_images, int stage, hipStream_t s);
 void launch_image_reduce(const Launch& L, int all_images, hipStream_t s);

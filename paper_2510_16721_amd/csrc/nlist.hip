@@ -55,10 +55,16 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
         const BandState* st = b.st;
         if (band_stopped(st)) continue;  // uniform over the block
         const int slot = st->slot[it.image];
-        const ImageGeom& g = b.geom[slot];
+        const gmem<const ImageGeom>* g = gp<const ImageGeom>(b.geom + slot);
+        double D[9], E[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            D[q] = g->D[q];
+            E[q] = g->E[q];
+        }
         const bool valid = b.skst[slot].valid != 0;
-        const double* __restrict__ X = Xs(b, slot);
-        const double* __restrict__ Rr = b.Rref + size_t(slot) * slot_rows(b);
+        const gmem<const double>* __restrict__ X = gp<const double>(Xs(b, slot));
+        const gmem<const double>* __restrict__ Rr = gp<const double>(b.Rref + size_t(slot) * slot_rows(b));
         double x[Q][3], a[Q][3];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -71,18 +77,18 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
             }
         }
         double m[1] = {0.0};
-        double4* __restrict__ R = Rs(b, slot);
+        gmem<double4>* __restrict__ R = gp(Rs(b, slot));
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
             if (i >= b.N) continue;
             double r[3];
-            for (int c = 0; c < 3; ++c) r[c] = (x[q][0] * g.D[c] + x[q][1] * g.D[3 + c]) + x[q][2] * g.D[6 + c];
-            R[i] = make_double4(r[0], r[1], r[2], 0.0);
+            for (int c = 0; c < 3; ++c) r[c] = (x[q][0] * D[c] + x[q][1] * D[3 + c]) + x[q][2] * D[6 + c];
+            store4(R, i, make_double4(r[0], r[1], r[2], 0.0));
             if (valid) {
                 double d2 = 0.0;
                 for (int c = 0; c < 3; ++c) {
-                    const double ref = a[q][c] + ((a[q][0] * g.E[c] + a[q][1] * g.E[3 + c]) + a[q][2] * g.E[6 + c]);
+                    const double ref = a[q][c] + ((a[q][0] * E[c] + a[q][1] * E[3 + c]) + a[q][2] * E[6 + c]);
                     const double d = r[c] - ref;
                     d2 += d * d;
                 }
@@ -433,7 +439,7 @@ __device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
 
 // vmask: the band variants (potential, force precision) this launch serves
 template <typename T, bool STORE_BONDS>
-__global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_images, unsigned vmask)
+__global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_images, unsigned vmask, int ignore_stop)
 {
     ItemLoop loop(bd, KIND_ATOM, all_images);
     Item it;
@@ -442,7 +448,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_imag
         if (!((vmask >> band_variant(b)) & 1u)) continue;
         BandState* st = b.st;
         const int i = it.tile * CFNEB_TILE + threadIdx.x;
-        if (band_stopped(st) || i >= b.N) continue;
+        if ((!ignore_stop && band_stopped(st)) || i >= b.N) continue;
         filter_item<T, STORE_BONDS>(b, st, st->slot[it.image], i);
     }
 }
@@ -471,7 +477,18 @@ void launch_filter(const Launch& L, int all_images, hipStream_t s)
 {
     const unsigned g = L.g[KIND_ATOM];
     const unsigned lj = L.variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_LJ64));
-    if (lj) k_filter<double, false><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj);
+    if (lj) k_filter<double, false><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj, 0);
+}
+
+// Packed neighbour lists of every image of the table's Tersoff bands, for a host
+// readout (their step path keeps per-candidate data only): the exact test of the
+// current candidates on the positions and cell of the last evaluation.
+void launch_neighbour_lists(const Launch& L, hipStream_t s)
+{
+    const unsigned ts = L.variants & ((1u << VARIANT_TS32) | (1u << VARIANT_TS64));
+    if (!ts) return;
+    launch_plan(L, 1, 1, s);
+    k_filter<double, false><<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, 1, ts, 1);
 }
 
 }  // namespace cfneb

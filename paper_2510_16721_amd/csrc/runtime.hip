@@ -23,7 +23,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     int N, ld, Mcap, ntA, ntR, ntR4, nbcap, cap, ccap, fp64, tersoff;
-    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, P, geom, scal, dotred,
+    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, bcid, P, crev, geom,
+        scal, dotred,
         evpart, dotpart, maxpart, refpart, staging, state, table, live, plan, total;
 };
 
@@ -46,6 +47,8 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
         const double ratio = (rc + p->nbr_skin) / rc;
         L->ccap = int(std::ceil(1.25 * p->nbr_cap * ratio * ratio * ratio));
     }
+    // Tersoff candidate slots are 16-bit in the reverse index
+    if (p->potential == CFNEB_TERSOFF_C && L->ccap > 65535) return false;
     L->fp64 = p->force_fp64 ? 1 : 0;
     L->tersoff = (p->potential == CFNEB_TERSOFF_C) ? 1 : 0;
     const size_t M = size_t(L->Mcap), N = size_t(L->N), rows = 3 * size_t(L->ld);
@@ -73,7 +76,9 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->skin = take(M * sizeof(SkinState));
     L->dvec = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
     L->bo = take(L->tersoff ? M * size_t(L->cap) * N * 2 * tsz : 0);
-    L->P = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
+    L->bcid = take(L->tersoff ? M * size_t(L->cap) * N * 2 : 0);
+    L->P = take(L->tersoff ? M * size_t(L->ccap) * N * 4 * tsz : 0);
+    L->crev = take(L->tersoff ? M * size_t(L->ccap) * N * 2 : 0);
     L->geom = take(M * sizeof(ImageGeom));
     L->scal = take(M * sizeof(ImageScal));
     L->evpart = take(M * L->ntA * 10 * 8);
@@ -273,7 +278,9 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.skst = reinterpret_cast<SkinState*>(base + L.skin);
     d.dvec = L.tersoff ? base + L.dvec : nullptr;
     d.bo = L.tersoff ? base + L.bo : nullptr;
+    d.bcid = L.tersoff ? reinterpret_cast<uint16_t*>(base + L.bcid) : nullptr;
     d.P = L.tersoff ? base + L.P : nullptr;
+    d.crev = L.tersoff ? reinterpret_cast<uint16_t*>(base + L.crev) : nullptr;
     d.geom = reinterpret_cast<ImageGeom*>(base + L.geom);
     d.scal = reinterpret_cast<ImageScal*>(base + L.scal);
     d.evpart = reinterpret_cast<double*>(base + L.evpart);
@@ -824,6 +831,11 @@ int cfneb_neighbours(const cfneb_band* cb, int k, int32_t* cnt, int32_t* ent, in
     const int slot = image_slot(b, k);
     if (slot < 0) return CFNEB_EINVAL;
     const size_t N = size_t(b->L.N), C = size_t(b->L.cap);
+    if (b->L.tersoff) {
+        launch_neighbour_lists(b->launch, b->stream);
+        HIP_TRY(b, hipGetLastError());
+        HIP_TRY(b, hipStreamSynchronize(b->stream));
+    }
     std::vector<uint32_t> nb(C * N);
     HIP_TRY(b, hipMemcpy(cnt, b->d.ncnt + size_t(slot) * N, N * 4, hipMemcpyDeviceToHost));
     HIP_TRY(b, hipMemcpy(nb.data(), b->d.nbr + size_t(slot) * C * N, nb.size() * 4, hipMemcpyDeviceToHost));

@@ -5,8 +5,13 @@
 //   fc = 1 below R, 1/2 + 1/2 cos(pi (r - R)/(S - R)) between R and S, 0 beyond.
 // U_i depends only on i's bond vectors, so one thread per atom finds its neighbours
 // among its candidates (exact test), keeps the bond vectors in registers and forms
-// every P_ij = dU_i/dr^ij; a second kernel gathers F_i = sum_j (P_ij - P_ji) through
-// the reverse entry (i, -n) of j's list.  No atomics: the result is deterministic.
+// every P_ij = dU_i/dr^ij, stored in the pair's candidate slot (zero for candidates
+// that are not bonds); a second kernel gathers F_i = sum_j (P_ij - P_ji) over the
+// candidates, P_ji read from the reverse candidate (i, -n) of j's list.  The exact
+// inclusion test is symmetric to the last bit (the separation of (j, i, -n) is the
+// negated separation of (i, j, n) in every rounding), so a pair and its reverse are
+// bonds together.  The reverse slots are found once per candidate build.  No
+// atomics: the result is deterministic.
 //
 // g is evaluated as 1 + (c^2/d^2) x / (d^2 + x), x = (h - cos)^2: the textbook form
 // 1 + c^2/d^2 - c^2/(d^2 + x) cancels two numbers near 7.7e7 and loses about four
@@ -108,8 +113,8 @@ __device__ inline void add_virial(double* acc, T dx, T dy, T dz, T px, T py, T p
 // g(cos) and g'(cos) are symmetric in the two bonds, so each unordered bond pair is
 // evaluated once: it adds to both zetas, and its derivative to both P's.
 template <typename T, int MAXB>
-__device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB], vec4_t<T>* Pout, size_t N,
-                             int i, int cnt, double* acc)
+__device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB], const int (&cid)[MAXB],
+                             gmem<vec4_t<T>>* Pout, size_t N, int i, int cnt, double* acc)
 {
     constexpr int NP = MAXB * (MAXB - 1) / 2;
     T dx[MAXB], dy[MAXB], dz[MAXB], ir[MAXB], fc[MAXB], dfc[MAXB], fr[MAXB], fa[MAXB];
@@ -214,14 +219,14 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
         o.y = py[e];
         o.z = pz[e];
         o.w = T(0);
-        Pout[size_t(e) * N + i] = o;
+        store4(Pout, size_t(cid[e]) * N + i, o);
         add_virial<T>(acc, dx[e], dy[e], dz[e], px[e], py[e], pz[e]);
     }
 }
 
 // Any number of bonds: bond orders go through the per-bond scratch array.
 template <typename T>
-__device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_t<T>* bo,
+__device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_t<T>* bo, const uint16_t* bcid,
                                 vec4_t<T>* Pout, size_t N, int i, int cnt, double* acc)
 {
     for (int e = 0; e < cnt; ++e) {
@@ -275,9 +280,38 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
         o.y = py;
         o.z = pz;
         o.w = T(0);
-        Pout[size_t(e) * N + i] = o;
+        Pout[size_t(bcid[size_t(e) * N + i]) * N + i] = o;
         add_virial<T>(acc, de.x, de.y, de.z, px, py, pz);
     }
+}
+
+// Reverse candidate of each of atom i's candidates: the slot of (i, -n) in j's list.
+// Runs on the steps that rebuild the image's candidates.
+__device__ void ts_reverse_candidates(const BandDev& b, BandState* st, int slot, int i, int nc)
+{
+    const size_t N = b.N;
+    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
+    const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
+    gmem<uint16_t>* __restrict__ crev = gp(b.crev + size_t(slot) * b.ccap * N);
+    bool missing = false;
+    for (int c = 0; c < nc; ++c) {
+        const uint32_t ent = cand[size_t(c) * N + i];
+        const int j = nbr_j(ent);
+        const uint32_t want = pack_nbr(i, -nbr_n(ent, 0), -nbr_n(ent, 1), -nbr_n(ent, 2));
+        const int cj = ncand[j];
+        int found = -1;
+        for (int q = 0; q < cj; ++q)
+            if (cand[size_t(q) * N + j] == want) {
+                found = q;
+                break;
+            }
+        if (found < 0) {
+            missing = true;
+            found = 0;
+        }
+        crev[size_t(c) * N + i] = uint16_t(found);
+    }
+    if (missing) set_error(st, CFNEB_ENEIGH);
 }
 
 // Neighbours of atom i by the exact test of its candidates (as the candidate filter
@@ -293,36 +327,51 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < b.N) {
         const ImageGeom& g = b.geom[slot];
-        const double4* R = Rs(b, slot);
-        const uint32_t* cand = b.cand + size_t(slot) * b.ccap * N;
-        uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
+        const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
+        const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
+        vec4_t<T>* Praw = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.ccap * N;
+        gmem<vec4_t<T>>* __restrict__ Pout = gp(Praw);
         vec4_t<T>* dv = reinterpret_cast<vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
+        uint16_t* bcid = b.bcid + size_t(slot) * b.cap * N;
         double h[9];
         for (int q = 0; q < 9; ++q) h[q] = g.h[q];
-        const double4 r4 = R[i];
+        const double4 r4 = load4(R, i);
         const double ri[3] = {r4.x, r4.y, r4.z};
-        const int nc = b.ncand[size_t(slot) * N + i];
+        const int nc = gp<const int>(b.ncand)[size_t(slot) * N + i];
+        const double rc2 = b.rc2;
+        const int cap = b.cap;
+        if (b.skst[slot].rebuild) ts_reverse_candidates(b, st, slot, i, nc);
         vec4_t<T> bond[MB];
+        int cid[MB];
 #pragma unroll
-        for (int s2 = 0; s2 < MB; ++s2) bond[s2] = vec4_t<T>{};
+        for (int s2 = 0; s2 < MB; ++s2) {
+            bond[s2] = vec4_t<T>{};
+            cid[s2] = 0;
+        }
+        vec4_t<T> zero{};
         int cnt = 0;
         constexpr int U = 4;
         for (int e0 = 0; e0 < nc; e0 += U) {
             uint32_t ent[U];
             double4 rj[U];
+            // past the last candidate the loads repeat it (in bounds, no branch
+            // between the loads); the tests below stop there
 #pragma unroll
-            for (int u = 0; u < U; ++u) ent[u] = (e0 + u < nc) ? cand[size_t(e0 + u) * N + i] : 0u;
+            for (int u = 0; u < U; ++u) ent[u] = cand[size_t(min(e0 + u, nc - 1)) * N + i];
 #pragma unroll
-            for (int u = 0; u < U; ++u) rj[u] = (e0 + u < nc) ? R[nbr_j(ent[u])] : r4;
+            for (int u = 0; u < U; ++u) rj[u] = load4(R, nbr_j(ent[u]));
+            __builtin_amdgcn_sched_barrier(0);  // the four positions are in flight together
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (e0 + u >= nc) break;
                 double d[3];
                 const double rr = exact_r2(ri, rj[u].x, rj[u].y, rj[u].z, h, nbr_n(ent[u], 0), nbr_n(ent[u], 1),
                                            nbr_n(ent[u], 2), d);
-                if (!(rr < b.rc2)) continue;
-                if (cnt < b.cap) {
-                    nbr[size_t(cnt) * N + i] = ent[u];
+                if (!(rr < rc2)) {
+                    store4(Pout, size_t(e0 + u) * N + i, zero);
+                    continue;
+                }
+                if (cnt < cap) {
                     vec4_t<T> v;
                     v.x = T(d[0]);
                     v.y = T(d[1]);
@@ -330,24 +379,31 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
                     v.w = T(sqrt(rr));
 #pragma unroll
                     for (int s2 = 0; s2 < MB; ++s2)
-                        if (s2 == cnt) bond[s2] = v;
-                    if (cnt >= MB) dv[size_t(cnt) * N + i] = v;
+                        if (s2 == cnt) {
+                            bond[s2] = v;
+                            cid[s2] = e0 + u;
+                        }
+                    if (cnt >= MB) {
+                        dv[size_t(cnt) * N + i] = v;
+                        bcid[size_t(cnt) * N + i] = uint16_t(e0 + u);
+                    }
                 }
                 ++cnt;
             }
         }
-        b.ncnt[size_t(slot) * N + i] = cnt;
-        if (cnt > b.cap) set_error(st, CFNEB_ENEIGH);
-        const int nb = min(cnt, b.cap);
+        if (cnt > cap) set_error(st, CFNEB_ENEIGH);
+        const int nb = min(cnt, cap);
         const TersoffT<T> P(b);
-        vec4_t<T>* Pout = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.cap * N;
         if (nb <= MB) {
-            ts_atom_regs<T, MB>(P, bond, Pout, N, i, nb, acc);
+            ts_atom_regs<T, MB>(P, bond, cid, Pout, N, i, nb, acc);
         } else {
 #pragma unroll
-            for (int s2 = 0; s2 < MB; ++s2) dv[size_t(s2) * N + i] = bond[s2];
+            for (int s2 = 0; s2 < MB; ++s2) {
+                dv[size_t(s2) * N + i] = bond[s2];
+                bcid[size_t(s2) * N + i] = uint16_t(cid[s2]);
+            }
             vec2_t<T>* bo = reinterpret_cast<vec2_t<T>*>(b.bo) + size_t(slot) * b.cap * N;
-            ts_atom_generic<T>(P, dv, bo, Pout, N, i, nb, acc);
+            ts_atom_generic<T>(P, dv, bo, bcid, Praw, N, i, nb, acc);
         }
     }
     block_sum<10>(acc, lds);
@@ -370,46 +426,53 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_filter_bonds(BatchDev bd, int
     }
 }
 
-// F_i = sum_e (P_e - P_rev(e)), rev(e) = the entry (i, -n) in j's list.
+// F_i = sum_c (P_c - P_rev(c)) over i's candidates, rev(c) = the slot of (i, -n) in
+// j's candidates; both P vanish unless the pair is a bond.  Four candidates at a
+// time: their slots, reverse slots and own P, then the reverse P, are in flight
+// together.
 template <typename T>
 __device__ void ts_gather_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const size_t N = b.N;
-    const uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
-    const int* ncnt = b.ncnt + size_t(slot) * N;
-    const vec4_t<T>* Pb = reinterpret_cast<const vec4_t<T>*>(b.P) + size_t(slot) * b.cap * N;
-    const int cnt = min(ncnt[i], b.cap);
+    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
+    const gmem<const uint16_t>* __restrict__ crev = gp<const uint16_t>(b.crev + size_t(slot) * b.ccap * N);
+    const gmem<const vec4_t<T>>* __restrict__ Pb =
+        gp<const vec4_t<T>>(reinterpret_cast<const vec4_t<T>*>(b.P) + size_t(slot) * b.ccap * N);
+    const int nc = gp<const int>(b.ncand)[size_t(slot) * N + i];
     T fx = 0, fy = 0, fz = 0;
-    bool missing = false;
-    for (int e = 0; e < cnt; ++e) {
-        const uint32_t ent = nbr[size_t(e) * N + i];
-        const int j = nbr_j(ent);
-        const vec4_t<T> pe = Pb[size_t(e) * N + i];
-        fx += pe.x;
-        fy += pe.y;
-        fz += pe.z;
-        const uint32_t want = pack_nbr(i, -nbr_n(ent, 0), -nbr_n(ent, 1), -nbr_n(ent, 2));
-        const int cj = min(ncnt[j], b.cap);
-        int found = -1;
-        for (int q = 0; q < cj; ++q)
-            if (nbr[size_t(q) * N + j] == want) {
-                found = q;
-                break;
-            }
-        if (found < 0) {
-            missing = true;
-            continue;
+    constexpr int U = 4;
+    for (int c0 = 0; c0 < nc; c0 += U) {
+        uint32_t ent[U];
+        int rv[U];
+        vec4_t<T> pe[U], pr[U];
+        // past the last candidate the loads repeat it (always in bounds, no branch
+        // between the loads) and the sum below stops
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t o = size_t(min(c0 + u, nc - 1)) * N + i;
+            ent[u] = cand[o];
+            rv[u] = int(crev[o]);
+            pe[u] = load4(Pb, o);
         }
-        const vec4_t<T> pr = Pb[size_t(found) * N + j];
-        fx -= pr.x;
-        fy -= pr.y;
-        fz -= pr.z;
+        __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of their uses
+#pragma unroll
+        for (int u = 0; u < U; ++u) pr[u] = load4(Pb, size_t(rv[u]) * N + nbr_j(ent[u]));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c0 + u >= nc) break;
+            fx += pe[u].x;
+            fy += pe[u].y;
+            fz += pe[u].z;
+            fx -= pr[u].x;
+            fy -= pr[u].y;
+            fz -= pr[u].z;
+        }
     }
-    T* F = reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b);
+    gmem<T>* F = gp(reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b));
     F[i] = fx;
     F[b.ld + i] = fy;
     F[2 * size_t(b.ld) + i] = fz;
-    if (missing) set_error(st, CFNEB_ENEIGH);
     if (!isfinite(double(fx) + double(fy) + double(fz))) set_error(st, CFNEB_ENONFINITE);
 }
 
