@@ -60,7 +60,7 @@ __global__ void k_summary(BatchDev bd, int* out)
     o[0] = st->done;
     o[1] = st->err;
     o[2] = st->steps_call;
-    o[3] = st->M;
+    o[3] = st->step;
 }
 
 void launch_plan(const Launch& L, int all_images, int ignore_stop, hipStream_t s)
@@ -89,7 +89,7 @@ void launch_evaluate(const Launch& L, int all_images, hipStream_t s)
 }
 
 // One band step of every live band.
-void launch_step(const Launch& L, hipStream_t s)
+void launch_step_core(const Launch& L, hipStream_t s)
 {
     launch_evaluate(L, 0, s);
     launch_dots(L, s);
@@ -97,6 +97,11 @@ void launch_step(const Launch& L, hipStream_t s)
     launch_update(L, s);
     launch_finalize(L, s);
     launch_move(L, s);
+}
+
+void launch_step(const Launch& L, hipStream_t s)
+{
+    launch_step_core(L, s);
     launch_refine(L, 0, s);
 }
 

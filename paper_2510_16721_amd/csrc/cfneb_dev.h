@@ -515,6 +515,10 @@ void launch_move(const Launch& L, hipStream_t s);
 void launch_refine(const Launch& L, int forced, hipStream_t s);
 void launch_readout(const Launch& L, hipStream_t s);
 void launch_evaluate(const Launch& L, int all_images, hipStream_t s);
+// One band step: launch_step_core (evaluation, projection, FIRE, move) then the
+// refinement phase; a step on which no band can be due for refinement may launch the
+// core alone (refinement then has nothing to do).
+void launch_step_core(const Launch& L, hipStream_t s);
 void launch_step(const Launch& L, hipStream_t s);
 void launch_summary(const Launch& L, int* out, hipStream_t s);
 

@@ -298,19 +298,23 @@ __device__ inline void wrap_bin(int v, int nb, int& a, int& m)
 }
 
 // Candidates of atom i: every (j, n) within rcl, in stencil order; R_ref = R.
+// A run of bin records is read four at a time (the loads of a batch are in flight
+// together); with a one-bin stencil and no wrap along the third axis, the bounds of
+// all nine runs are read before the first run.
 __device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const double4 r4 = Rs(b, slot)[i];
-    const int* start = b.bstart + bin_base(b, slot);
-    const BinAtom* bp = b.bpos + size_t(slot) * b.N;
+    const double4 r4 = load4(gp<const double4>(Rs(b, slot)), i);
+    const gmem<const int>* __restrict__ start = gp<const int>(b.bstart + bin_base(b, slot));
+    const gmem<const double4>* __restrict__ bp =
+        gp<const double4>(reinterpret_cast<const double4*>(b.bpos + size_t(slot) * b.N));
     const size_t N = b.N;
-    uint32_t* cand = b.cand + size_t(slot) * b.ccap * N;
+    gmem<uint32_t>* __restrict__ cand = gp(b.cand + size_t(slot) * b.ccap * N);
 
     double h[9];
     for (int q = 0; q < 9; ++q) h[q] = g.h[q];
     const double ri[3] = {r4.x, r4.y, r4.z};
-    double* Rr = b.Rref + size_t(slot) * slot_rows(b);
+    gmem<double>* __restrict__ Rr = gp(b.Rref + size_t(slot) * slot_rows(b));
     Rr[i] = ri[0];
     Rr[b.ld + i] = ri[1];
     Rr[2 * size_t(b.ld) + i] = ri[2];
@@ -319,54 +323,78 @@ __device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
     const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];
     const int b0 = me.x / (nb1 * nb2), b1 = (me.x / nb2) % nb1, b2 = me.x % nb2;
     const int r0 = g.reach[0], r1 = g.reach[1], r2 = g.reach[2];
+    const double rcl2 = b.rcl2;
+    const int ccap = b.ccap, natoms = b.N;
     int cnt = 0;
     bool bad_shift = false;
-    for (int dx = -r0; dx <= r0; ++dx) {
-        int a0, m0;
-        wrap_bin(b0 + dx, nb0, a0, m0);
-        for (int dy = -r1; dy <= r1; ++dy) {
-            int a1, m1;
-            wrap_bin(b1 + dy, nb1, a1, m1);
-            const int row = (a0 * nb1 + a1) * nb2;
-            // The z bins b2-r2 .. b2+r2 of a row are one contiguous run of records
-            // unless the stencil wraps; then each bin is its own segment.
-            const bool flat = (b2 - r2 >= 0) && (b2 + r2 < nb2);
-            const int nseg = flat ? 1 : 2 * r2 + 1;
-            for (int sgi = 0; sgi < nseg; ++sgi) {
-                int lo, hi, m2 = 0;
-                if (flat) {
-                    lo = start[row + b2 - r2];
-                    hi = start[row + b2 + r2 + 1];
-                } else {
-                    int a2;
-                    wrap_bin(b2 - r2 + sgi, nb2, a2, m2);
-                    lo = start[row + a2];
-                    hi = start[row + a2 + 1];
+    // records lo..hi-1 of the bin-ordered array, seen from bin shift (m0, m1, m2)
+    auto scan = [&](int lo, int hi, int m0, int m1, int m2) {
+        hi = min(hi, natoms);
+        constexpr int U = 4;
+        for (int p0 = lo; p0 < hi; p0 += U) {
+            double4 a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = load4(bp, min(p0 + u, hi - 1));
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (p0 + u >= hi) break;
+                const long long info = __double_as_longlong(a[u].w);
+                const int j = info_j(info);
+                const int n0 = m0 + im0 - info_n(info, 0);
+                const int n1 = m1 + im1 - info_n(info, 1);
+                const int n2 = m2 + im2 - info_n(info, 2);
+                if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
+                double d[3];
+                const double rr = exact_r2(ri, a[u].x, a[u].y, a[u].z, h, n0, n1, n2, d);
+                if (!(rr < rcl2)) continue;
+                if (abs(n0) > CFNEB_MAX_SHIFT || abs(n1) > CFNEB_MAX_SHIFT || abs(n2) > CFNEB_MAX_SHIFT) {
+                    bad_shift = true;
+                    continue;
                 }
-                hi = min(hi, b.N);
-                for (int p = lo; p < hi; ++p) {
-                    const BinAtom a = bp[p];
-                    const int j = info_j(a.info);
-                    const int n0 = m0 + im0 - info_n(a.info, 0);
-                    const int n1 = m1 + im1 - info_n(a.info, 1);
-                    const int n2 = m2 + im2 - info_n(a.info, 2);
-                    if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-                    double d[3];
-                    const double rr = exact_r2(ri, a.x, a.y, a.z, h, n0, n1, n2, d);
-                    if (!(rr < b.rcl2)) continue;
-                    if (abs(n0) > CFNEB_MAX_SHIFT || abs(n1) > CFNEB_MAX_SHIFT || abs(n2) > CFNEB_MAX_SHIFT) {
-                        bad_shift = true;
-                        continue;
+                if (cnt < ccap) cand[size_t(cnt) * N + i] = pack_nbr(j, n0, n1, n2);
+                ++cnt;
+            }
+        }
+    };
+    // The z bins b2-r2 .. b2+r2 of a row are one contiguous run of records unless the
+    // stencil wraps; then each bin is its own segment.
+    const bool flat = (b2 - r2 >= 0) && (b2 + r2 < nb2);
+    if (flat && r0 == 1 && r1 == 1) {
+        int lo[9], hi[9], m0s[9], m1s[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            int a0, a1;
+            wrap_bin(b0 + q / 3 - 1, nb0, a0, m0s[q]);
+            wrap_bin(b1 + q % 3 - 1, nb1, a1, m1s[q]);
+            const int row = (a0 * nb1 + a1) * nb2;
+            lo[q] = start[row + b2 - r2];
+            hi[q] = start[row + b2 + r2 + 1];
+        }
+        for (int q = 0; q < 9; ++q) scan(lo[q], hi[q], m0s[q], m1s[q], 0);
+    } else {
+        for (int dx = -r0; dx <= r0; ++dx) {
+            int a0, m0;
+            wrap_bin(b0 + dx, nb0, a0, m0);
+            for (int dy = -r1; dy <= r1; ++dy) {
+                int a1, m1;
+                wrap_bin(b1 + dy, nb1, a1, m1);
+                const int row = (a0 * nb1 + a1) * nb2;
+                const int nseg = flat ? 1 : 2 * r2 + 1;
+                for (int sgi = 0; sgi < nseg; ++sgi) {
+                    if (flat) {
+                        scan(start[row + b2 - r2], start[row + b2 + r2 + 1], m0, m1, 0);
+                    } else {
+                        int a2, m2;
+                        wrap_bin(b2 - r2 + sgi, nb2, a2, m2);
+                        scan(start[row + a2], start[row + a2 + 1], m0, m1, m2);
                     }
-                    if (cnt < b.ccap) cand[size_t(cnt) * N + i] = pack_nbr(j, n0, n1, n2);
-                    ++cnt;
                 }
             }
         }
     }
-    b.ncand[size_t(slot) * N + i] = min(cnt, b.ccap);
+    b.ncand[size_t(slot) * N + i] = min(cnt, ccap);
     if (bad_shift) set_error(st, CFNEB_ECELL);
-    if (cnt > b.ccap) set_error(st, CFNEB_ENEIGH);
+    if (cnt > ccap) set_error(st, CFNEB_ENEIGH);
 }
 
 __global__ void __launch_bounds__(CFNEB_TILE) k_cand(BatchDev bd, int all_images)

@@ -136,8 +136,10 @@ struct cfneb_band {
     Launch launch;  // the band as a table of one
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;  // a whole step
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_core = nullptr;  // a step without the refinement phase
+    hipGraphExec_t exec_core = nullptr;
     BandState* host_state = nullptr;  // pinned
     bool use_graph = true;
     std::string last_error;
@@ -339,20 +341,54 @@ void aos_to_soa(const double* aos, int ld, int rows, double* soa)
         for (int c = 0; c < 3; ++c) soa[size_t(c) * ld + r] = aos[3 * size_t(r) + c];
 }
 
-int launch_step_direct(cfneb_band* b)
+// Refinement runs on the steps that finish with step % refine_every == 0 (the band's
+// step counter advances by one on every step that moves it, and a band that does not
+// move refines nothing), so the host knows which launches can need it.
+bool refine_due(const cfneb_params& p, long long step_after)
 {
-    launch_step(b->launch, b->stream);
+    return p.refine_every > 0 && step_after % p.refine_every == 0;
+}
+
+int launch_step_direct(cfneb_band* b, bool with_refine)
+{
+    if (with_refine)
+        launch_step(b->launch, b->stream);
+    else
+        launch_step_core(b->launch, b->stream);
     return check_kernels(b, "step");
 }
 
-int ensure_graph(cfneb_band* b)
+int capture_band_graphs(cfneb_band* b)
 {
-    if (b->exec || !b->use_graph) return CFNEB_OK;
     HIP_TRY(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed));
     launch_step(b->launch, b->capture_stream);
     HIP_TRY(b, hipStreamEndCapture(b->capture_stream, &b->graph));
     HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    HIP_TRY(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed));
+    launch_step_core(b->launch, b->capture_stream);
+    HIP_TRY(b, hipStreamEndCapture(b->capture_stream, &b->graph_core));
+    HIP_TRY(b, hipGraphInstantiate(&b->exec_core, b->graph_core, nullptr, nullptr, 0));
     return CFNEB_OK;
+}
+
+void drop_band_graphs(cfneb_band* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec_core) (void)hipGraphExecDestroy(b->exec_core);
+    if (b->graph_core) (void)hipGraphDestroy(b->graph_core);
+    b->exec = b->exec_core = nullptr;
+    b->graph = b->graph_core = nullptr;
+}
+
+// Both step graphs, or neither (a failed capture leaves none behind).
+int ensure_graph(cfneb_band* b)
+{
+    if ((b->exec && b->exec_core) || !b->use_graph) return CFNEB_OK;
+    drop_band_graphs(b);
+    const int rc = capture_band_graphs(b);
+    if (rc != CFNEB_OK) drop_band_graphs(b);
+    return rc;
 }
 
 }  // namespace
@@ -530,19 +566,23 @@ int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, doub
     if (!b || max_steps < 0) return CFNEB_EINVAL;
     launch_begin_call(b->launch, f_tol, -1, b->stream);
     int rc = ensure_graph(b);
+    if (rc == CFNEB_OK) rc = read_state(b);
     if (rc != CFNEB_OK) return rc;
+    long long next = b->host_state->step + 1;  // step count after the next launch moves the band
     const int check_every = 16;
-    for (int s = 0; s < max_steps; ++s) {
+    for (int s = 0; s < max_steps; ++s, ++next) {
+        const bool with_refine = refine_due(b->p, next);
         if (b->exec) {
-            HIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+            HIP_TRY(b, hipGraphLaunch(with_refine ? b->exec : b->exec_core, b->stream));
         } else {
-            rc = launch_step_direct(b);
+            rc = launch_step_direct(b, with_refine);
             if (rc != CFNEB_OK) return rc;
         }
         if ((s + 1) % check_every == 0 && s + 1 < max_steps) {
             rc = read_state(b);
             if (rc != CFNEB_OK) return rc;
             if (b->host_state->done || b->host_state->err) break;
+            next = b->host_state->step;  // the loop's ++next makes it the next launch's
         }
     }
     rc = read_state(b);
@@ -572,8 +612,11 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
         }
     const Launch& d = b->launch;
     hipStream_t s = b->stream;
+    if (rc == CFNEB_OK) rc = read_state(b);
+    const long long step0 = rc == CFNEB_OK ? b->host_state->step : 0;
     for (int st = 0; st < max_steps && rc == CFNEB_OK; ++st) {
         hipEvent_t* e = ev.data() + size_t(st) * (NP + 1);
+        const bool with_refine = refine_due(b->p, step0 + st + 1);
         for (int ph = 0; ph < NP; ++ph) {
             (void)hipEventRecord(e[ph], s);
             switch (ph) {
@@ -594,7 +637,9 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
             case CFNEB_PH_UPDATE: launch_update(d, s); break;
             case CFNEB_PH_FINALIZE: launch_finalize(d, s); break;
             case CFNEB_PH_MOVE: launch_move(d, s); break;
-            case CFNEB_PH_REFINE: launch_refine(d, 0, s); break;
+            case CFNEB_PH_REFINE:
+                if (with_refine) launch_refine(d, 0, s);
+                break;
             default: break;
             }
         }
@@ -859,8 +904,7 @@ int cfneb_destroy(cfneb_band* b)
 {
     if (!b) return CFNEB_EINVAL;
     if (b->stream || b->host_state) (void)hipStreamSynchronize(b->stream);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    drop_band_graphs(b);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     if (b->host_state) (void)hipHostFree(b->host_state);
     delete b;
@@ -882,11 +926,13 @@ struct cfneb_batch {
     int* live = nullptr;
     int* plan = nullptr;
     int* summary = nullptr;
-    int* host_summary = nullptr;  // pinned, 4 ints per table entry
+    int* host_summary = nullptr;  // pinned, per table entry: done, err, steps this call, step
     std::vector<cfneb_band*> bands;
     unsigned graph_variants = 0;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;  // a whole step
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_core = nullptr;  // a step without the refinement phase
+    hipGraphExec_t exec_core = nullptr;
     bool use_graph = true;
 };
 
@@ -917,8 +963,39 @@ void drop_graph(cfneb_batch* B)
 {
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
-    B->exec = nullptr;
-    B->graph = nullptr;
+    if (B->exec_core) (void)hipGraphExecDestroy(B->exec_core);
+    if (B->graph_core) (void)hipGraphDestroy(B->graph_core);
+    B->exec = B->exec_core = nullptr;
+    B->graph = B->graph_core = nullptr;
+}
+
+int capture_batch_graphs(cfneb_batch* B)
+{
+    if (hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return CFNEB_EHIP;
+    launch_step(B->launch, B->capture_stream);
+    if (hipStreamEndCapture(B->capture_stream, &B->graph) != hipSuccess ||
+        hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess)
+        return CFNEB_EHIP;
+    if (hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return CFNEB_EHIP;
+    launch_step_core(B->launch, B->capture_stream);
+    if (hipStreamEndCapture(B->capture_stream, &B->graph_core) != hipSuccess ||
+        hipGraphInstantiate(&B->exec_core, B->graph_core, nullptr, nullptr, 0) != hipSuccess)
+        return CFNEB_EHIP;
+    return CFNEB_OK;
+}
+
+// Whether the step after `ahead` more launches can refine any band of the table:
+// summary field 3 of a band is its step count at the last summary.
+bool batch_refine_due(const cfneb_batch* B, int ahead)
+{
+    for (int q = 0; q < B->cap; ++q) {
+        const cfneb_band* bb = B->bands[q];
+        if (!bb) continue;
+        const int* o = B->host_summary + 4 * q;
+        if (o[0] || o[1]) continue;  // stopped: nothing to refine
+        if (refine_due(bb->p, (long long)o[3] + ahead + 1)) return true;
+    }
+    return false;
 }
 
 int read_summary(cfneb_batch* B)
@@ -1024,27 +1101,34 @@ int cfneb_batch_step(cfneb_batch* B, int max_steps, double f_tol, int* steps_don
 {
     if (!B || max_steps < 0) return CFNEB_EINVAL;
     launch_begin_call(B->launch, f_tol, -1, B->stream);
-    if (B->use_graph && (!B->exec || B->graph_variants != B->launch.variants)) {
+    if (B->use_graph && (!B->exec || !B->exec_core || B->graph_variants != B->launch.variants)) {
         drop_graph(B);
-        if (hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return CFNEB_EHIP;
-        launch_step(B->launch, B->capture_stream);
-        if (hipStreamEndCapture(B->capture_stream, &B->graph) != hipSuccess ||
-            hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess)
-            return CFNEB_EHIP;
+        const int crc = capture_batch_graphs(B);
+        if (crc != CFNEB_OK) {
+            drop_graph(B);
+            return crc;
+        }
         B->graph_variants = B->launch.variants;
     }
     const int check_every = 16;
-    int rc = CFNEB_OK;
-    for (int s = 0; s < max_steps; ++s) {
+    int rc = read_summary(B);
+    if (rc != CFNEB_OK) return rc;
+    int ahead = 0;  // launches since the last summary
+    for (int s = 0; s < max_steps; ++s, ++ahead) {
+        const bool with_refine = batch_refine_due(B, ahead);
         if (B->exec) {
-            if (hipGraphLaunch(B->exec, B->stream) != hipSuccess) return CFNEB_EHIP;
+            if (hipGraphLaunch(with_refine ? B->exec : B->exec_core, B->stream) != hipSuccess) return CFNEB_EHIP;
         } else {
-            launch_step(B->launch, B->stream);
+            if (with_refine)
+                launch_step(B->launch, B->stream);
+            else
+                launch_step_core(B->launch, B->stream);
             if (hipGetLastError() != hipSuccess) return CFNEB_EHIP;
         }
         if ((s + 1) % check_every == 0 && s + 1 < max_steps) {
             rc = read_summary(B);
             if (rc != CFNEB_OK) return rc;
+            ahead = -1;  // the loop's ++ahead makes it 0 for the next launch
             bool active = false;
             for (int q = 0; q < B->cap; ++q)
                 if (B->bands[q] && !B->host_summary[4 * q] && !B->host_summary[4 * q + 1]) active = true;
