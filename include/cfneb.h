@@ -110,8 +110,8 @@ enum {
     CFNEB_PH_FORCE0,        /* LJ pair forces, or Tersoff zeta and bond orders */
     CFNEB_PH_FORCE1,        /* Tersoff dU_i/dr^ij per bond (unused for LJ) */
     CFNEB_PH_FORCE2,        /* Tersoff force gather (unused for LJ) */
-    CFNEB_PH_REDUCE,        /* per-image E, V, enthalpy, lattice force */
-    CFNEB_PH_DOTS,          /* ten band dot products per image */
+    CFNEB_PH_REDUCE,        /* (empty in a step: the dots phase reduces E and V) */
+    CFNEB_PH_DOTS,          /* per-image E, V, enthalpy, lattice force; band dots */
     CFNEB_PH_SCALARS,       /* tangents, climbing image, projection, FIRE proposal */
     CFNEB_PH_UPDATE,        /* NEB force rows, new velocities, row maxima */
     CFNEB_PH_FINALIZE,      /* fmax, convergence, step clamp, FIRE commit */

@@ -86,7 +86,8 @@ __device__ inline void atom_gen_force(const DP D, const T (&fr)[3], double (&f)[
 
 // An item is 1024 rows, four per thread (rows tile*1024 + q*256 + thread, so every
 // load is coalesced).  A tile of atom rows only issues all loads of its four rows
-// before any arithmetic; the image's last tile (cell rows, ragged end) goes row by row.
+// before any arithmetic; the image's last tile (cell rows, ragged end) first reduces
+// the image's energy and virial, then goes row by row.
 template <typename T>
 __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
 {
@@ -124,6 +125,10 @@ __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile
             dots_row(a, x0[q], xm[q], xp[q], v[q], f, true);
         }
     } else {
+        // the image's last tile holds its cell rows, whose force needs the image's
+        // energy and virial: this block reduces them first
+        image_reduce_item(b, const_cast<BandState*>(st), s0, lds);
+        __syncthreads();
         for (int q = 0; q < Q; ++q) {
             const int r = r0 + q * CFNEB_TILE;
             if (r >= b.N + 3) break;

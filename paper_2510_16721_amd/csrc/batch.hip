@@ -1,7 +1,8 @@
 // Work plan of a band table and the order of the kernels of one step.
 //
 // A table holds up to CFNEB_MAX_BANDS bands (a single band is a table of one).  The
-// plan kernel runs first in every step: each thread counts one band's items of every
+// plan is written first in every step (by block 0 of the geometry kernel, or by the
+// plan kernel for calls outside a step): each thread counts one band's items of every
 // kind (per-atom tiles, per-row tiles, per-image, ...) from its live image count and
 // flags, and the exclusive prefix offsets go to the plan array that every persistent
 // kernel of the step walks.  A converged or failed band contributes no items, so a
@@ -12,38 +13,7 @@ namespace cfneb {
 
 __global__ void __launch_bounds__(CFNEB_MAX_BANDS) k_plan(BatchDev bd, int all_images, int ignore_stop)
 {
-    __shared__ int cnt[NKIND][CFNEB_MAX_BANDS];
-    const int t = threadIdx.x;
-    if (t == 0) {
-        *rebuild_flag(bd) = 0;
-        *refine_flag(bd) = 0;
-    }
-    if (t < bd.cap) {
-        int c[NKIND];
-        for (int q = 0; q < NKIND; ++q) c[q] = 0;
-        if (bd.live[t]) {
-            const BandDev& b = bd.bands[t];
-            const BandState* st = b.st;
-            if (ignore_stop || !band_stopped(st)) {
-                const int M = st->M;
-                for (int q = 0; q < NKIND; ++q) {
-                    int first;
-                    kind_span(b, q, M, all_images, c[q], first);
-                }
-            }
-        }
-        for (int q = 0; q < NKIND; ++q) cnt[q][t] = c[q];
-    }
-    __syncthreads();
-    if (t < NKIND) {
-        int* off = bd.plan + t * (bd.cap + 1);
-        int run = 0;
-        for (int bi = 0; bi < bd.cap; ++bi) {
-            off[bi] = run;
-            run += cnt[t][bi];
-        }
-        off[bd.cap] = run;
-    }
+    plan_block(bd, all_images, ignore_stop);
 }
 
 // Per-band status for the host: done, err, steps of the call, M (4 ints per band).
@@ -74,18 +44,18 @@ void launch_summary(const Launch& L, int* out, hipStream_t s)
 }
 
 // Energies, forces, virials and generalized forces of the moving images (or of every
-// image): geometry, cell lists, neighbour lists, potential, per-image reduction.
+// image): geometry, cell lists, neighbour lists, potential, per-image reduction.  In
+// a step (moving images only) the per-image reduction runs inside the band dots pass.
 void launch_evaluate(const Launch& L, int all_images, hipStream_t s)
 {
-    launch_plan(L, all_images, 0, s);
-    launch_geom(L, all_images, s);
+    launch_geom(L, all_images, s);  // also writes the plan
     launch_skin(L, all_images, s);
     launch_bins(L, all_images, s);
     launch_list(L, all_images, s);
     launch_filter(L, all_images, s);
     launch_force_stage(L, all_images, 0, s);
     launch_force_stage(L, all_images, 1, s);
-    launch_image_reduce(L, all_images, s);
+    if (all_images) launch_image_reduce(L, all_images, s);
 }
 
 // One band step of every live band.

@@ -374,6 +374,45 @@ struct ItemLoop {
     }
 };
 
+// The work plan of a table, written by one block of CFNEB_MAX_BANDS threads: each
+// thread counts one band's items of every kind, then the exclusive prefix offsets go
+// to the plan; the step's device flags are cleared.
+__device__ inline void plan_block(const BatchDev& bd, int all_images, int ignore_stop)
+{
+    __shared__ int cnt[NKIND][CFNEB_MAX_BANDS];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        *rebuild_flag(bd) = 0;
+        *refine_flag(bd) = 0;
+    }
+    if (t < bd.cap) {
+        int c[NKIND];
+        for (int q = 0; q < NKIND; ++q) c[q] = 0;
+        if (bd.live[t]) {
+            const BandDev& b = bd.bands[t];
+            const BandState* st = b.st;
+            if (ignore_stop || !band_stopped(st)) {
+                const int M = st->M;
+                for (int q = 0; q < NKIND; ++q) {
+                    int first;
+                    kind_span(b, q, M, all_images, c[q], first);
+                }
+            }
+        }
+        for (int q = 0; q < NKIND; ++q) cnt[q][t] = c[q];
+    }
+    __syncthreads();
+    if (t < NKIND) {
+        int* off = bd.plan + t * (bd.cap + 1);
+        int run = 0;
+        for (int bi = 0; bi < bd.cap; ++bi) {
+            off[bi] = run;
+            run += cnt[t][bi];
+        }
+        off[bd.cap] = run;
+    }
+}
+
 // Grid sizes of the persistent launches (multiples of 8).
 #define CFNEB_GRID_TILES 2048
 #define CFNEB_GRID_IMAGES 512
@@ -491,6 +530,49 @@ __host__ __device__ inline void mm3(const double* a, const double* b, double* c)
 // ---------------------------------------------------------------- launchers
 // Defined in the kernel translation units, called by the host runtime.
 // One band, direct launches (construction and readout helpers):
+// Per-image reduction of the energy and virial tile partials in a fixed order, then
+// the enthalpy and the lattice force G = D^-T (V - P Omega I) D^-1 / c_f
+// (Eqs. (16)-(17)); thread 0 writes the image's scalars.
+__device__ inline void image_reduce_item(const BandDev& b, BandState* st, int slot, double* lds)
+{
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double* part = b.evpart + size_t(slot) * b.ntA * 10;
+    for (int t = threadIdx.x; t < b.ntA; t += CFNEB_TILE)
+        for (int q = 0; q < 10; ++q) acc[q] += part[size_t(t) * 10 + q];
+    block_sum<10>(acc, lds);
+    if (threadIdx.x != 0) return;
+    const ImageGeom& g = b.geom[slot];
+    ImageScal& s = b.scal[slot];
+    s.E = acc[0];
+    s.H = acc[0] + b.press * g.omega;
+    bool finite = isfinite(s.H);
+    double Veff[9];
+    for (int q = 0; q < 9; ++q) {
+        s.V[q] = acc[1 + q];
+        Veff[q] = acc[1 + q];
+        finite = finite && isfinite(Veff[q]);
+    }
+    for (int q = 0; q < 3; ++q) Veff[4 * q] -= b.press * g.omega;
+    double DinvT[9], T1[9], G[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) DinvT[3 * r + c] = g.Dinv[3 * c + r];
+    mm3(DinvT, Veff, T1);
+    if (b.cell_filter == 1) {
+        // D-variant (Eq. (13)): the conjugate of D is D^-T V_eff, all nine entries
+        for (int q = 0; q < 9; ++q) s.Fcell[q] = T1[q] / b.cf;
+    } else {
+        mm3(T1, g.Dinv, G);
+        const double sc = (b.cell_filter == 2) ? b.bscale / b.cf : 0.0;
+        // the force conjugate to the symmetric B is the symmetric part of G (the FP32
+        // virial is symmetric only to rounding; an antisymmetric rest would move the
+        // cell rows along a direction the energy does not see)
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) s.Fcell[3 * r + c] = sc * (0.5 * (G[3 * r + c] + G[3 * c + r]));
+    }
+    if (!finite) set_error(st, CFNEB_ENONFINITE);
+}
+
+
 void launch_init_endpoints(const BandDev& b, hipStream_t s);
 void launch_init_images(const BandDev& b, int M, hipStream_t s);
 void launch_init_state(const BandDev& b, int M, hipStream_t s);

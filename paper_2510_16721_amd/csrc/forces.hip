@@ -96,47 +96,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj(BatchDev bd, int all_images, 
 }
 
 // ------------------------------------------------------------ per-image reduction
-// E and V in a fixed order; enthalpy and the rotation-free lattice force
-// G = D^-T (V - P Omega I) D^-1 / c_f (Eqs. (16)-(17)).
-__device__ void image_reduce_item(const BandDev& b, BandState* st, int slot, double* lds)
-{
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const double* part = b.evpart + size_t(slot) * b.ntA * 10;
-    for (int t = threadIdx.x; t < b.ntA; t += CFNEB_TILE)
-        for (int q = 0; q < 10; ++q) acc[q] += part[size_t(t) * 10 + q];
-    block_sum<10>(acc, lds);
-    if (threadIdx.x != 0) return;
-    const ImageGeom& g = b.geom[slot];
-    ImageScal& s = b.scal[slot];
-    s.E = acc[0];
-    s.H = acc[0] + b.press * g.omega;
-    bool finite = isfinite(s.H);
-    double Veff[9];
-    for (int q = 0; q < 9; ++q) {
-        s.V[q] = acc[1 + q];
-        Veff[q] = acc[1 + q];
-        finite = finite && isfinite(Veff[q]);
-    }
-    for (int q = 0; q < 3; ++q) Veff[4 * q] -= b.press * g.omega;
-    double DinvT[9], T1[9], G[9];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) DinvT[3 * r + c] = g.Dinv[3 * c + r];
-    mm3(DinvT, Veff, T1);
-    if (b.cell_filter == 1) {
-        // D-variant (Eq. (13)): the conjugate of D is D^-T V_eff, all nine entries
-        for (int q = 0; q < 9; ++q) s.Fcell[q] = T1[q] / b.cf;
-    } else {
-        mm3(T1, g.Dinv, G);
-        const double sc = (b.cell_filter == 2) ? b.bscale / b.cf : 0.0;
-        // the force conjugate to the symmetric B is the symmetric part of G (the FP32
-        // virial is symmetric only to rounding; an antisymmetric rest would move the
-        // cell rows along a direction the energy does not see)
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) s.Fcell[3 * r + c] = sc * (0.5 * (G[3 * r + c] + G[3 * c + r]));
-    }
-    if (!finite) set_error(st, CFNEB_ENONFINITE);
-}
-
+// (image_reduce_item: the step reduces its moving images inside the band dots pass)
 __global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BatchDev bd, int all_images)
 {
     __shared__ double lds[4 * 10];

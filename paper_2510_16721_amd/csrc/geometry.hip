@@ -111,35 +111,43 @@ __device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
     return true;
 }
 
-// One block per band, one thread per image.
-__global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_geom(BatchDev bd, int all_images)
+// Geometry of image k of band b and its strain since the candidate build.
+__device__ void geom_image(const BandDev& b, BandState* st, int k)
 {
-    ItemLoop loop(bd, KIND_BAND, all_images);
-    Item it;
-    while (loop.next(it)) {
-        const BandDev& b = bd.bands[it.band];
+    const int slot = st->slot[k];
+    ImageGeom g;
+    g.err = 0;
+    if (!image_geometry(b, Xs(b, slot), g)) {
+        g.err = 1;
+        set_error(st, CFNEB_ECELL);
+    }
+    // strain since the candidate build: E = h_ref^-1 h - I
+    const SkinState& sk = b.skst[slot];
+    g.enorm = 0.0;
+    if (sk.valid) {
+        mm3(sk.hrefinv, g.h, g.E);
+        for (int q = 0; q < 3; ++q) g.E[4 * q] -= 1.0;
+        for (int q = 0; q < 9; ++q) g.enorm += g.E[q] * g.E[q];
+        g.enorm = sqrt(g.enorm);
+    } else {
+        for (int q = 0; q < 9; ++q) g.E[q] = 0.0;
+    }
+    b.geom[slot] = g;
+}
+
+// One block per band, one thread per image; the bands are taken from the table
+// directly, so block 0 can write the step's work plan (every later kernel of the
+// step walks it) in the same launch.
+__global__ void __launch_bounds__(CFNEB_MAX_BANDS) k_geom(BatchDev bd, int all_images)
+{
+    if (blockIdx.x == 0) plan_block(bd, all_images, 0);
+    for (int t = blockIdx.x; t < bd.cap; t += int(gridDim.x)) {
+        if (!bd.live[t]) continue;
+        const BandDev& b = bd.bands[t];
         BandState* st = b.st;
         const int k = threadIdx.x;
         if (band_stopped(st) || k >= b.Mcap || !image_active(st, k, all_images)) continue;
-        const int slot = st->slot[k];
-        ImageGeom g;
-        g.err = 0;
-        if (!image_geometry(b, Xs(b, slot), g)) {
-            g.err = 1;
-            set_error(st, CFNEB_ECELL);
-        }
-        // strain since the candidate build: E = h_ref^-1 h - I
-        const SkinState& sk = b.skst[slot];
-        g.enorm = 0.0;
-        if (sk.valid) {
-            mm3(sk.hrefinv, g.h, g.E);
-            for (int q = 0; q < 3; ++q) g.E[4 * q] -= 1.0;
-            for (int q = 0; q < 9; ++q) g.enorm += g.E[q] * g.E[q];
-            g.enorm = sqrt(g.enorm);
-        } else {
-            for (int q = 0; q < 9; ++q) g.E[q] = 0.0;
-        }
-        b.geom[slot] = g;
+        geom_image(b, st, k);
     }
 }
 
@@ -271,9 +279,10 @@ void launch_init_images(const BandDev& b, int M, hipStream_t s)
 
 void launch_init_state(const BandDev& b, int M, hipStream_t s) { k_init_state<<<1, 1, 0, s>>>(b, M); }
 
+// Geometry of the active images and the step's work plan (no separate plan launch).
 void launch_geom(const Launch& L, int all_images, hipStream_t s)
 {
-    k_geom<<<L.g[KIND_BAND], CFNEB_MAX_IMAGES, 0, s>>>(L.bd, all_images);
+    k_geom<<<L.g[KIND_BAND], CFNEB_MAX_BANDS, 0, s>>>(L.bd, all_images);
 }
 
 void launch_image_positions(const BandDev& b, int k, hipStream_t s)

@@ -82,8 +82,8 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->geom = take(M * sizeof(ImageGeom));
     L->scal = take(M * sizeof(ImageScal));
     L->evpart = take(M * L->ntA * 10 * 8);
-    L->dotpart = take(M * L->ntR4 * CFNEB_NDOT * 8);
     L->dotred = take(M * CFNEB_NDOT * 8);
+    L->dotpart = take(M * L->ntR4 * CFNEB_NDOT * 8);
     L->maxpart = take(M * L->ntR4 * 3 * 8);
     L->refpart = take(M * L->ntR * 2 * 8);
     L->staging = take((6 * N + 64) * 8);
@@ -621,8 +621,7 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
             (void)hipEventRecord(e[ph], s);
             switch (ph) {
             case CFNEB_PH_GEOM:
-                launch_plan(d, 0, 0, s);
-                launch_geom(d, 0, s);
+                launch_geom(d, 0, s);  // also writes the plan
                 break;
             case CFNEB_PH_SKIN: launch_skin(d, 0, s); break;
             case CFNEB_PH_BINS: launch_bins(d, 0, s); break;
@@ -631,7 +630,7 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
             case CFNEB_PH_FORCE0: launch_force_stage(d, 0, 0, s); break;
             case CFNEB_PH_FORCE1: launch_force_stage(d, 0, 1, s); break;
             case CFNEB_PH_FORCE2: launch_force_stage(d, 0, 2, s); break;
-            case CFNEB_PH_REDUCE: launch_image_reduce(d, 0, s); break;
+            case CFNEB_PH_REDUCE: break;  // inside the band dots pass
             case CFNEB_PH_DOTS: launch_dots(d, s); break;
             case CFNEB_PH_SCALARS: launch_scalars(d, s); break;
             case CFNEB_PH_UPDATE: launch_update(d, s); break;
