@@ -350,7 +350,9 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
         }
         vec4_t<T> zero{};
         int cnt = 0;
-        constexpr int U = 4;
+        // two candidates at a time: carbon atoms have three or four, and a wider
+        // batch runs the whole exact test and bond insertion for slots most lanes lack
+        constexpr int U = 2;
         for (int e0 = 0; e0 < nc; e0 += U) {
             uint32_t ent[U];
             double4 rj[U];
@@ -360,7 +362,7 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
             for (int u = 0; u < U; ++u) ent[u] = cand[size_t(min(e0 + u, nc - 1)) * N + i];
 #pragma unroll
             for (int u = 0; u < U; ++u) rj[u] = load4(R, nbr_j(ent[u]));
-            __builtin_amdgcn_sched_barrier(0);  // the four positions are in flight together
+            __builtin_amdgcn_sched_barrier(0);  // the batch's positions are in flight together
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (e0 + u >= nc) break;
