@@ -62,7 +62,6 @@ struct ImageGeom {
 // 2 max_i |R_i - R_i,ref (I + E)| + (rc + skin) |E| < skin.
 struct SkinState {
     double href[9], hrefinv[9];
-    unsigned long long dmax2;  // bits of max_i |R_i - R_i,ref (I + E)|^2 (>= 0 doubles order as integers)
     int valid;                 // a candidate list exists for this slot
     int rebuild;               // this step rebuilds it
 };
@@ -156,6 +155,7 @@ struct BandDev {
     double* dotpart;    // [k][CFNEB_NDOT][ntR4]
     double* dotred;     // [k][CFNEB_NDOT] reduced band dots
     double* maxpart;    // [k][3][ntR4]
+    double* skmax;      // [slot][1024-atom tile] max |R_i - R_i,ref (I + E)|^2 of the tile
     uint64_t* refpart;  // [k][ntR][2]
     double* staging;    // endpoint upload and readout area
     BandState* st;
@@ -362,9 +362,10 @@ struct ItemLoop {
         it.band = lo;
         if (kind == KIND_ROW4) {
             // tile-major: the same rows of consecutive images are neighbouring items,
-            // so the neighbour images' X read by the band passes come from L2
+            // so the neighbour images' X read by the band passes come from L2; last
+            // tile first, since the tile with the cell rows is the slowest item
             const int nimg = count / nt;
-            it.tile = local / nimg;
+            it.tile = nt - 1 - local / nimg;
             it.image = first + local % nimg;
         } else {
             it.tile = local % nt;

@@ -43,7 +43,8 @@ __device__ inline int info_n(long long v, int k) { return int((v >> (20 + 10 * k
 
 // 1024 atoms per item, four per thread: all loads of the four atoms are issued before
 // any position is stored.  R = R~ D; d_i^2 against the strained reference when a list
-// exists (block maximum, then an integer atomic max per image).
+// exists; the tile's maximum goes to its own slot (no atomics: many tiles per image
+// would contend on one address).
 __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_images)
 {
     __shared__ double lds[CFNEB_TILE / 64];
@@ -96,30 +97,32 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
             }
         }
         block_max<1>(m, lds);
-        if (threadIdx.x == 0 && m[0] > 0.0)
-            atomicMax(&b.skst[slot].dmax2, (unsigned long long)__double_as_longlong(m[0]));
+        if (threadIdx.x == 0) b.skmax[size_t(slot) * kind_tiles(b, KIND_ATOM4) + it.tile] = m[0];
     }
 }
 
-// One block per band, one thread per image.
-__global__ void __launch_bounds__(CFNEB_MAX_IMAGES) k_skin_decide(BatchDev bd, int all_images)
+// One block per band, sixteen threads per image: the maximum over the image's tile
+// maxima (max is exact in any order), then the decision.
+__global__ void __launch_bounds__(16 * CFNEB_MAX_IMAGES) k_skin_decide(BatchDev bd, int all_images)
 {
     ItemLoop loop(bd, KIND_BAND, all_images);
     Item it;
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         BandState* st = b.st;
-        const int k = threadIdx.x;
-        if (band_stopped(st) || k >= b.Mcap || !image_active(st, k, all_images)) continue;
-        const int slot = st->slot[k];
+        const int k = threadIdx.x >> 4, lane = threadIdx.x & 15;
+        const bool act = !band_stopped(st) && k < b.Mcap && image_active(st, k, all_images);
+        const int slot = act ? st->slot[k] : 0;
+        const int nt = kind_tiles(b, KIND_ATOM4);
+        double m = 0.0;
+        if (act)
+            for (int t = lane; t < nt; t += 16) m = fmax(m, b.skmax[size_t(slot) * nt + t]);
+        for (int off = 8; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 16));
+        if (!act || lane != 0) continue;
         SkinState& sk = b.skst[slot];
         const ImageGeom& g = b.geom[slot];
         bool rebuild = true;
-        if (b.skin > 0.0 && sk.valid) {
-            const double dmax = sqrt(__longlong_as_double((long long)sk.dmax2));
-            rebuild = !(2.0 * dmax + b.rcl * g.enorm < b.skin * (1.0 - 1e-6));
-        }
-        sk.dmax2 = 0ull;
+        if (b.skin > 0.0 && sk.valid) rebuild = !(2.0 * sqrt(m) + b.rcl * g.enorm < b.skin * (1.0 - 1e-6));
         sk.rebuild = rebuild ? 1 : 0;
         if (rebuild) {
             for (int q = 0; q < 9; ++q) {
@@ -484,7 +487,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_imag
 void launch_skin(const Launch& L, int all_images, hipStream_t s)
 {
     k_skin_check<<<L.g[KIND_ATOM4], CFNEB_TILE, 0, s>>>(L.bd, all_images);
-    k_skin_decide<<<L.g[KIND_BAND], CFNEB_MAX_IMAGES, 0, s>>>(L.bd, all_images);
+    k_skin_decide<<<L.g[KIND_BAND], 16 * CFNEB_MAX_IMAGES, 0, s>>>(L.bd, all_images);
 }
 
 void launch_bins(const Launch& L, int all_images, hipStream_t s)

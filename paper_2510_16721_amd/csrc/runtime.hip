@@ -24,7 +24,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     int N, ld, Mcap, ntA, ntR, ntR4, nbcap, cap, ccap, fp64, tersoff;
     size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, bcid, P, crev, geom,
-        scal, dotred,
+        scal, dotred, skmax,
         evpart, dotpart, maxpart, refpart, staging, state, table, live, plan, total;
 };
 
@@ -85,6 +85,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->dotred = take(M * CFNEB_NDOT * 8);
     L->dotpart = take(M * L->ntR4 * CFNEB_NDOT * 8);
     L->maxpart = take(M * L->ntR4 * 3 * 8);
+    L->skmax = take(M * size_t((L->N + CFNEB_TILE4 - 1) / CFNEB_TILE4) * 8);
     L->refpart = take(M * L->ntR * 2 * 8);
     L->staging = take((6 * N + 64) * 8);
     L->state = take(sizeof(BandState));
@@ -289,6 +290,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.dotpart = reinterpret_cast<double*>(base + L.dotpart);
     d.dotred = reinterpret_cast<double*>(base + L.dotred);
     d.maxpart = reinterpret_cast<double*>(base + L.maxpart);
+    d.skmax = reinterpret_cast<double*>(base + L.skmax);
     d.refpart = reinterpret_cast<uint64_t*>(base + L.refpart);
     d.staging = reinterpret_cast<double*>(base + L.staging);
     d.st = reinterpret_cast<BandState*>(base + L.state);
