@@ -9,7 +9,7 @@ namespace cfneb {
 
 // Symmetric positive square root by cyclic Jacobi rotations on the symmetric part.
 // Returns false if an eigenvalue is not positive.
-__device__ bool sym_sqrt(const double* Bin, double* D)
+__device__ __forceinline__ bool sym_sqrt(const double* Bin, double* D)
 {
     double a[3][3], q[3][3];
     for (int i = 0; i < 3; ++i)
@@ -21,6 +21,7 @@ __device__ bool sym_sqrt(const double* Bin, double* D)
         const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
         const double on = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
         if (off <= 1e-36 * on) break;
+#pragma unroll
         for (int pr = 0; pr < 3; ++pr) {
             const int p = (pr == 2) ? 1 : 0;
             const int r = (pr == 0) ? 1 : 2;
@@ -30,16 +31,19 @@ __device__ bool sym_sqrt(const double* Bin, double* D)
             const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
             const double c = rsqrt(t * t + 1.0);
             const double s = t * c;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = a[k][p], y = a[k][r];
                 a[k][p] = c * x - s * y;
                 a[k][r] = s * x + c * y;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = a[p][k], y = a[r][k];
                 a[p][k] = c * x - s * y;
                 a[r][k] = s * x + c * y;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = q[k][p], y = q[k][r];
                 q[k][p] = c * x - s * y;
@@ -58,7 +62,7 @@ __device__ bool sym_sqrt(const double* Bin, double* D)
     return true;
 }
 
-__device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
+__device__ __forceinline__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
 {
     double B[9];
     const double icf = 1.0 / b.cf;
@@ -77,6 +81,7 @@ __device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
     inv3(g.h, g.hinv);
     g.omega = fabs(det3(g.h));
     if (!(g.omega > 0.0) || !isfinite(g.omega)) return false;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double* u = g.h + 3 * ((k + 1) % 3);
         const double* v = g.h + 3 * ((k + 2) % 3);
@@ -89,6 +94,7 @@ __device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
     // rcl = rc + skin the candidate cutoff, so a +-1 bin stencil holds every pair closer
     // than rcl.  Cells narrower than that get one bin and a stencil wide enough for all
     // the periodic images needed.
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double q = g.w[k] / (b.rcl * (1.0 + 1e-9));
         if (q >= 1.0) {
@@ -99,20 +105,30 @@ __device__ bool image_geometry(const BandDev& b, const double* X, ImageGeom& g)
             g.reach[k] = int(ceil(b.rcl / g.w[k])) + 1;
         }
     }
-    while (g.nb[0] * g.nb[1] * g.nb[2] > b.nbcap) {
-        int k = 0;
-        if (g.nb[1] > g.nb[k]) k = 1;
-        if (g.nb[2] > g.nb[k]) k = 2;
-        g.nb[k] -= 1;  // wider bins keep the +-1 stencil valid
+    // (scalar counts: an array indexed at run time would keep the whole geometry
+    // record in scratch memory)
+    int n0 = g.nb[0], n1 = g.nb[1], n2 = g.nb[2];
+    while (n0 * n1 * n2 > b.nbcap) {
+        // the first of the largest counts loses a bin; wider bins keep the +-1
+        // stencil valid
+        if (n1 > n0 && n1 >= n2)
+            --n1;
+        else if (n2 > n0 && n2 > n1)
+            --n2;
+        else
+            --n0;
     }
-    g.nbins = g.nb[0] * g.nb[1] * g.nb[2];
+    g.nb[0] = n0;
+    g.nb[1] = n1;
+    g.nb[2] = n2;
+    g.nbins = n0 * n1 * n2;
     for (int k = 0; k < 3; ++k)
         if (g.reach[k] > 8) return false;  // shifts beyond the 4-bit packing
     return true;
 }
 
 // Geometry of image k of band b and its strain since the candidate build.
-__device__ void geom_image(const BandDev& b, BandState* st, int k)
+__device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int k)
 {
     const int slot = st->slot[k];
     ImageGeom g;
