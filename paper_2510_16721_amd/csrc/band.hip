@@ -165,25 +165,24 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BatchDev bd, unsigned 
     }
 }
 
-// One block per moving image: the image's tile partials, in a fixed order.
-__global__ void __launch_bounds__(CFNEB_TILE) k_band_dots_reduce(BatchDev bd)
+// One block per moving image, one wave per dot (waves take dots w and w + 16): each
+// lane sums every 64th tile partial, then the wave sums its lanes, in a fixed order.
+__global__ void __launch_bounds__(1024) k_band_dots_reduce(BatchDev bd)
 {
-    __shared__ double lds[(CFNEB_TILE / 64) * CFNEB_NDOT];
     ItemLoop loop(bd, KIND_IMAGE, 0);
     Item it;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         if (band_stopped(b.st)) continue;  // uniform over the block
         const int k = it.image;
-        double a[CFNEB_NDOT];
-#pragma unroll
-        for (int q = 0; q < CFNEB_NDOT; ++q) a[q] = 0.0;
-        const double* part = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4;
-        for (int t = threadIdx.x; t < b.ntR4; t += CFNEB_TILE)
-            for (int q = 0; q < CFNEB_NDOT; ++q) a[q] += part[size_t(q) * b.ntR4 + t];
-        block_sum<CFNEB_NDOT>(a, lds);
-        if (threadIdx.x == 0)
-            for (int q = 0; q < CFNEB_NDOT; ++q) b.dotred[size_t(k) * CFNEB_NDOT + q] = a[q];
+        const gmem<const double>* part = gp<const double>(b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4);
+        for (int q = w; q < CFNEB_NDOT; q += 16) {
+            double a = 0.0;
+            for (int t = lane; t < b.ntR4; t += 64) a += part[size_t(q) * b.ntR4 + t];
+            a = wave_sum(a);
+            if (lane == 0) b.dotred[size_t(k) * CFNEB_NDOT + q] = a;
+        }
     }
 }
 
@@ -563,7 +562,7 @@ void launch_dots(const Launch& L, hipStream_t s)
     const unsigned g = L.g[KIND_ROW4];
     if (f32_mask(L.variants)) k_band_dots<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, f32_mask(L.variants));
     if (f64_mask(L.variants)) k_band_dots<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, f64_mask(L.variants));
-    k_band_dots_reduce<<<L.g[KIND_IMAGE], CFNEB_TILE, 0, s>>>(L.bd);
+    k_band_dots_reduce<<<L.g[KIND_IMAGE], 1024, 0, s>>>(L.bd);
 }
 
 void launch_scalars(const Launch& L, hipStream_t s) { k_band_scalars<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd); }

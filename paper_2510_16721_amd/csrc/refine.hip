@@ -178,15 +178,20 @@ __device__ void decide_item(const BandDev& b, BandState* st, int mode)
     __shared__ U128 d2[CFNEB_MAX_IMAGES];
     const int M = st->M;
     const int t = threadIdx.x;
-    if (t < M - 1) {
+    // one wave per interval: integer sums are exact, so the order is free
+    const int lane = t & 63, nw = int(blockDim.x) >> 6;
+    for (int k = t >> 6; k < M - 1; k += nw) {
         U128 s = {0, 0};
-        const uint64_t* p = b.refpart + size_t(t) * b.ntR * 2;
-        for (int q = 0; q < b.ntR; ++q) {
+        const uint64_t* p = b.refpart + size_t(k) * b.ntR * 2;
+        for (int q = lane; q < b.ntR; q += 64) {
             const U128 v = {p[2 * q], p[2 * q + 1]};
             add128(s, v);
         }
-        d2[t] = s;
-        st->d2[t] = double(s.hi) + double(s.lo) * 5.421010862427522e-20;  // 2^-64
+        s = wave_sum128(s);
+        if (lane == 0) {
+            d2[k] = s;
+            st->d2[k] = double(s.hi) + double(s.lo) * 5.421010862427522e-20;  // 2^-64
+        }
     }
     __syncthreads();
     if (t == 0 && mode != 2) {
@@ -257,7 +262,7 @@ __device__ void decide_item(const BandDev& b, BandState* st, int mode)
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(64) k_refine_decide(BatchDev bd, int mode)
+__global__ void __launch_bounds__(1024) k_refine_decide(BatchDev bd, int mode)
 {
     if (mode == 0 && *refine_flag(bd) == 0) return;  // no band is due this step
     ItemLoop loop(bd, KIND_BAND, 0);
@@ -337,7 +342,7 @@ void launch_refine(const Launch& L, int forced, hipStream_t s)
 {
     const int mode = forced ? 1 : 0;
     k_refine_dist<<<L.g[KIND_IVAL], CFNEB_TILE, 0, s>>>(L.bd, mode);
-    k_refine_decide<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd, mode);
+    k_refine_decide<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd, mode);
     k_refine_apply<<<L.g[KIND_SLOTROW], CFNEB_TILE, 0, s>>>(L.bd, mode);
 }
 
@@ -345,7 +350,7 @@ void launch_refine(const Launch& L, int forced, hipStream_t s)
 void launch_readout(const Launch& L, hipStream_t s)
 {
     k_refine_dist<<<L.g[KIND_IVAL], CFNEB_TILE, 0, s>>>(L.bd, 1);
-    k_refine_decide<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd, 2);
+    k_refine_decide<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd, 2);
     k_readout<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd);
 }
 
