@@ -144,7 +144,7 @@ __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile
             dots_row(a, x0, xm, xp, v, f, r < b.N);
         }
     }
-    block_sum<CFNEB_NDOT>(a, lds);
+    block_sum_t<CFNEB_NDOT>(a, lds);
     if (threadIdx.x == 0) {
         // [image][dot][tile]: the reduction reads consecutive tiles
         double* out = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4 + tile;

@@ -482,6 +482,53 @@ __device__ inline void block_sum(double (&v)[NV], double* lds)
     __syncthreads();
 }
 
+// Block sum of NV doubles by a transposed wave reduction: at each halving step a lane
+// keeps half of its values and trades the other half with its partner, so a wave
+// makes P - 1 + 6 - log2 P exchanges instead of 6 NV (P = NV rounded up to a power of
+// two, at most 64), at the price of selects.  Fixed order; the result is valid in
+// thread 0.  lds must hold (blockDim.x / 64) * NV doubles.
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+template <int NV>
+__device__ inline void block_sum_t(double (&v)[NV], double* lds)
+{
+    constexpr int P = pow2_at_least(NV);
+    static_assert(P <= 64, "at most 64 values");
+    constexpr int LOGP = P <= 1 ? 0 : P <= 2 ? 1 : P <= 4 ? 2 : P <= 8 ? 3 : P <= 16 ? 4 : P <= 32 ? 5 : 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
+    double u[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[i] = i < NV ? v[i] : 0.0;
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int m = 32 >> st;
+        const int n = (P >> st) > 1 ? (P >> st) : 1;  // values a lane still holds
+        if (n > 1) {
+            const int half = n / 2;
+            const bool up = (lane & m) != 0;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const double send = up ? u[i] : u[half + i];
+                const double keep = up ? u[half + i] : u[i];
+                u[i] = keep + __shfl_xor(send, m, 64);
+            }
+        } else {
+            u[0] += __shfl_xor(u[0], m, 64);
+        }
+    }
+    // the lane's sum is value (lane >> (6 - LOGP)) of the wave
+    const int idx = (lane >> (6 - LOGP)) & (P - 1);
+    if ((lane & ((64 >> LOGP) - 1)) == 0 && idx < NV) lds[wid * NV + idx] = u[0];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = lds[q];
+            for (int w = 1; w < nw; ++w) s += lds[w * NV + q];
+            v[q] = s;
+        }
+    __syncthreads();
+}
+
 template <int NV>
 __device__ inline void block_max(double (&v)[NV], double* lds)
 {

@@ -74,7 +74,7 @@ __device__ void lj_item(const BandDev& b, BandState* st, int slot, int tile, dou
         F[2 * size_t(b.ld) + i] = fz;
         if (!isfinite(double(fx) + double(fy) + double(fz))) set_error(st, CFNEB_ENONFINITE);
     }
-    block_sum<10>(acc, lds);
+    block_sum_t<10>(acc, lds);
     if (threadIdx.x == 0) {
         double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
         for (int q = 0; q < 10; ++q) out[q] = acc[q];
