@@ -344,7 +344,9 @@ def main():
     counts = np.concatenate([band.neighbours(k)[0] for k in range(1, m_now - 1)]).astype(np.float64)
     mean_bonds = float(counts.mean())
     flops_per_atom = float(ts_bonds_flops_per_atom(counts).mean())
-    bytes_per_atom = float((20.0 * counts + 40.0).mean())
+    # own position 32 B and candidate count 4 B; per bond the candidate entry 4 B and
+    # P_ij 16 B (the neighbours' positions are gathered from L2)
+    bytes_per_atom = float((20.0 * counts + 36.0).mean())
     per_launch = {k: v / max(pdone, 1) for k, v in phase_ms.items()}
     total_ms = sum(per_launch.values())
     dom = max(per_launch, key=per_launch.get)
