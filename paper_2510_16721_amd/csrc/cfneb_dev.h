@@ -114,7 +114,7 @@ struct BandDev {
     double rc, rc2;
     double skin, rcl, rcl2;  // candidate skin, list cutoff rc + skin and its square
     double lj_eps, lj_sig2, lj_eshift;
-    double ts_A, ts_B, ts_l1, ts_l2, ts_beta, ts_bn, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
+    double ts_A, ts_B, ts_l1, ts_l2, ts_beta, ts_bn, ts_lnbeta, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
     double k_spring;
     int climb_after, cell_filter;
     int relax;  // no tangent projection or springs: F_NEB = generalized force

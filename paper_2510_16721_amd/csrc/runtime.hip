@@ -233,6 +233,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.ts_l2 = p->ts_lambda2;
     d.ts_beta = p->ts_beta;
     d.ts_bn = std::pow(p->ts_beta, p->ts_n);
+    d.ts_lnbeta = std::log(p->ts_beta);
     d.ts_n = p->ts_n;
     d.ts_c2 = p->ts_c * p->ts_c;
     d.ts_d2 = p->ts_d * p->ts_d;

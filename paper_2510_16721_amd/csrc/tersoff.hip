@@ -28,29 +28,73 @@ namespace cfneb {
 __device__ inline float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ inline double qdiv(double a, double b) { return a / b; }
 
-// Bond order b = (1 + x)^(-1/2n), x = beta^n zeta^n.  Both powers keep the accurately
-// rounded pow: the energy of a perfect crystal adds every bond's rounding of b
-// coherently, and a cheaper exp2(n log2(beta zeta)) form misses 1e-6 eV/atom there.
-__device__ inline void bond_order_pow(float z, float beta, float n, float bn, float& x)
+// FP64 natural logarithm and exponential for the FP32 bond order.  FP64 vector
+// operations run at the FP32 rate on this GPU, so two short polynomial evaluations
+// cost a fraction of two accurately rounded FP32 powers, and their results are far
+// more accurate than FP32 before the final rounding.
+// ln: u = m 2^e with m in [1/sqrt 2, sqrt 2); ln m = 2 atanh(s), s = (m - 1)/(m + 1),
+// |s| <= 0.1716, by its series through s^13 (absolute error below 5e-13).
+__device__ inline double ln64(double u)
 {
-    (void)beta;
-    x = bn * powf(z, n);
+    int e;
+    double m = frexp(u, &e);
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 13.0;
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    p = fma(p, s2, 1.0);
+    return fma(double(e), 0.69314718055994531, 2.0 * s * p);
 }
-__device__ inline float bond_order_b(float base, float n) { return powf(base, -0.5f / n); }
-__device__ inline void bond_order_pow(double z, double beta, double n, double bn, double& x)
+// exp: y = k ln 2 + r with ln 2 in two parts (k ln2_hi exact), |r| <= ln 2 / 2; exp r
+// by its Taylor series through r^10 / 10! (relative error below 3e-13), then 2^k.
+__device__ inline double exp64(double y)
 {
-    (void)beta;
-    x = bn * pow(z, n);
+    const double k = rint(y * 1.4426950408889634);
+    double r = fma(-k, 6.93147180369123816490e-01, y);
+    r = fma(-k, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 3628800.0;
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, int(k));
 }
-__device__ inline double bond_order_b(double base, double n) { return pow(base, -0.5 / n); }
+
+// The potential's parameters are the same for every lane: marking them uniform lets
+// the compiler keep them in scalar registers instead of vector ones.
+__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline double uni(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(bits & 0xffffffffll)));
+    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(bits >> 32)));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 template <typename T>
 struct TersoffT {
-    T A, B, l1, l2, beta, bn, n, c2, d2, c2d2, h, R, S, pi_w;
+    T A, B, l1, l2, c2, d2, c2d2, h, R, S, pi_w;
+    double n, bn, lnbeta, inv2n, A64, B64, l1_64, l2_64;
     __device__ explicit TersoffT(const BandDev& b)
-        : A(T(b.ts_A)), B(T(b.ts_B)), l1(T(b.ts_l1)), l2(T(b.ts_l2)), beta(T(b.ts_beta)), bn(T(b.ts_bn)),
-          n(T(b.ts_n)), c2(T(b.ts_c2)), d2(T(b.ts_d2)), c2d2(T(b.ts_c2d2)), h(T(b.ts_h)), R(T(b.ts_R)),
-          S(T(b.ts_S)), pi_w(T(3.14159265358979323846 / (b.ts_S - b.ts_R)))
+        : A(uni(T(b.ts_A))), B(uni(T(b.ts_B))), l1(uni(T(b.ts_l1))), l2(uni(T(b.ts_l2))),
+          c2(uni(T(b.ts_c2))), d2(uni(T(b.ts_d2))), c2d2(uni(T(b.ts_c2d2))), h(uni(T(b.ts_h))),
+          R(uni(T(b.ts_R))), S(uni(T(b.ts_S))), pi_w(uni(T(3.14159265358979323846 / (b.ts_S - b.ts_R)))),
+          n(uni(b.ts_n)), bn(uni(b.ts_bn)), lnbeta(uni(b.ts_lnbeta)), inv2n(uni(0.5 / b.ts_n)),
+          A64(uni(b.ts_A)), B64(uni(b.ts_B)), l1_64(uni(b.ts_l1)), l2_64(uni(b.ts_l2))
     {
     }
     __device__ T fc(T r) const
@@ -73,18 +117,61 @@ struct TersoffT {
         g = T(1) + c2d2 * x * iden;
         dg = T(-2) * c2 * t * (iden * iden);
     }
-    // bond order and its zeta derivative
-    __device__ void bond_order(T z, T& b, T& db) const
+    // bond order b = (1 + x)^(-1/2n), x = (beta zeta)^n, and its zeta derivative; b64
+    // is b before rounding to T
+    __device__ void bond_order(T z, T& b, T& db, double& b64) const
     {
         b = T(1);
         db = T(0);
+        b64 = 1.0;
         if (z > T(0)) {
-            T x;
-            bond_order_pow(z, beta, n, bn, x);
-            const T base = T(1) + x;
-            b = bond_order_b(base, n);
-            db = T(-0.5) * qdiv(x, z) * qdiv(b, base);
+            if constexpr (sizeof(T) == 4) {
+                const double x = exp64(n * (ln64(double(z)) + lnbeta));
+                const double u = 1.0 + x;
+                b64 = exp64(-inv2n * ln64(u));
+                b = T(b64);
+                db = T(-0.5) * qdiv(T(x), z) * qdiv(b, T(u));
+            } else {
+                const T x = T(bn) * pow(z, T(n));
+                const T base = T(1) + x;
+                b = pow(base, T(-0.5) / T(n));
+                db = T(-0.5) * qdiv(x, z) * qdiv(b, base);
+                b64 = double(b);
+            }
         }
+    }
+    // Pair terms A exp(-l1 r) and B exp(-l2 r) and the bond energy.  On the FP32 path
+    // the energy is summed in FP64 from FP64 terms of the FP32 bond length: in a
+    // perfect crystal every bond rounds alike, so FP32 terms would add their roundings
+    // coherently (about 2e-6 eV/atom on diamond).  Both terms take the same FP32 r, so
+    // its rounding cancels in fr - b fa near the bond's minimum.  The repulsive term is
+    // formed once in FP64 (the force takes it rounded) and its energy half added at
+    // once; the attractive one is formed in FP32 for the force and again in FP64 for the
+    // energy once the bond order is known.  On the FP64 path the whole bond energy is
+    // added with the attractive half.
+    __device__ T repulsive(T r) const
+    {
+        if constexpr (sizeof(T) == 4)
+            return T(A64 * exp64(-l1_64 * double(r)));
+        else
+            return A * exp(-l1 * r);
+    }
+    __device__ T repulsive(T r, T fcr, double& e) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            const double f = A64 * exp64(-l1_64 * double(r));
+            e += 0.5 * double(fcr) * f;
+            return T(f);
+        } else {
+            return repulsive(r);
+        }
+    }
+    __device__ void attractive_energy(T r, T fcr, T fa, T bb, double b64, T fr, double& e) const
+    {
+        if constexpr (sizeof(T) == 4)
+            e -= 0.5 * double(fcr) * (b64 * (B64 * exp64(-l2_64 * double(r))));
+        else
+            e += double(T(0.5) * fcr * (fr - bb * fa));
     }
 };
 
@@ -128,7 +215,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
             ir[e] = qdiv(T(1), d.w);
             fc[e] = P.fc(d.w);
             dfc[e] = P.dfc(d.w);
-            fr[e] = P.A * exp(-P.l1 * d.w);
+            fr[e] = P.repulsive(d.w, fc[e], acc[0]);
             fa[e] = P.B * exp(-P.l2 * d.w);
         } else {
             dx[e] = dy[e] = dz[e] = T(0);
@@ -168,8 +255,9 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
         dV[e] = pre[e] = T(0);
         if (e < cnt) {
             T bb, db;
-            P.bond_order(z[e], bb, db);
-            acc[0] += double(T(0.5) * fc[e] * (fr[e] - bb * fa[e]));
+            double b64;
+            P.bond_order(z[e], bb, db, b64);
+            P.attractive_energy(bond[e].w, fc[e], fa[e], bb, b64, fr[e], acc[0]);
             dV[e] = dfc[e] * (fr[e] - bb * fa[e]) + fc[e] * (-P.l1 * fr[e] + bb * P.l2 * fa[e]);
             pre[e] = fc[e] * fa[e] * db;
         }
@@ -241,10 +329,12 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
             z += P.fc(dq.w) * g;
         }
         vec2_t<T> o;
-        P.bond_order(z, o.x, o.y);
+        double b64;
+        P.bond_order(z, o.x, o.y, b64);
         bo[size_t(e) * N + i] = o;
-        const T fr = P.A * exp(-P.l1 * de.w), fa = P.B * exp(-P.l2 * de.w);
-        acc[0] += double(T(0.5) * P.fc(de.w) * (fr - o.x * fa));
+        const T fce = P.fc(de.w);
+        const T fr = P.repulsive(de.w, fce, acc[0]), fa = P.B * exp(-P.l2 * de.w);
+        P.attractive_energy(de.w, fce, fa, o.x, b64, fr, acc[0]);
     }
     for (int e = 0; e < cnt; ++e) {
         const vec4_t<T> de = dv[size_t(e) * N + i];
@@ -252,7 +342,7 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
         const T re = de.w, ire = T(1) / re;
         const T hx = de.x * ire, hy = de.y * ire, hz = de.z * ire;
         const T fce = P.fc(re), dfce = P.dfc(re);
-        const T fre = P.A * exp(-P.l1 * re), fae = P.B * exp(-P.l2 * re);
+        const T fre = P.repulsive(re), fae = P.B * exp(-P.l2 * re);
         const T dV = dfce * (fre - be.x * fae) + fce * (-P.l1 * fre + be.x * P.l2 * fae);
         T px = T(0.5) * dV * hx, py = T(0.5) * dV * hy, pz = T(0.5) * dV * hz;
         const T pre_e = fce * fae * be.y;
@@ -416,7 +506,7 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_ts_filter_bonds(BatchDev bd, int all_images, int variant)
+__device__ void ts_filter_bonds_loop(const BatchDev& bd, int all_images, int variant)
 {
     __shared__ double lds[4 * 10];
     ItemLoop loop(bd, KIND_ATOM, all_images);
@@ -426,6 +516,21 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_filter_bonds(BatchDev bd, int
         if (band_variant(b) != variant || band_stopped(b.st)) continue;  // uniform over the block
         ts_filter_bonds_item<T>(b, b.st, b.st->slot[it.image], it.tile, lds);
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_ts_filter_bonds(BatchDev bd, int all_images, int variant)
+{
+    ts_filter_bonds_loop<T>(bd, all_images, variant);
+}
+
+// FP32 bonds: four waves per SIMD (at most 128 VGPRs, a few bytes of spill); left
+// alone the FP64 energy terms take 135 VGPRs and the kernel runs 15% slower at three.
+template <>
+__global__ void __launch_bounds__(CFNEB_TILE) __attribute__((amdgpu_waves_per_eu(4)))
+k_ts_filter_bonds<float>(BatchDev bd, int all_images, int variant)
+{
+    ts_filter_bonds_loop<float>(bd, all_images, variant);
 }
 
 // F_i = sum_c (P_c - P_rev(c)) over i's candidates, rev(c) = the slot of (i, -n) in

@@ -65,10 +65,10 @@ def test_energy_force_virial_per_image(name, fp64):
                               pressure_GPa=press)
     p = oracle_params_like(kind, pressure_GPa=press)
     scale = 1e-6 if fp64 else 1.0
-    # random dense carbon (+1.8 eV/atom, bonds down to 1.1 A) cancels repulsive and
-    # attractive bond terms near 30 eV each; one FP32 rounding of such a term is
-    # about 2e-6 eV, so this far-from-equilibrium case gets ten times the energy bound
-    e_scale = 10.0 if (name == "ts_dense" and not fp64) else 1.0
+    # the FP32 Tersoff path sums its bond energies in FP64 from FP64 pair terms and
+    # bond orders, so even random dense carbon (+1.8 eV/atom, repulsive and attractive
+    # terms near 30 eV each) meets the uniform energy bound
+    e_scale = 1.0
     n = g.n
     for k in range(5):
         img = g.image(k)
