@@ -146,3 +146,44 @@ def test_batch_workload_subset_matches_oracle():
         assert g["ci"] in (r["ci"], M - 1 - r["ci"])
         assert abs(g["barrier"] - r["barrier"]) <= TOL_BARRIER, (g["barrier"], r["barrier"])
     batch.close()
+
+
+# Refinement kernels launch only on the steps that can end with a refinement (the
+# host predicts them from each band's step count); one call of many steps must equal
+# single-step calls, where every call reads the step count afresh.  ins_num = 0 makes
+# every due refinement insert an image until max_images.
+REFINE_KW = [dict(n_images=5, max_images=9, refine_every=3, ins_num=0, climb_after=8),
+             dict(n_images=5, max_images=8, refine_every=4, ins_num=0, climb_after=8)]
+
+
+def test_refinement_schedule_one_call_equals_single_steps():
+    a = make_pair("ts_small", oracle_too=False, **REFINE_KW[0])[0]
+    b = make_pair("ts_small", oracle_too=False, **REFINE_KW[0])[0]
+    assert a.step(31)[0] == 31
+    for _ in range(31):
+        assert b.step(1)[0] == 1
+    assert a.get_state()["X"].shape[0] == 9  # four insertions at steps 3, 6, 9, 12
+    _same_state(a, b)
+
+
+def test_batch_refinement_schedule_one_call_equals_single_steps():
+    from paper_2510_16721_amd import cfneb
+    runs = []
+    for single in (False, True):
+        bands = [make_pair("ts_small", oracle_too=False, **kw)[0] for kw in REFINE_KW]
+        batch = cfneb.Batch(4)
+        slots = [batch.attach(b) for b in bands]
+        if single:
+            for _ in range(25):
+                steps, conv, errs = batch.step(1)
+                assert list(steps[slots]) == [1, 1] and not errs.any()
+        else:
+            steps, conv, errs = batch.step(25)
+            assert list(steps[slots]) == [25, 25] and not errs.any()
+        runs.append((bands, batch))
+    for x, y in zip(runs[0][0], runs[1][0]):
+        assert x.get_state()["X"].shape[0] == y.get_state()["X"].shape[0]
+        _same_state(x, y)
+    assert [b.get_state()["X"].shape[0] for b in runs[0][0]] == [9, 8]
+    for _, batch in runs:
+        batch.close()
