@@ -13,8 +13,9 @@
 // (r + d_i + d_j) / (1 - |E|), so 2 max d_i + rcl |E| < skin keeps the list complete.
 //
 // Kernels, in order (each a persistent walk over the items of every live band):
-//   k_skin_check   R = R~ D; max_i d_i^2 per image
-//   k_skin_decide  rebuild flag per image; a rebuild takes the current cell as reference
+//   k_skin_check   R = R~ D; max_i d_i^2 per 1024-atom tile
+//   k_skin_decide  max over an image's tiles, rebuild flag per image; a rebuild takes
+//                  the current cell as reference
 //   k_bin_assign   (rebuilds) wrapped fractional coordinate, bin id; the count atomic
 //                  returns the atom's rank inside its bin
 //   k_bin_scan     (rebuilds) exclusive prefix sum of the bin counts (one block per
@@ -23,8 +24,9 @@
 //   k_bin_sort     (rebuilds) sort each bin by atom id, so lists are deterministic
 //   k_cand         (rebuilds) stencil walk over bin-ordered records, pairs within rcl,
 //                  packed entry-major candidate lists; R_ref = R
-//   k_filter       exact test of every candidate, packed entry-major neighbour lists
-//                  (entry e of atom i at [e][i]) and, for Tersoff, the bond vectors
+//   k_filter       (LJ; Tersoff for a host readout only: its bond kernel tests the
+//                  candidates itself) exact test of every candidate, packed
+//                  entry-major neighbour lists (entry e of atom i at [e][i])
 #include <type_traits>
 
 #include "cfneb_dev.h"
@@ -416,60 +418,50 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_cand(BatchDev bd, int all_images
     }
 }
 
-// Exact test of atom i's candidates with the current R and h.
-template <typename T, bool STORE_BONDS>
+// Exact test of atom i's candidates with the current R and h: the packed neighbour
+// list.  Four candidates at a time: their entries, then their positions, are in
+// flight together before any test (past the last candidate the loads repeat it, so
+// no branch separates them; the tests stop there).
 __device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const double4* R = Rs(b, slot);
+    const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
     const size_t N = b.N;
-    const uint32_t* cand = b.cand + size_t(slot) * b.ccap * N;
-    uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
-    using T4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
-    T4* dvec = STORE_BONDS ? reinterpret_cast<T4*>(b.dvec) + size_t(slot) * b.cap * N : nullptr;
+    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
+    gmem<uint32_t>* __restrict__ nbr = gp(b.nbr + size_t(slot) * b.cap * N);
     double h[9];
     for (int q = 0; q < 9; ++q) h[q] = g.h[q];
-    const double4 r4 = R[i];
+    const double4 r4 = load4(R, i);
     const double ri[3] = {r4.x, r4.y, r4.z};
-    const int nc = b.ncand[size_t(slot) * N + i];
+    const int nc = gp<const int>(b.ncand)[size_t(slot) * N + i];
+    const double rc2 = b.rc2;
+    const int cap = b.cap;
     int cnt = 0;
-    // four candidates at a time: their entries, then their positions, are in flight
-    // together before any test
     constexpr int U = 4;
     for (int e0 = 0; e0 < nc; e0 += U) {
         uint32_t ent[U];
         double4 rj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) ent[u] = (e0 + u < nc) ? cand[size_t(e0 + u) * N + i] : 0u;
+        for (int u = 0; u < U; ++u) ent[u] = cand[size_t(min(e0 + u, nc - 1)) * N + i];
 #pragma unroll
-        for (int u = 0; u < U; ++u) rj[u] = (e0 + u < nc) ? R[nbr_j(ent[u])] : r4;
+        for (int u = 0; u < U; ++u) rj[u] = load4(R, nbr_j(ent[u]));
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (e0 + u >= nc) break;
-            const int n0 = nbr_n(ent[u], 0), n1 = nbr_n(ent[u], 1), n2 = nbr_n(ent[u], 2);
             double d[3];
-            const double rr = exact_r2(ri, rj[u].x, rj[u].y, rj[u].z, h, n0, n1, n2, d);
-            if (!(rr < b.rc2)) continue;
-            if (cnt < b.cap) {
-                nbr[size_t(cnt) * N + i] = ent[u];
-                if (STORE_BONDS) {
-                    T4 v;
-                    v.x = T(d[0]);
-                    v.y = T(d[1]);
-                    v.z = T(d[2]);
-                    v.w = T(sqrt(rr));
-                    dvec[size_t(cnt) * N + i] = v;
-                }
-            }
+            const double rr = exact_r2(ri, rj[u].x, rj[u].y, rj[u].z, h, nbr_n(ent[u], 0), nbr_n(ent[u], 1),
+                                       nbr_n(ent[u], 2), d);
+            if (!(rr < rc2)) continue;
+            if (cnt < cap) nbr[size_t(cnt) * N + i] = ent[u];
             ++cnt;
         }
     }
-    b.ncnt[size_t(slot) * N + i] = cnt;
-    if (cnt > b.cap) set_error(st, CFNEB_ENEIGH);
+    gp(b.ncnt)[size_t(slot) * N + i] = cnt;
+    if (cnt > cap) set_error(st, CFNEB_ENEIGH);
 }
 
 // vmask: the band variants (potential, force precision) this launch serves
-template <typename T, bool STORE_BONDS>
 __global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_images, unsigned vmask, int ignore_stop)
 {
     ItemLoop loop(bd, KIND_ATOM, all_images);
@@ -480,7 +472,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_imag
         BandState* st = b.st;
         const int i = it.tile * CFNEB_TILE + threadIdx.x;
         if ((!ignore_stop && band_stopped(st)) || i >= b.N) continue;
-        filter_item<T, STORE_BONDS>(b, st, st->slot[it.image], i);
+        filter_item(b, st, st->slot[it.image], i);
     }
 }
 
@@ -508,7 +500,7 @@ void launch_filter(const Launch& L, int all_images, hipStream_t s)
 {
     const unsigned g = L.g[KIND_ATOM];
     const unsigned lj = L.variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_LJ64));
-    if (lj) k_filter<double, false><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj, 0);
+    if (lj) k_filter<<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj, 0);
 }
 
 // Packed neighbour lists of every image of the table's Tersoff bands, for a host
@@ -519,7 +511,7 @@ void launch_neighbour_lists(const Launch& L, hipStream_t s)
     const unsigned ts = L.variants & ((1u << VARIANT_TS32) | (1u << VARIANT_TS64));
     if (!ts) return;
     launch_plan(L, 1, 1, s);
-    k_filter<double, false><<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, 1, ts, 1);
+    k_filter<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, 1, ts, 1);
 }
 
 }  // namespace cfneb
