@@ -26,49 +26,62 @@ __device__ void lj_item(const BandDev& b, BandState* st, int slot, int tile, dou
     const size_t N = b.N;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // u, then V row-major
     if (i < b.N) {
-        const double4* R = Rs(b, slot);
+        const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
         const ImageGeom& g = b.geom[slot];
         double h[9];
         for (int q = 0; q < 9; ++q) h[q] = g.h[q];
-        const double4 ri = R[i];
+        const double4 ri = load4(R, i);
         const double ri0 = ri.x, ri1 = ri.y, ri2 = ri.z;
-        const uint32_t* nbr = b.nbr + size_t(slot) * b.cap * N;
-        const int cnt = min(b.ncnt[size_t(slot) * N + i], b.cap);
+        const gmem<const uint32_t>* __restrict__ nbr = gp<const uint32_t>(b.nbr + size_t(slot) * b.cap * N);
+        const int cnt = min(gp<const int>(b.ncnt)[size_t(slot) * N + i], b.cap);
         const T eps4 = T(4.0 * b.lj_eps), eps24 = T(24.0 * b.lj_eps), sig2 = T(b.lj_sig2),
                 esh = T(b.lj_eshift);
         T fx = 0, fy = 0, fz = 0;
-        for (int e = 0; e < cnt; ++e) {
-            const uint32_t ent = nbr[size_t(e) * N + i];
-            const int j = nbr_j(ent);
-            const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
-            const double4 rj = R[j];
-            const double d0 = (rj.x - ri0) + ((n0 * h[0] + n1 * h[3]) + n2 * h[6]);
-            const double d1 = (rj.y - ri1) + ((n0 * h[1] + n1 * h[4]) + n2 * h[7]);
-            const double d2 = (rj.z - ri2) + ((n0 * h[2] + n1 * h[5]) + n2 * h[8]);
-            const T dx = T(d0), dy = T(d1), dz = T(d2);
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            const T ir2 = T(1) / r2;
-            T s6 = sig2 * ir2;
-            s6 = s6 * s6 * s6;
-            const T phi = eps4 * (s6 * s6 - s6) - esh;
-            const T fr = eps24 * (s6 - T(2) * s6 * s6) * ir2;  // phi'(r) / r
-            fx += fr * dx;
-            fy += fr * dy;
-            fz += fr * dz;
-            acc[0] += double(T(0.5) * phi);
-            const T hf = T(-0.5) * fr;
-            const T wx = hf * dx, wy = hf * dy, wz = hf * dz;
-            acc[1] += double(wx * dx);
-            acc[2] += double(wx * dy);
-            acc[3] += double(wx * dz);
-            acc[4] += double(wy * dx);
-            acc[5] += double(wy * dy);
-            acc[6] += double(wy * dz);
-            acc[7] += double(wz * dx);
-            acc[8] += double(wz * dy);
-            acc[9] += double(wz * dz);
+        // four neighbours at a time: their entries, then their positions, are in flight
+        // together (past the last neighbour the loads repeat it; the sums stop there)
+        constexpr int U = 4;
+        for (int e0 = 0; e0 < cnt; e0 += U) {
+            uint32_t ents[U];
+            double4 rjs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) ents[u] = nbr[size_t(min(e0 + u, cnt - 1)) * N + i];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rjs[u] = load4(R, nbr_j(ents[u]));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (e0 + u >= cnt) break;
+                const uint32_t ent = ents[u];
+                const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
+                const double4 rj = rjs[u];
+                const double d0 = (rj.x - ri0) + ((n0 * h[0] + n1 * h[3]) + n2 * h[6]);
+                const double d1 = (rj.y - ri1) + ((n0 * h[1] + n1 * h[4]) + n2 * h[7]);
+                const double d2 = (rj.z - ri2) + ((n0 * h[2] + n1 * h[5]) + n2 * h[8]);
+                const T dx = T(d0), dy = T(d1), dz = T(d2);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T ir2 = T(1) / r2;
+                T s6 = sig2 * ir2;
+                s6 = s6 * s6 * s6;
+                const T phi = eps4 * (s6 * s6 - s6) - esh;
+                const T fr = eps24 * (s6 - T(2) * s6 * s6) * ir2;  // phi'(r) / r
+                fx += fr * dx;
+                fy += fr * dy;
+                fz += fr * dz;
+                acc[0] += double(T(0.5) * phi);
+                const T hf = T(-0.5) * fr;
+                const T wx = hf * dx, wy = hf * dy, wz = hf * dz;
+                acc[1] += double(wx * dx);
+                acc[2] += double(wx * dy);
+                acc[3] += double(wx * dz);
+                acc[4] += double(wy * dx);
+                acc[5] += double(wy * dy);
+                acc[6] += double(wy * dz);
+                acc[7] += double(wz * dx);
+                acc[8] += double(wz * dy);
+                acc[9] += double(wz * dz);
+            }
         }
-        T* F = reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b);
+        gmem<T>* F = gp(reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b));
         F[i] = fx;
         F[b.ld + i] = fy;
         F[2 * size_t(b.ld) + i] = fz;
