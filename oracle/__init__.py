@@ -92,6 +92,10 @@ def _declare(L):
     L.orc_band_set_state.argtypes = [c_void, c_int, _dp, _dp, ctypes.POINTER(FireState)]
     L.orc_band_image.argtypes = [c_void, c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_band_destroy.argtypes = [c_void]
+    L.orc_profile.argtypes = [c_int, c_int, c_int, _dp, _dp, _dp, _dp, _dp]
+    L.orc_spline_eval.argtypes = [c_int, _dp, _dp, _dp, c_int, _dp, _dp]
+    L.orc_spline_max.argtypes = [c_int, _dp, _dp, _dp, _dp, _dp]
+    L.orc_band_profile.argtypes = [c_void, c_int, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_band_destroy.restype = None
     L.orc_tangent_coeffs.argtypes = [c_double, c_double, c_double, _dp, _dp]
     L.orc_tangent_coeffs.restype = None
@@ -263,6 +267,39 @@ def refine_decide(X, ci, max_images, min_images, ins=(9, 4), dele=(1, 4)):
     return ia.value, da.value, d2[:M - 1]
 
 
+def profile(X, H, Fg, natoms):
+    """Path coordinate s and slopes dH/ds of a band (X, Fg: M x dim; the first natoms
+    rows of 3 are atoms, taken modulo a rigid translation)."""
+    X = _f64(X)
+    M = X.shape[0]
+    X = X.reshape(M, -1)
+    Fg = _f64(Fg).reshape(M, -1)
+    s = np.zeros(M)
+    sl = np.zeros(M)
+    _check(lib().orc_profile(M, int(natoms), X.shape[1], _d(X), _d(_f64(H, M)), _d(Fg), _d(s), _d(sl)),
+           "profile")
+    return s, sl
+
+
+def spline_eval(s, H, slope, sq):
+    """Hermite interpolant through (s_k, H_k) with the given slopes, at the queries sq."""
+    s = _f64(s)
+    sq = _f64(sq)
+    out = np.zeros(sq.size)
+    _check(lib().orc_spline_eval(s.size, _d(s), _d(_f64(H)), _d(_f64(slope)), sq.size, _d(sq), _d(out)),
+           "spline_eval")
+    return out
+
+
+def spline_max(s, H, slope):
+    """(H_max, s_at) of the Hermite interpolant."""
+    s = _f64(s)
+    hm, at = np.zeros(1), np.zeros(1)
+    _check(lib().orc_spline_max(s.size, _d(s), _d(_f64(H)), _d(_f64(slope)), _d(hm), _d(at)),
+           "spline_max")
+    return hm[0], at[0]
+
+
 def neb2d(kappa, xy, k_spring=1.0, climb_after=0, dt0=0.01, dtmax=0.1, maxstep=0.05,
           max_steps=20000, f_tol=1e-10):
     xy = _f64(xy, (-1, 2)).copy()
@@ -334,6 +371,16 @@ class Band:
         _check(lib().orc_band_energies(self._h, _d(H), cap, ctypes.byref(M), _d(bar),
                                        ctypes.byref(ci), _d(xi)), "band_energies")
         return dict(H=H[:M.value].copy(), barrier=bar[0], ci=ci.value, xi=xi[:M.value].copy())
+
+    def profile(self, n_samples=0):
+        """Energy profile at the current coordinates (every image evaluated afresh)."""
+        M = self.n_images
+        s, H, sl = np.zeros(M), np.zeros(M), np.zeros(M)
+        smp = np.zeros(max(n_samples, 1))
+        bar, xm = np.zeros(1), np.zeros(1)
+        _check(lib().orc_band_profile(self._h, int(n_samples), _d(s), _d(H), _d(sl), _d(smp), _d(bar),
+                                      _d(xm)), "band_profile")
+        return dict(s=s, H=H, slope=sl, samples=smp[:n_samples].copy(), barrier=bar[0], xi_max=xm[0])
 
     def get_state(self):
         cap = self.p.max_images

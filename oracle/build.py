@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["geometry.cpp", "neighbours.cpp", "potentials.cpp", "cellfilter.cpp", "neb.cpp"]
+SOURCES = ["geometry.cpp", "neighbours.cpp", "potentials.cpp", "cellfilter.cpp", "neb.cpp", "profile.cpp"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

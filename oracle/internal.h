@@ -42,6 +42,10 @@ double cell_factor_of(const orc_params* p, int n, const double* h0);
 // stores C = D itself (det D > 0 required).  ECELL otherwise.
 int cell_gauge(const orc_params* p, const double* C, double* D);
 
+// Subtract from each of the three components of the first natoms rows of a its mean
+// over those rows (removes a rigid translation of the atoms; later rows untouched).
+void remove_translation(std::vector<double>& a, int natoms);
+
 }  // namespace orc
 
 #endif

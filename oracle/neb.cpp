@@ -595,6 +595,36 @@ extern "C" int orc_band_image(const orc_band* b, int k, double* E, double* H, do
 
 extern "C" void orc_band_destroy(orc_band* b) { delete b; }
 
+// Energy profile of the band at its current coordinates: every image is evaluated
+// afresh, then the Hermite interpolant of H over the path coordinate is sampled at
+// n_samples evenly spaced normalized coordinates and its maximum is located.
+extern "C" int orc_band_profile(orc_band* b, int n_samples, double* s, double* H, double* slope,
+                                double* samples, double* barrier, double* xi_max)
+{
+    auto& c = b->c;
+    const int M = c.M;
+    if (n_samples < 0 || n_samples == 1) return ORC_EINVAL;
+    int rc = eval_range(b, 0, M - 1);
+    if (rc != ORC_OK) return rc;
+    std::vector<double> X(size_t(M) * c.dim), Fg(size_t(M) * c.dim);
+    for (int k = 0; k < M; ++k) {
+        std::copy(c.X[k].begin(), c.X[k].end(), X.begin() + size_t(k) * c.dim);
+        std::copy(c.Fg[k].begin(), c.Fg[k].end(), Fg.begin() + size_t(k) * c.dim);
+        H[k] = c.H[k];
+    }
+    rc = orc_profile(M, b->n, c.dim, X.data(), H, Fg.data(), s, slope);
+    if (rc != ORC_OK) return rc;
+    const double S = s[M - 1];
+    std::vector<double> sq(n_samples);
+    for (int j = 0; j < n_samples; ++j) sq[j] = double(j) / double(n_samples - 1) * S;
+    if (n_samples > 0) orc_spline_eval(M, s, H, slope, n_samples, sq.data(), samples);
+    double hmax, at;
+    orc_spline_max(M, s, H, slope, &hmax, &at);
+    *barrier = hmax - H[0];
+    *xi_max = S > 0.0 ? at / S : 0.0;
+    return ORC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // analytic two-dimensional surface, through the same NEB and FIRE code
 extern "C" int orc_neb2d(double kappa, int M, double* xy, double k_spring, int climb_after,

@@ -23,6 +23,9 @@
  *     Henkelman & Jonsson 2000; Henkelman, Uberuaga & Jonsson 2000)   Sec. I / II.A
  *   - adaptive insertion / deletion of images after each iteration:   Sec. III
  *   - FIRE (Bitzek et al. 2006) as the "standard optimizer":          Sec. II.C / III
+ *   - energy profile, enthalpy against the normalized path
+ *     coordinate, as the transitions are reported (Hermite
+ *     interpolant with tangential-force slopes):                     Sec. III figures
  *
  * Parity pins: every function is pinned by a CPU test against finite
  * differences, brute force, closed forms or invariants (tests/test_oracle_*.py).
@@ -150,6 +153,27 @@ int  orc_band_set_state(orc_band* b, int n_images, const double* X, const double
 int  orc_band_image(const orc_band* b, int k, double* E, double* H, double* V,
                     double* F, double* Fg, double* Fneb, double* R, double* h);
 void orc_band_destroy(orc_band* b);
+
+/* ---------------- energy profile (readout) ------------------------------ */
+/* The transitions of Sec. III are shown as enthalpy against a normalized path
+ * coordinate.  Path coordinate s_0 = 0, s_{k+1} = s_k + |X_{k+1} - X_k| and slopes
+ * dH/ds = -Fg_k . tau_k / |tau_k| (improved tangent for moving images, one-sided
+ * difference at the ends), all modulo a rigid translation of the first natoms rows.
+ * X and Fg are M x dim row-major; s and slope receive M values. */
+int  orc_profile(int M, int natoms, int dim, const double* X, const double* H, const double* Fg,
+                 double* s, double* slope);
+/* Cubic Hermite interpolant through (s_k, H_k) with slopes slope_k, at nq queries. */
+int  orc_spline_eval(int M, const double* s, const double* H, const double* slope, int nq,
+                     const double* sq, double* out);
+/* Maximum of that interpolant over [s_0, s_{M-1}] and where it is reached. */
+int  orc_spline_max(int M, const double* s, const double* H, const double* slope, double* Hmax,
+                    double* s_at);
+/* Band profile at the current coordinates (every image evaluated afresh): s, H,
+ * slope (M values each), samples at xi_j = j / (n_samples - 1) of the normalized
+ * coordinate s / s_{M-1} (n_samples = 0 or >= 2), the interpolant's maximum minus
+ * H_0 and its normalized coordinate. */
+int  orc_band_profile(orc_band* b, int n_samples, double* s, double* H, double* slope,
+                      double* samples, double* barrier, double* xi_max);
 
 /* ---------------- pieces exposed for pinning ----------------------------- */
 /* Improved tangent coefficients: tau = a tau+ + b tau-. */
