@@ -182,6 +182,28 @@ int cfneb_refine(cfneb_band* b, int* inserted_at, int* deleted_at);
 int cfneb_energies(const cfneb_band* b, double* H, int cap, int* n_images, double* barrier,
                    int* ci_index, double* path_coord);
 
+/* Energy profile of the band at its current coordinates: the enthalpy against the
+ * path coordinate, the form in which Sec. III reports its transitions, continued
+ * between the images so that barriers can be read between them.  Every image is
+ * evaluated afresh (also the endpoints and a band that has converged).  With
+ * translation-free image differences and forces (atom-row means removed):
+ *   s_0 = 0, s_{k+1} = s_k + |X_{k+1} - X_k|   arc length in generalized coordinates
+ *   slope_k = dH/ds = -Fg_k . tau_k / |tau_k|   tau_k the improved tangent of the
+ *                                               band for 0 < k < M-1, X_1 - X_0 at
+ *                                               k = 0, X_{M-1} - X_{M-2} at M-1
+ * and on each interval the cubic Hermite interpolant through (s_k, H_k) and
+ * (s_{k+1}, H_{k+1}) with those slopes.
+ * Outputs (host arrays; any pointer may be NULL): s, H, slope (M values each,
+ * cap >= M when any is given); samples[j] = the interpolant at the normalized
+ * coordinate xi_j = j / (n_samples - 1) of s / s_{M-1}, for n_samples = 0 (none) or
+ * 2 .. CFNEB_PROFILE_MAX_SAMPLES; *barrier = its maximum minus H_0; *xi_max = the
+ * normalized coordinate of that maximum.  Overwrites the images' stored energies
+ * and forces with those of the current coordinates (what a following step computes
+ * first anyway); not during a cfneb_batch_step call of a batch holding the band. */
+#define CFNEB_PROFILE_MAX_SAMPLES 4096
+int cfneb_profile(cfneb_band* b, int n_samples, double* s, double* H, double* slope, int cap, int* n_images,
+                  double* samples, double* barrier, double* xi_max);
+
 /* Cartesian positions (n_atoms x 3) and cell (3x3) of current image k:
  * h = h0 D, R = R~ D with D = symsqrt(B). */
 int cfneb_get_image(const cfneb_band* b, int k, double* pos, double* cell);

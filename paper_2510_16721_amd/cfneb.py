@@ -22,7 +22,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECELL", -5: "ENE
 # exported entry points declared in include/cfneb.h
 SYMBOLS = ["cfneb_params_default", "cfneb_band_bytes", "cfneb_create_band", "cfneb_step",
            "cfneb_step_profiled",
-           "cfneb_refine", "cfneb_energies", "cfneb_get_image", "cfneb_relax", "cfneb_get_state",
+           "cfneb_refine", "cfneb_energies", "cfneb_profile", "cfneb_get_image", "cfneb_relax", "cfneb_get_state",
            "cfneb_set_state", "cfneb_image_data", "cfneb_record_neb_force", "cfneb_neighbours",
            "cfneb_destroy", "cfneb_strerror", "cfneb_last_error", "cfneb_batch_bytes",
            "cfneb_batch_create", "cfneb_batch_attach", "cfneb_batch_detach", "cfneb_batch_step",
@@ -95,6 +95,8 @@ def _declare(L):
     L.cfneb_refine.argtypes = [c_void, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     L.cfneb_energies.argtypes = [c_void, _dp, c_int, ctypes.POINTER(c_int), _dp,
                                  ctypes.POINTER(c_int), _dp]
+    L.cfneb_profile.argtypes = [c_void, c_int, _dp, _dp, _dp, c_int, ctypes.POINTER(c_int), _dp, _dp,
+                                _dp]
     L.cfneb_get_image.argtypes = [c_void, c_int, _dp, _dp]
     L.cfneb_relax.argtypes = [ctypes.POINTER(Params), c_int64, _ip, _dp, _dp, c_int, c_double,
                               c_void, c_size, c_void, ctypes.POINTER(c_int), _dp,
@@ -259,6 +261,22 @@ class Band:
         self._check(lib().cfneb_energies(self._h, _d(H), cap, ctypes.byref(M), ctypes.byref(bar),
                                          ctypes.byref(ci), _d(xi)), "cfneb_energies")
         return dict(H=H[:M.value].copy(), barrier=bar.value, ci=ci.value, xi=xi[:M.value].copy())
+
+    def profile(self, n_samples=0):
+        """Energy profile at the current coordinates (every image evaluated afresh):
+        arc length s, H and slope dH/ds per image, n_samples evenly spaced samples of
+        the Hermite interpolant over the normalized coordinate, its maximum minus H_0
+        and where that maximum lies."""
+        cap = 64
+        s, H, sl = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+        smp = np.zeros(max(int(n_samples), 1))
+        M = ctypes.c_int()
+        bar, xm = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().cfneb_profile(self._h, int(n_samples), _d(s), _d(H), _d(sl), cap, ctypes.byref(M),
+                                        _d(smp), ctypes.byref(bar), ctypes.byref(xm)), "cfneb_profile")
+        m = M.value
+        return dict(s=s[:m].copy(), H=H[:m].copy(), slope=sl[:m].copy(), samples=smp[:n_samples].copy(),
+                    barrier=bar.value, xi_max=xm.value)
 
     def get_image(self, k):
         pos = np.zeros((self.n, 3))

@@ -543,6 +543,210 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_move(BatchDev bd)
     }
 }
 
+// ---------------------------------------------------------------- energy profile
+// Readout of the enthalpy along the path, the form in which the transitions of
+// Sec. III are reported.  After an evaluation of every image, each image gets 14
+// sums over its rows: |t+|^2, |t-|^2, t+.t-, Fg.t+, Fg.t- and the atom-row sums of
+// t+, t- and Fg (t+ = X_{k+1} - X_k, absent at the last image; t- = X_k - X_{k-1},
+// absent at the first).  From their translation-free forms one block per band takes
+// the arc length of each interval and the slope dH/ds = -Fg.tau/|tau| (improved
+// tangent for the moving images, the one-sided difference at the ends), then
+// samples the cubic Hermite interpolant of H over the arc length and finds its
+// maximum from the nodes and the critical points inside each interval.
+template <typename T>
+__device__ void profile_dots_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
+{
+    const int M = st->M;
+    const int s0 = st->slot[k];
+    const int sp = k + 1 < M ? st->slot[k + 1] : s0;
+    const int sm = k > 0 ? st->slot[k - 1] : s0;
+    const gmem<const double>* __restrict__ X0 = gp<const double>(Xs(b, s0));
+    const gmem<const double>* __restrict__ Xp = gp<const double>(Xs(b, sp));
+    const gmem<const double>* __restrict__ Xm = gp<const double>(Xs(b, sm));
+    double a[CFNEB_NPROF];
+#pragma unroll
+    for (int q = 0; q < CFNEB_NPROF; ++q) a[q] = 0.0;
+    for (int q = 0; q < CFNEB_TILE4 / CFNEB_TILE; ++q) {
+        const int r = tile * CFNEB_TILE4 + q * CFNEB_TILE + int(threadIdx.x);
+        if (r >= b.N + 3) break;
+        double f[3];
+        gen_force_row<T>(b, s0, r, f);
+        const bool atom = r < b.N;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = size_t(c) * b.ld + r;
+            const double x0 = X0[o];
+            const double tp = Xp[o] - x0, tm = x0 - Xm[o];
+            a[0] += tp * tp;
+            a[1] += tm * tm;
+            a[2] += tp * tm;
+            a[3] += f[c] * tp;
+            a[4] += f[c] * tm;
+            if (atom) {
+                a[5 + c] += tp;
+                a[8 + c] += tm;
+                a[11 + c] += f[c];
+            }
+        }
+    }
+    block_sum_t<CFNEB_NPROF>(a, lds);
+    if (threadIdx.x == 0) {
+        double* out = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4 + tile;
+        for (int q = 0; q < CFNEB_NPROF; ++q) out[size_t(q) * b.ntR4] = a[q];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CFNEB_TILE) k_profile_dots(BatchDev bd, unsigned vmask)
+{
+    __shared__ double lds[(CFNEB_TILE / 64) * CFNEB_NPROF];
+    ItemLoop loop(bd, KIND_ROW4, 1);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        if (!((vmask >> band_variant(b)) & 1u)) continue;  // uniform
+        profile_dots_item<T>(b, b.st, it.image, it.tile, lds);
+    }
+}
+
+// One block per image, one wave per sum.
+__global__ void __launch_bounds__(1024) k_profile_reduce(BatchDev bd)
+{
+    ItemLoop loop(bd, KIND_IMAGE, 1);
+    Item it;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const int k = it.image;
+        const double* part = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4;
+        if (w < CFNEB_NPROF) {
+            double a = 0.0;
+            for (int t = lane; t < b.ntR4; t += 64) a += part[size_t(w) * b.ntR4 + t];
+            a = wave_sum(a);
+            if (lane == 0) b.dotred[size_t(k) * CFNEB_NDOT + w] = a;
+        }
+    }
+}
+
+// Cubic Hermite interpolant on one interval of length d at t in [0, 1].
+__device__ inline double hermite_at(double H0, double H1, double m0, double m1, double d, double t)
+{
+    const double u = 1.0 - t;
+    // h00 = (1 + 2t) u^2, h10 = t u^2, h01 = t^2 (3 - 2t), h11 = -t^2 u
+    return (1.0 + 2.0 * t) * u * u * H0 + t * u * u * (d * m0) + t * t * (3.0 - 2.0 * t) * H1 -
+           t * t * u * (d * m1);
+}
+
+__global__ void __launch_bounds__(CFNEB_TILE) k_profile(BatchDev bd, int n_samples)
+{
+    __shared__ double s[CFNEB_MAX_IMAGES], H[CFNEB_MAX_IMAGES], m[CFNEB_MAX_IMAGES], len[CFNEB_MAX_IMAGES];
+    __shared__ double bv[CFNEB_MAX_IMAGES], ba[CFNEB_MAX_IMAGES];
+    ItemLoop loop(bd, KIND_BAND, 0);
+    Item it;
+    const int t = threadIdx.x;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const BandState* st = b.st;
+        const int M = st->M;
+        if (t < M) H[t] = b.scal[st->slot[t]].H;
+        __syncthreads();
+        if (t < M) {
+            const double* raw = b.dotred + size_t(t) * CFNEB_NDOT;
+            const double N = double(b.N);
+            double mp[3], mm[3], mf[3];
+            for (int c = 0; c < 3; ++c) {
+                mp[c] = raw[5 + c] / N;
+                mm[c] = raw[8 + c] / N;
+                mf[c] = raw[11 + c] / N;
+            }
+            auto nd = [&](const double* x, const double* y) {
+                return N * ((x[0] * y[0] + x[1] * y[1]) + x[2] * y[2]);
+            };
+            const double pp = raw[0] - nd(mp, mp), qq = raw[1] - nd(mm, mm), pq = raw[2] - nd(mp, mm);
+            const double fp = raw[3] - nd(mf, mp), fq = raw[4] - nd(mf, mm);
+            double a = 1.0, c = 0.0;
+            if (t == M - 1) {
+                a = 0.0;
+                c = 1.0;
+            } else if (t > 0) {
+                tangent_coeffs(H[t - 1], H[t], H[t + 1], a, c);
+            }
+            const double nt = sqrt(fmax(a * a * pp + 2.0 * a * c * pq + c * c * qq, 0.0));
+            m[t] = nt > 0.0 ? -(a * fp + c * fq) / nt : 0.0;
+            len[t] = sqrt(fmax(pp, 0.0));
+        }
+        __syncthreads();
+        if (t == 0) {
+            s[0] = 0.0;
+            for (int k = 0; k + 1 < M; ++k) s[k + 1] = s[k] + len[k];
+        }
+        __syncthreads();
+        // each interval: the largest of its right node and its interior critical points
+        if (t + 1 < M) {
+            const double d = s[t + 1] - s[t];
+            double best = H[t + 1], at = s[t + 1];
+            if (d > 0.0) {
+                const double g0 = d * m[t], g1 = d * m[t + 1];
+                // derivative in t of the interval's cubic: A t^2 + B t + C
+                const double A = 6.0 * (H[t] - H[t + 1]) + 3.0 * (g0 + g1);
+                const double B = 6.0 * (H[t + 1] - H[t]) - 4.0 * g0 - 2.0 * g1;
+                const double C = g0;
+                double r[2];
+                int nr = 0;
+                if (A == 0.0) {
+                    if (B != 0.0) r[nr++] = -C / B;
+                } else {
+                    const double disc = B * B - 4.0 * A * C;
+                    if (disc >= 0.0) {
+                        const double q = -0.5 * (B + copysign(sqrt(disc), B));
+                        r[nr++] = q / A;
+                        if (q != 0.0) r[nr++] = C / q;
+                    }
+                }
+                for (int j = 0; j < nr; ++j)
+                    if (r[j] > 0.0 && r[j] < 1.0) {
+                        const double v = hermite_at(H[t], H[t + 1], m[t], m[t + 1], d, r[j]);
+                        if (v > best) {
+                            best = v;
+                            at = s[t] + r[j] * d;
+                        }
+                    }
+            }
+            bv[t] = best;
+            ba[t] = at;
+        }
+        __syncthreads();
+        double* out = b.staging;
+        const double S = s[M - 1];
+        if (t == 0) {
+            double best = H[0], at = 0.0;
+            for (int k = 0; k + 1 < M; ++k)
+                if (bv[k] > best) {
+                    best = bv[k];
+                    at = ba[k];
+                }
+            out[CFNEB_PROF_OUT] = best - H[0];
+            out[CFNEB_PROF_OUT + 1] = S > 0.0 ? at / S : 0.0;
+            out[CFNEB_PROF_OUT + 2] = best;
+        }
+        if (t < M) {
+            out[CFNEB_PROF_S + t] = s[t];
+            out[CFNEB_PROF_H + t] = H[t];
+            out[CFNEB_PROF_SLOPE + t] = m[t];
+        }
+        for (int j = t; j < n_samples; j += int(blockDim.x)) {
+            const double x = double(j) / double(n_samples - 1) * S;
+            int k = 0;  // the last interval starting at or before x
+            for (int q = 1; q + 1 < M; ++q)
+                if (s[q] <= x) k = q;
+            const double d = s[k + 1] - s[k];
+            const double u = d > 0.0 ? fmin(fmax((x - s[k]) / d, 0.0), 1.0) : 0.0;
+            out[CFNEB_PROF_SAMP + j] = hermite_at(H[k], H[k + 1], m[k], m[k + 1], d, u);
+        }
+        __syncthreads();
+    }
+}
+
 static unsigned f32_mask(unsigned variants)
 {
     return variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_TS32));
@@ -563,6 +767,16 @@ void launch_dots(const Launch& L, hipStream_t s)
     if (f32_mask(L.variants)) k_band_dots<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, f32_mask(L.variants));
     if (f64_mask(L.variants)) k_band_dots<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, f64_mask(L.variants));
     k_band_dots_reduce<<<L.g[KIND_IMAGE], 1024, 0, s>>>(L.bd);
+}
+
+// Energy profile after an evaluation of every image (launch_evaluate(L, 1, s)).
+void launch_profile(const Launch& L, int n_samples, hipStream_t s)
+{
+    const unsigned g = L.g[KIND_ROW4];
+    if (f32_mask(L.variants)) k_profile_dots<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, f32_mask(L.variants));
+    if (f64_mask(L.variants)) k_profile_dots<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, f64_mask(L.variants));
+    k_profile_reduce<<<L.g[KIND_IMAGE], 1024, 0, s>>>(L.bd);
+    k_profile<<<L.g[KIND_BAND], CFNEB_TILE, 0, s>>>(L.bd, n_samples);
 }
 
 void launch_scalars(const Launch& L, hipStream_t s) { k_band_scalars<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd); }

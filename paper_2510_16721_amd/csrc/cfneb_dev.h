@@ -31,6 +31,17 @@
 #define CFNEB_TILE 256           // threads per block of every streaming kernel
 #define CFNEB_TILE4 1024         // rows (atoms) of a streaming item with 4 per thread
 #define CFNEB_NDOT 22            // band-dot partial sums per moving image and row tile
+#define CFNEB_NPROF 14           // energy-profile partial sums per image and row tile
+#define CFNEB_PROFILE_SAMPLES CFNEB_PROFILE_MAX_SAMPLES
+// Energy-profile readout area at the start of the staging buffer (doubles): arc
+// lengths s, enthalpies H and slopes dH/ds of the images, then barrier, normalized
+// coordinate of the maximum and H_max, then the samples.
+#define CFNEB_PROF_S 0
+#define CFNEB_PROF_H CFNEB_MAX_IMAGES
+#define CFNEB_PROF_SLOPE (2 * CFNEB_MAX_IMAGES)
+#define CFNEB_PROF_OUT (3 * CFNEB_MAX_IMAGES)
+#define CFNEB_PROF_SAMP (3 * CFNEB_MAX_IMAGES + 8)
+#define CFNEB_PROF_DOUBLES (CFNEB_PROF_SAMP + CFNEB_PROFILE_SAMPLES)
 #define CFNEB_MAX_SHIFT 7        // packed shifts are 4-bit offset-binary
 #define CFNEB_J_BITS 20
 #define CFNEB_MAX_ATOMS (1 << CFNEB_J_BITS)
@@ -627,6 +638,7 @@ void launch_init_state(const BandDev& b, int M, hipStream_t s);
 void launch_image_positions(const BandDev& b, int k, hipStream_t s);
 // Persistent launches over every live band of a table:
 void launch_plan(const Launch& L, int all_images, int ignore_stop, hipStream_t s);
+void launch_profile(const Launch& L, int n_samples, hipStream_t s);
 void launch_begin_call(const Launch& L, double f_tol, int only, hipStream_t s);
 void launch_geom(const Launch& L, int all_images, hipStream_t s);
 void launch_skin(const Launch& L, int all_images, hipStream_t s);

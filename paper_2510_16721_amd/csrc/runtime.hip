@@ -87,7 +87,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->maxpart = take(M * L->ntR4 * 3 * 8);
     L->skmax = take(M * size_t((L->N + CFNEB_TILE4 - 1) / CFNEB_TILE4) * 8);
     L->refpart = take(M * L->ntR * 2 * 8);
-    L->staging = take((6 * N + 64) * 8);
+    L->staging = take(std::max<size_t>(6 * N + 64, CFNEB_PROF_DOUBLES) * 8);
     L->state = take(sizeof(BandState));
     // the band's own one-entry table for the persistent kernels
     L->table = take(sizeof(BandDev));
@@ -704,6 +704,47 @@ int cfneb_energies(const cfneb_band* cb, double* H, int cap, int* n_images, doub
     }
     if (barrier) *barrier = st.barrier;
     if (ci_index) *ci_index = st.ci;
+    return CFNEB_OK;
+}
+
+int cfneb_profile(cfneb_band* b, int n_samples, double* s, double* H, double* slope, int cap, int* n_images,
+                  double* samples, double* barrier, double* xi_max)
+{
+    if (!b) return CFNEB_EINVAL;
+    if (n_samples < 0 || n_samples == 1 || n_samples > CFNEB_PROFILE_SAMPLES || (n_samples > 0 && !samples))
+        return fail(b, CFNEB_EINVAL, "cfneb_profile: n_samples");
+    int rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    BandState& st = *b->host_state;
+    if (st.err != 0) return fail(b, st.err, "cfneb_profile");
+    if ((s || H || slope) && cap < st.M) return fail(b, CFNEB_EINVAL, "cfneb_profile: cap");
+    if (st.done) {
+        // the evaluation kernels skip a band that converged in its last call; the flag
+        // only describes that call and is cleared by the next one anyway
+        st.done = 0;
+        rc = write_state(b);
+        if (rc != CFNEB_OK) return rc;
+    }
+    launch_evaluate(b->launch, 1, b->stream);
+    launch_profile(b->launch, n_samples, b->stream);
+    rc = check_kernels(b, "profile");
+    if (rc == CFNEB_OK) rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    if (st.err != 0) return fail(b, st.err, "cfneb_profile");
+    const int M = st.M;
+    std::vector<double> out(size_t(CFNEB_PROF_SAMP) + size_t(n_samples));
+    HIP_TRY(b, hipMemcpyAsync(out.data(), b->d.staging, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (n_images) *n_images = M;
+    for (int k = 0; k < M; ++k) {
+        if (s) s[k] = out[CFNEB_PROF_S + k];
+        if (H) H[k] = out[CFNEB_PROF_H + k];
+        if (slope) slope[k] = out[CFNEB_PROF_SLOPE + k];
+    }
+    for (int j = 0; j < n_samples; ++j) samples[j] = out[CFNEB_PROF_SAMP + j];
+    if (barrier) *barrier = out[CFNEB_PROF_OUT];
+    if (xi_max) *xi_max = out[CFNEB_PROF_OUT + 1];
     return CFNEB_OK;
 }
 
