@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("refine_every", ctypes.c_int),
         ("ins_num", ctypes.c_int), ("ins_den", ctypes.c_int),
         ("del_num", ctypes.c_int), ("del_den", ctypes.c_int),
+        ("stress_GPa", ctypes.c_double * 6),
     ]
 
 

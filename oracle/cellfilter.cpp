@@ -60,6 +60,27 @@ extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const d
     *H = e + P * omega;
     for (int k = 0; k < 9; ++k) V[k] = vir[k];
 
+    // Applied stress beyond the pressure: a second Piola-Kirchhoff stress S referred
+    // to h0 does the work Omega0 S : E on the Green-Lagrange strain E = (D D^T - I)/2
+    // (D maps reference rows to current rows, so lengths go with D D^T).  Its change
+    // under dD is Omega0 tr(S D dD^T), the same as that of a virial Omega0 D^T S D
+    // under the strain D^-1 dD, so it enters both filters through the virial.
+    double S[9];
+    const int voigt[9] = {0, 5, 4, 5, 1, 3, 4, 3, 2};
+    for (int k = 0; k < 9; ++k) S[k] = p->stress_GPa[voigt[k]] / kEvPerA3InGPa;
+    const double omega0 = std::fabs(orc_det3(h0));
+    double DT0[9], DDT[9], SD[9], DTSD[9];
+    orc::transpose3(D, DT0);
+    orc::matmul3(D, DT0, DDT);
+    orc::matmul3(S, D, SD);
+    orc::matmul3(DT0, SD, DTSD);
+    double SE = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) SE += S[3 * r + c] * 0.5 * (DDT[3 * r + c] - (r == c ? 1.0 : 0.0));
+    *H -= omega0 * SE;
+    double Vs[9];
+    for (int k = 0; k < 9; ++k) Vs[k] = vir[k] + omega0 * DTSD[k];
+
     // atoms: F D^T
     double DT[9];
     orc::transpose3(D, DT);
@@ -67,7 +88,7 @@ extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const d
     // lattice
     if (p->cell_filter == 2) {
         double Veff[9];
-        for (int k = 0; k < 9; ++k) Veff[k] = vir[k];
+        for (int k = 0; k < 9; ++k) Veff[k] = Vs[k];
         for (int k = 0; k < 3; ++k) Veff[4 * k] -= P * omega;
         orc_inv3(D, Dinv);
         orc::transpose3(Dinv, DinvT);
@@ -82,7 +103,7 @@ extern "C" int orc_cf_eval(const orc_params* p, int n, const double* h0, const d
     } else if (p->cell_filter == 1) {
         // D-variant (Sec. II.C, Eq. (13)): coordinates D, conjugate force D^-T V
         double Veff[9];
-        for (int k = 0; k < 9; ++k) Veff[k] = vir[k];
+        for (int k = 0; k < 9; ++k) Veff[k] = Vs[k];
         for (int k = 0; k < 3; ++k) Veff[4 * k] -= P * omega;
         orc_inv3(D, Dinv);
         orc::transpose3(Dinv, DinvT);

@@ -78,6 +78,10 @@ typedef struct orc_params {
     /* adaptive images */
     int refine_every;        /* 0 = off */
     int ins_num, ins_den, del_num, del_den;
+    /* applied stress beyond the pressure: a constant second Piola-Kirchhoff stress S
+       (Voigt xx yy zz yz xz xy, GPa, tensile positive) referred to h0; the enthalpy
+       gains -Omega0 S : E with E = (D D^T - I)/2 and Omega0 = |det h0| */
+    double stress_GPa[6];
 } orc_params;
 
 /* ---------------- 3x3 geometry (row-major, lattice vectors are rows) ---- */

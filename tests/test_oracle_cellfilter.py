@@ -208,3 +208,100 @@ def test_d_variant_keeps_rotations(orc):
         res.append((orc.evaluate(p, R, h)[0], h @ h.T))
     assert res[0][0] == pytest.approx(res[1][0], abs=1e-9)
     np.testing.assert_allclose(res[0][1], res[1][1], atol=1e-6)
+
+
+# ------------------------------------------------------------- applied stress
+# A constant second Piola-Kirchhoff stress S referred to h0 (the non-hydrostatic
+# loading that motivates finite-deformation NEB in Sec. I) adds -Omega0 S : E,
+# E = (D D^T - I)/2, to the enthalpy.
+STRESS_TS = (6.0, -3.5, 2.0, 4.0, -2.5, 5.0)  # GPa, Voigt xx yy zz yz xz xy
+STRESS_LJ = tuple(40.0 * s for s in STRESS_TS)
+
+
+@pytest.mark.parametrize("kind,filt", [("lj", 2), ("ts", 2), ("lj", 1), ("ts", 1)])
+def test_applied_stress_forces_by_finite_differences(orc, kind, filt):
+    p, h0, X = (_image if filt == 2 else _image_dvariant)(orc, kind, 5.0)
+    p.stress_GPa = STRESS_LJ if kind == "lj" else STRESS_TS
+    out = orc.cf_eval(p, h0, X)
+    n = X.shape[0] - 3
+    delta = 1e-6
+    dcell = delta * n
+    for m in range(3):
+        for k in range(3):
+            if filt == 2 and k < m:
+                continue
+            dX = np.zeros((3, 3))
+            dX[m, k] += dcell
+            if filt == 2:
+                dX[k, m] = dX[m, k]
+            Xp, Xm = X.copy(), X.copy()
+            Xp[n:] += dX
+            Xm[n:] -= dX
+            fd = -(orc.cf_eval(p, h0, Xp)["H"] - orc.cf_eval(p, h0, Xm)["H"]) / 2.0
+            # rotation-free: the printed B force is twice the conjugate (as without stress)
+            pred = (0.5 if filt == 2 else 1.0) * np.sum(out["Fg"][n:] * dX)
+            assert pred == pytest.approx(fd, rel=2e-5, abs=1e-9), (m, k)
+    # atom rows do not see the stress
+    q = orc.default_params(p.potential, pressure_GPa=5.0, cell_filter=filt)
+    np.testing.assert_array_equal(out["Fg"][:n], orc.cf_eval(q, h0, X)["Fg"][:n])
+
+
+def test_applied_stress_work_is_rotation_invariant(orc):
+    # the Green-Lagrange strain sees lengths only: rotating the current cell and
+    # atoms together (D -> D Q in the D-variant) changes neither U nor the stress work
+    p, h0, X = _image_dvariant(orc, "ts", 0.0)
+    p.stress_GPa = STRESS_TS
+    n = X.shape[0] - 3
+    Q = _rot(21)
+    Xr = X.copy()
+    Xr[n:] = X[n:] @ Q
+    a, b = orc.cf_eval(p, h0, X), orc.cf_eval(p, h0, Xr)
+    assert b["E"] == pytest.approx(a["E"], rel=1e-12)
+    assert b["H"] == pytest.approx(a["H"], rel=1e-12, abs=1e-12)
+    assert abs(a["H"] - a["E"]) > 1e-3  # the work term is not trivially zero here
+
+
+def test_isotropic_stress_agrees_with_pressure_to_first_order(orc):
+    # S = -P I against the pressure P: the stress work P Omega0 tr E equals
+    # P (Omega - Omega0) up to O(strain^2)
+    w = W.fcc_vacancy_hop(2, 2, 2, 1.5496)
+    P = 300.0
+    ps = orc.default_params(orc.LJ, cell_filter=1, stress_GPa=(-P, -P, -P, 0.0, 0.0, 0.0))
+    pp = orc.default_params(orc.LJ, cell_filter=1, pressure_GPa=P)
+    XA, _ = orc.build_endpoints(pp, w["pos_init"], w["cell_init"], w["pos_init"], w["cell_init"])
+    n = XA.shape[0] - 3
+    h0 = w["cell_init"]
+    rng = np.random.default_rng(8)
+    G = rng.normal(size=(3, 3))
+    res = []
+    for a in (1e-3, 2e-3, 4e-3):
+        X = XA.copy()
+        X[n:] = XA[n:] @ (np.eye(3) + a * G)
+        hs, hp = orc.cf_eval(ps, h0, X)["H"], orc.cf_eval(pp, h0, X)["H"]
+        om0 = abs(np.linalg.det(h0))
+        P_ev = P / 160.21766208
+        first = P_ev * om0 * a * np.trace(G)  # first-order volume term
+        d = hs - (hp - P_ev * om0)  # the pressure's enthalpy carries P Omega0 at the reference
+        assert abs(d) < 0.05 * abs(first)
+        res.append(d)
+    # the difference is second order: doubling the strain multiplies it by four
+    assert res[1] / res[0] == pytest.approx(4.0, rel=0.02)
+    assert res[2] / res[1] == pytest.approx(4.0, rel=0.02)
+
+
+def test_relaxed_crystal_carries_the_applied_stress(orc):
+    # relaxed under S, the crystal's own Cauchy stress -V/Omega is the push-forward
+    # J^-1 F S F^T of S (F = D^T in the row convention); tension lengthens its axis
+    w = W.fcc_vacancy_hop(2, 2, 2, 1.5496)
+    S = (120.0, -40.0, 20.0, 30.0, 0.0, -50.0)  # GPa; LJ in eV and A is stiff (~10^4 GPa)
+    for filt in (2, 1):
+        p = orc.default_params(orc.LJ, cell_filter=filt, stress_GPa=S)
+        R, h, steps, fmax = orc.relax(p, w["pos_init"], w["cell_init"], max_steps=5000, f_tol=1e-7)
+        assert fmax < 1e-7
+        D = np.linalg.solve(w["cell_init"], h)
+        E, u, F, V = orc.evaluate(orc.default_params(orc.LJ), R, h)
+        Sm = np.array([[S[0], S[5], S[4]], [S[5], S[1], S[3]], [S[4], S[3], S[2]]]) / 160.21766208
+        om, om0 = abs(np.linalg.det(h)), abs(np.linalg.det(w["cell_init"]))
+        np.testing.assert_allclose(-V / om, (om0 / om) * D.T @ Sm @ D, rtol=0, atol=2e-5)
+        # tension along x gives a positive Green-Lagrange strain there
+        assert 0.5 * (D @ D.T - np.eye(3))[0, 0] > 1e-3
