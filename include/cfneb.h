@@ -87,6 +87,14 @@ typedef struct cfneb_params {
                                are rebuilt when atoms (relative to the affinely strained cell)
                                or the cell moved enough that a pair could have crossed it.
                                0: rebuild every step.  The neighbour set is the same. */
+    double stress_GPa[6];   /* applied stress beyond the pressure, Voigt order xx yy zz yz xz
+                               xy, tensile positive: a constant second Piola-Kirchhoff stress S
+                               referred to the reference cell h0 (the non-hydrostatic loading
+                               that Sec. I names as the reason for finite-deformation NEB).
+                               Images carry H = U + P Omega - Omega0 S : E with
+                               E = (D D^T - I) / 2 and Omega0 = |det h0|, and the lattice
+                               forces of both filters follow from V_eff = V - P Omega I +
+                               Omega0 D^T S D.  All zero: hydrostatic only. */
 } cfneb_params;
 
 /* Optimizer and band bookkeeping, for checkpoints and tests. */

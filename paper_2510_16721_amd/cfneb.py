@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
         ("ins_num", ctypes.c_int), ("ins_den", ctypes.c_int),
         ("del_num", ctypes.c_int), ("del_den", ctypes.c_int),
         ("nbr_cap", ctypes.c_int), ("nbr_skin", ctypes.c_double),
+        ("stress_GPa", ctypes.c_double * 6),
     ]
 
 

@@ -130,6 +130,9 @@ struct BandDev {
     int climb_after, cell_filter;
     int relax;  // no tangent projection or springs: F_NEB = generalized force
     double cf, bscale, press;
+    int stressed;          // an applied stress beyond the pressure is set
+    double sapp[9];        // applied second Piola-Kirchhoff stress (eV/A^3), referred to h0
+    double omega0;         // |det h0|
     double dt0, dtmax, maxstep;
     int nmin;
     double finc, fdec, astart, fa;
@@ -612,6 +615,27 @@ __device__ inline void image_reduce_item(const BandDev& b, BandState* st, int sl
         finite = finite && isfinite(Veff[q]);
     }
     for (int q = 0; q < 3; ++q) Veff[4 * q] -= b.press * g.omega;
+    if (b.stressed) {
+        // H gains -Omega0 S : E with E = (D D^T - I) / 2, whose virtual work in the
+        // strain D^-1 dD is that of the extra virial Omega0 D^T S D
+        double SD[9], W[9];
+        mm3(b.sapp, g.D, SD);
+        double work = 0.0;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double e = 0.0, w = 0.0;
+                for (int q = 0; q < 3; ++q) {
+                    e += g.D[3 * r + q] * g.D[3 * c + q];
+                    w += g.D[3 * q + r] * SD[3 * q + c];
+                }
+                if (r == c) e -= 1.0;
+                work += b.sapp[3 * r + c] * (0.5 * e);
+                W[3 * r + c] = w;
+            }
+        s.H -= b.omega0 * work;
+        for (int q = 0; q < 9; ++q) Veff[q] += b.omega0 * W[q];
+        finite = finite && isfinite(s.H);
+    }
     double DinvT[9], T1[9], G[9];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) DinvT[3 * r + c] = g.Dinv[3 * c + r];

@@ -249,6 +249,17 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.relax = relax;
     d.bscale = p->b_force_scale;
     d.press = p->pressure_GPa / kEvPerA3InGPa;
+    {
+        // applied stress (Voigt xx yy zz yz xz xy) as a symmetric 3x3 in eV/A^3
+        static const int voigt[9] = {0, 5, 4, 5, 1, 3, 4, 3, 2};
+        d.stressed = 0;
+        for (int q = 0; q < 9; ++q) {
+            d.sapp[q] = p->stress_GPa[voigt[q]] / kEvPerA3InGPa;
+            if (d.sapp[q] != 0.0) d.stressed = 1;
+        }
+        d.omega0 = std::fabs(h0[0] * (h0[4] * h0[8] - h0[5] * h0[7]) - h0[1] * (h0[3] * h0[8] - h0[5] * h0[6]) +
+                             h0[2] * (h0[3] * h0[7] - h0[4] * h0[6]));
+    }
     d.dt0 = p->fire_dt0;
     d.dtmax = p->fire_dtmax;
     d.maxstep = p->fire_maxstep;
@@ -317,6 +328,8 @@ int validate(const cfneb_params* p, int64_t n_atoms)
     if (p->cell_filter < 0 || p->cell_filter > 2) return CFNEB_EINVAL;
     if (p->nbr_cap < 1 || p->nbr_cap > 1024) return CFNEB_EINVAL;
     if (!(p->nbr_skin >= 0.0) || !(p->nbr_skin <= 2.0)) return CFNEB_EINVAL;
+    for (int q = 0; q < 6; ++q)
+        if (!std::isfinite(p->stress_GPa[q])) return CFNEB_EINVAL;
     if (!(p->fire_dt0 > 0.0) || !(p->fire_maxstep > 0.0)) return CFNEB_EINVAL;
     if (p->refine_every < 0 || p->ins_num < 0 || p->ins_den < 1 || p->del_num < 0 || p->del_den < 1)
         return CFNEB_EINVAL;
@@ -444,6 +457,7 @@ int cfneb_params_default(int potential, cfneb_params* out)
     p.del_den = 4;
     p.nbr_cap = potential == CFNEB_LJ ? 128 : 16;
     p.nbr_skin = 0.3;
+    for (int q = 0; q < 6; ++q) p.stress_GPa[q] = 0.0;
     return CFNEB_OK;
 }
 
