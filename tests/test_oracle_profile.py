@@ -133,3 +133,29 @@ def test_vacancy_hop_profile_peaks_at_the_climbing_image(orc):
     assert pr["barrier"] == pytest.approx(pr["H"][3] - pr["H"][0], abs=1e-6)
     assert pr["barrier"] == pytest.approx(e["barrier"], abs=1e-3)
     assert pr["samples"][0] == pr["H"][0] and pr["samples"][-1] == pr["H"][-1]
+
+
+def test_coincident_images_give_a_zero_length_interval(orc):
+    # two coincident images (same X, so the same H): the interval between them has
+    # zero length and carries no curve; the nodes are still reproduced and the maximum
+    # agrees with dense sampling
+    rng = np.random.default_rng(9)
+    s = np.array([0.0, 0.7, 0.7, 1.5, 2.2])
+    H = np.array([0.0, 0.8, 0.8, 0.3, -0.2])
+    for trial in range(5):
+        sl = 2.0 * rng.standard_normal(5)
+        np.testing.assert_allclose(orc.spline_eval(s, H, sl, s), H, atol=1e-14)
+        # the slopes on the two sides of the zero-length interval differ, so the curve
+        # may peak at a kink on a node: the grid includes the nodes
+        dense = orc.spline_eval(s, H, sl, np.union1d(np.linspace(0, s[-1], 100001), s))
+        assert np.isfinite(dense).all()
+        hm, at = orc.spline_max(s, H, sl)
+        assert dense.max() <= hm + 1e-12 and hm - dense.max() < 1e-7
+    # from coordinates: the coincident pair has zero spacing and one-sided slopes
+    natoms, s0, X, H0, dH, Fg, c = _straight_cubic_band(rng)
+    X[3] = X[2]
+    Fg[3] = Fg[2]
+    H0 = H0.copy()
+    H0[3] = H0[2]
+    s1, sl1 = orc.profile(X, H0, Fg, natoms)
+    assert s1[3] == s1[2] and np.isfinite(sl1).all()
