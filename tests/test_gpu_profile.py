@@ -154,3 +154,25 @@ def test_full_size_profile_sampled():
     assert abs(sl0[0] - pr["slope"][0]) <= tol_slope
     assert np.isfinite(pr["samples"]).all()
     assert pr["barrier"] >= pr["H"].max() - pr["H"][0] - 1e-9
+
+
+def test_profile_with_coincident_images():
+    # two coincident images: a zero-length interval (no curve on it), one-sided
+    # tangents beside it; the device and the oracle agree on the whole profile
+    import oracle
+    kw = dict(n_images=7, max_images=7, climb_after=-1)
+    g, _, w, kind = make_pair("lj31", fp64=True, oracle_too=False, **kw)
+    g.step(5)
+    st = g.get_state()
+    X = st["X"].copy()
+    X[3] = X[2]
+    g.set_state(X, st["v"], st["dt"], st["alpha"], st["n_pos"], st["fresh"], st["step"], st["ci"])
+    pr = g.profile(n_samples=301)
+    ref = _oracle_profile(oracle_params_like(kind, **kw), w["cell_init"], X, g.n, 301)
+    tol_h, tol_slope, tol_samp = _tolerances(g.n, ref["s"])
+    assert pr["s"][3] == pr["s"][2] and ref["s"][3] == ref["s"][2]
+    assert pr["H"][3] == pr["H"][2]
+    np.testing.assert_allclose(pr["s"], ref["s"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(pr["slope"], ref["slope"], rtol=0, atol=tol_slope)
+    np.testing.assert_allclose(pr["samples"], ref["samples"], rtol=0, atol=tol_samp)
+    assert abs(pr["barrier"] - ref["barrier"]) <= 2 * tol_samp
