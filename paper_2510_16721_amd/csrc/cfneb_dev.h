@@ -432,6 +432,7 @@ __device__ inline void plan_block(const BatchDev& bd, int all_images, int ignore
 #define CFNEB_GRID_TILES 2048
 #define CFNEB_GRID_IMAGES 512
 #define CFNEB_GRID_BANDS CFNEB_MAX_BANDS
+#define CFNEB_GRID_FORCE 16384
 
 __host__ __device__ inline unsigned grid_for(long long max_items, unsigned cap)
 {
@@ -454,6 +455,10 @@ __host__ __device__ inline int band_variant(const BandDev& b)
 struct Launch {
     BatchDev bd;
     unsigned g[NKIND];
+    // grid of the two Tersoff force kernels: one block per atom tile of the largest
+    // item count, so that the hardware hands out the last tiles to whichever slots
+    // free first (a persistent grid gives some blocks one tile more than others)
+    unsigned g_force;
     unsigned variants;
 };
 

@@ -110,6 +110,7 @@ void size_grids(Launch& L, long long atom_tiles, long long row_tiles, long long 
     L.g[KIND_IVAL] = grid_for(row_tiles, CFNEB_GRID_TILES);
     L.g[KIND_SLOTROW] = grid_for(row_tiles, CFNEB_GRID_TILES);
     L.g[KIND_BAND] = grid_for(bands, CFNEB_GRID_BANDS);
+    L.g_force = grid_for(atom_tiles, CFNEB_GRID_FORCE);
 }
 
 const char* err_text(int code)
@@ -1099,6 +1100,8 @@ int cfneb_batch_create(int max_bands, void* workspace, size_t workspace_bytes, v
     B->launch.bd.cap = max_bands;
     // any band may join later: size the persistent grids for the whole chip
     size_grids(B->launch, 1LL << 40, 1LL << 40, 1LL << 40, 1LL << 40, max_bands, 1LL << 40, 1LL << 40);
+    // a batch's item count is unknown in advance: its force kernels stay persistent
+    B->launch.g_force = B->launch.g[KIND_ATOM];
     B->launch.variants = 0;
     const char* ng = std::getenv("CFNEB_NO_GRAPH");
     B->use_graph = !(ng && ng[0] == '1');

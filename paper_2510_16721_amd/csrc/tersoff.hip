@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_gather(BatchDev bd, int all_i
 
 void launch_tersoff_stage(const Launch& L, int all_images, int stage, hipStream_t s)
 {
-    const unsigned g = L.g[KIND_ATOM];
+    const unsigned g = L.g_force;
     if (L.variants & (1u << VARIANT_TS32)) {
         if (stage == 0) k_ts_filter_bonds<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS32);
         if (stage == 1) k_ts_gather<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_TS32);
