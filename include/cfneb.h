@@ -221,8 +221,8 @@ int cfneb_get_image(const cfneb_band* b, int k, double* pos, double* cell);
  * FIRE, as in a band step, on the generalized coordinates (R~, c_f B) with the
  * input cell as reference h0, driven by the generalized force (F D^T, G / c_f)
  * without projection or springs, until the largest row norm is below f_tol or
- * max_steps moves were made.  Potential, pressure, cell filter, cell factor and
- * FIRE fields of p apply; image, spring, climbing-image and refine fields are
+ * max_steps moves were made.  Potential, pressure, applied stress (referred to the
+ * input cell), cell filter, cell factor and FIRE fields of p apply; image, spring, climbing-image and refine fields are
  * ignored.  pos (n_atoms x 3) and cell (3x3) are host arrays, read, then
  * overwritten with the relaxed R = R~ D and h = h0 D; on error they are left as
  * they were.  workspace: >= cfneb_band_bytes(p, n_atoms, 3) device bytes,
