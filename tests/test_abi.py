@@ -77,3 +77,26 @@ def test_size_limits_are_rejected_on_the_host(L):
     q = cfneb.default_params(cfneb.CFNEB_LJ, nbr_skin=-0.1)
     with pytest.raises(cfneb.CfnebError):
         cfneb.band_bytes(q, 10)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no CPU fallback: without the built HIP library every call raises
+    from paper_2510_16721_amd import cfneb
+    monkeypatch.setattr(cfneb, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libcfneb.so"))
+    monkeypatch.setattr(cfneb, "_LIB", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        cfneb.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        cfneb.default_params(cfneb.CFNEB_LJ)
+
+
+def test_product_never_reaches_the_oracle():
+    # the package and the HIP sources name no oracle module, header or library
+    pkg = os.path.join(ROOT, "paper_2510_16721_amd")
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath or "__pycache__" in dirpath:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\bimport\s+oracle\b|\bfrom\s+oracle\b|oracle\.h|liborc", text), f
