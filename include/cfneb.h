@@ -115,9 +115,10 @@ enum {
     CFNEB_PH_BINS,          /* bin ids, counting sort, per-bin order (rebuilds only) */
     CFNEB_PH_NLIST,         /* candidate pairs within rc + skin (rebuilds only) */
     CFNEB_PH_FILTER,        /* exact neighbour test of the candidates, packed lists */
-    CFNEB_PH_FORCE0,        /* LJ pair forces, or Tersoff zeta and bond orders */
-    CFNEB_PH_FORCE1,        /* Tersoff dU_i/dr^ij per bond (unused for LJ) */
-    CFNEB_PH_FORCE2,        /* Tersoff force gather (unused for LJ) */
+    CFNEB_PH_FORCE0,        /* LJ pair forces, or for Tersoff the exact test of the
+                               candidates, bond orders, energy, virial and dU_i/dr^ij */
+    CFNEB_PH_FORCE1,        /* Tersoff force gather (unused for LJ) */
+    CFNEB_PH_FORCE2,        /* (empty: the Tersoff kernels are fused into two) */
     CFNEB_PH_REDUCE,        /* (empty in a step: the dots phase reduces E and V) */
     CFNEB_PH_DOTS,          /* per-image E, V, enthalpy, lattice force; band dots */
     CFNEB_PH_SCALARS,       /* tangents, climbing image, projection, FIRE proposal */
