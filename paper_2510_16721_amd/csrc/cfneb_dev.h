@@ -455,10 +455,11 @@ __host__ __device__ inline int band_variant(const BandDev& b)
 struct Launch {
     BatchDev bd;
     unsigned g[NKIND];
-    // grid of the two Tersoff force kernels: one block per atom tile of the largest
-    // item count, so that the hardware hands out the last tiles to whichever slots
-    // free first (a persistent grid gives some blocks one tile more than others)
-    unsigned g_force;
+    // grid of the force kernels (LJ pair kernel, the two Tersoff kernels): the
+    // persistent grid g[KIND_ATOM] or one block per atom tile of the largest item
+    // count (g_force_tile), where the hardware hands the last tiles to whichever
+    // slots free first; chosen by timing before the step graphs are captured
+    unsigned g_force, g_force_tile;
     unsigned variants;
 };
 

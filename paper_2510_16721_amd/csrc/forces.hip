@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BatchDev bd, int al
 // stage 0: LJ, or Tersoff bond orders and dU_i/dr^ij; 1: Tersoff gather
 void launch_force_stage(const Launch& L, int all_images, int stage, hipStream_t s)
 {
-    const unsigned g = L.g[KIND_ATOM];
+    const unsigned g = L.g_force;
     if (stage == 0) {
         if (L.variants & (1u << VARIANT_LJ32)) k_lj<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ32);
         if (L.variants & (1u << VARIANT_LJ64)) k_lj<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ64);

@@ -110,7 +110,8 @@ void size_grids(Launch& L, long long atom_tiles, long long row_tiles, long long 
     L.g[KIND_IVAL] = grid_for(row_tiles, CFNEB_GRID_TILES);
     L.g[KIND_SLOTROW] = grid_for(row_tiles, CFNEB_GRID_TILES);
     L.g[KIND_BAND] = grid_for(bands, CFNEB_GRID_BANDS);
-    L.g_force = grid_for(atom_tiles, CFNEB_GRID_FORCE);
+    L.g_force_tile = grid_for(atom_tiles, CFNEB_GRID_FORCE);
+    L.g_force = L.g_force_tile;
 }
 
 const char* err_text(int code)
@@ -375,8 +376,56 @@ int launch_step_direct(cfneb_band* b, bool with_refine)
     return check_kernels(b, "step");
 }
 
+// Launch-shape tuning of the force kernels, before the step graphs are captured.
+// Both grids give bit-identical results (each item is computed the same way
+// whichever block takes it), so the faster is kept.  The table's moving images are
+// re-evaluated from their current positions and candidate lists (what the last
+// evaluation computed, so the stored forces do not change); three repetitions of
+// both force phases per grid, timed with HIP events on the table's stream.
+int tune_force_grid(Launch& L, hipStream_t s)
+{
+    const unsigned cand[2] = {L.g[KIND_ATOM], L.g_force_tile};
+    if (cand[0] == cand[1]) {
+        L.g_force = cand[0];
+        return CFNEB_OK;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return CFNEB_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CFNEB_EHIP;
+    }
+    int rc = CFNEB_OK;
+    float best = 0.0f;
+    unsigned pick = L.g_force_tile;
+    launch_plan(L, 0, 1, s);
+    for (int c = 0; c < 2 && rc == CFNEB_OK; ++c) {
+        L.g_force = cand[c];
+        launch_force_stage(L, 0, 0, s);  // warm-up
+        launch_force_stage(L, 0, 1, s);
+        if (hipEventRecord(e0, s) != hipSuccess) rc = CFNEB_EHIP;
+        for (int r = 0; r < 3; ++r) {
+            launch_force_stage(L, 0, 0, s);
+            launch_force_stage(L, 0, 1, s);
+        }
+        float ms = 0.0f;
+        if (rc != CFNEB_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+            rc = CFNEB_EHIP;
+        else if (c == 0 || ms < best) {
+            best = ms;
+            pick = cand[c];
+        }
+    }
+    L.g_force = pick;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 int capture_band_graphs(cfneb_band* b)
 {
+    if (tune_force_grid(b->launch, b->stream) != CFNEB_OK) return fail(b, CFNEB_EHIP, "tuning");
     HIP_TRY(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed));
     launch_step(b->launch, b->capture_stream);
     HIP_TRY(b, hipStreamEndCapture(b->capture_stream, &b->graph));
@@ -1029,6 +1078,7 @@ void drop_graph(cfneb_batch* B)
 
 int capture_batch_graphs(cfneb_batch* B)
 {
+    if (tune_force_grid(B->launch, B->stream) != CFNEB_OK) return CFNEB_EHIP;
     if (hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return CFNEB_EHIP;
     launch_step(B->launch, B->capture_stream);
     if (hipStreamEndCapture(B->capture_stream, &B->graph) != hipSuccess ||
@@ -1100,8 +1150,6 @@ int cfneb_batch_create(int max_bands, void* workspace, size_t workspace_bytes, v
     B->launch.bd.cap = max_bands;
     // any band may join later: size the persistent grids for the whole chip
     size_grids(B->launch, 1LL << 40, 1LL << 40, 1LL << 40, 1LL << 40, max_bands, 1LL << 40, 1LL << 40);
-    // a batch's item count is unknown in advance: its force kernels stay persistent
-    B->launch.g_force = B->launch.g[KIND_ATOM];
     B->launch.variants = 0;
     const char* ng = std::getenv("CFNEB_NO_GRAPH");
     B->use_graph = !(ng && ng[0] == '1');
