@@ -385,6 +385,12 @@ int launch_step_direct(cfneb_band* b, bool with_refine)
 int tune_force_grid(Launch& L, hipStream_t s)
 {
     const unsigned cand[2] = {L.g[KIND_ATOM], L.g_force_tile};
+    // CFNEB_FORCE_GRID=persistent|tile fixes the choice (tests, reproducible timing)
+    const char* fixed = std::getenv("CFNEB_FORCE_GRID");
+    if (fixed && (std::strcmp(fixed, "persistent") == 0 || std::strcmp(fixed, "tile") == 0)) {
+        L.g_force = cand[fixed[0] == 'p' ? 0 : 1];
+        return CFNEB_OK;
+    }
     if (cand[0] == cand[1]) {
         L.g_force = cand[0];
         return CFNEB_OK;

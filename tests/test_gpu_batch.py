@@ -187,3 +187,22 @@ def test_batch_refinement_schedule_one_call_equals_single_steps():
     assert [b.get_state()["X"].shape[0] for b in runs[0][0]] == [9, 8]
     for _, batch in runs:
         batch.close()
+
+
+def test_force_grid_shapes_give_identical_batches(monkeypatch):
+    # the tuner chooses between the persistent grid (2,048 blocks) and one block per
+    # atom tile (16,384 for a batch) for the force kernels: both give the same bands
+    # bit for bit
+    from paper_2510_16721_amd import cfneb
+    runs = []
+    for shape in ("persistent", "tile"):
+        monkeypatch.setenv("CFNEB_FORCE_GRID", shape)
+        bands = _bands()
+        batch = cfneb.Batch(8)
+        for b in bands:
+            batch.attach(b)
+        batch.step(23)
+        batch.close()
+        runs.append(bands)
+    for a, b in zip(*runs):
+        _same_state(a, b)
