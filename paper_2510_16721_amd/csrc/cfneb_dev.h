@@ -75,6 +75,7 @@ struct SkinState {
     double href[9], hrefinv[9];
     int valid;                 // a candidate list exists for this slot
     int rebuild;               // this step rebuilds it
+    int held;                  // rebuild, set aside while the force grid is tuned
 };
 
 struct ImageScal {
@@ -668,6 +669,10 @@ void launch_init_state(const BandDev& b, int M, hipStream_t s);
 void launch_image_positions(const BandDev& b, int k, hipStream_t s);
 // Persistent launches over every live band of a table:
 void launch_plan(const Launch& L, int all_images, int ignore_stop, hipStream_t s);
+// Set aside (hold = 1) or restore (hold = 0) the per-slot rebuild flags of every live
+// band, so that force kernels re-run outside a step do the work of a step without a
+// candidate rebuild.
+void launch_skin_hold(const Launch& L, int hold, hipStream_t s);
 void launch_profile(const Launch& L, int n_samples, hipStream_t s);
 void launch_begin_call(const Launch& L, double f_tol, int only, hipStream_t s);
 void launch_geom(const Launch& L, int all_images, hipStream_t s);

@@ -476,6 +476,28 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_filter(BatchDev bd, int all_imag
     }
 }
 
+__global__ void k_skin_hold(BatchDev bd, int hold)
+{
+    for (int q = int(blockIdx.x); q < bd.cap; q += int(gridDim.x)) {
+        if (!bd.live[q]) continue;
+        const BandDev& b = bd.bands[q];
+        for (int slot = int(threadIdx.x); slot < b.Mcap; slot += int(blockDim.x)) {
+            SkinState& sk = b.skst[slot];
+            if (hold) {
+                sk.held = sk.rebuild;
+                sk.rebuild = 0;
+            } else {
+                sk.rebuild = sk.held;
+            }
+        }
+    }
+}
+
+void launch_skin_hold(const Launch& L, int hold, hipStream_t s)
+{
+    k_skin_hold<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd, hold);
+}
+
 void launch_skin(const Launch& L, int all_images, hipStream_t s)
 {
     k_skin_check<<<L.g[KIND_ATOM4], CFNEB_TILE, 0, s>>>(L.bd, all_images);

@@ -380,8 +380,9 @@ int launch_step_direct(cfneb_band* b, bool with_refine)
 // Both grids give bit-identical results (each item is computed the same way
 // whichever block takes it), so the faster is kept.  The table's moving images are
 // re-evaluated from their current positions and candidate lists (what the last
-// evaluation computed, so the stored forces do not change); three repetitions of
-// both force phases per grid, timed with HIP events on the table's stream.
+// evaluation computed, so the stored forces do not change), with the candidate
+// rebuild flags held back as on most steps; three repetitions of both force phases
+// per grid, timed with HIP events on the table's stream.
 int tune_force_grid(Launch& L, hipStream_t s)
 {
     const unsigned cand[2] = {L.g[KIND_ATOM], L.g_force_tile};
@@ -405,6 +406,7 @@ int tune_force_grid(Launch& L, hipStream_t s)
     float best = 0.0f;
     unsigned pick = L.g_force_tile;
     launch_plan(L, 0, 1, s);
+    launch_skin_hold(L, 1, s);
     for (int c = 0; c < 2 && rc == CFNEB_OK; ++c) {
         L.g_force = cand[c];
         launch_force_stage(L, 0, 0, s);  // warm-up
@@ -423,6 +425,7 @@ int tune_force_grid(Launch& L, hipStream_t s)
             pick = cand[c];
         }
     }
+    launch_skin_hold(L, 0, s);
     L.g_force = pick;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
