@@ -88,11 +88,13 @@ def test_energy_force_virial_per_image(name, fp64):
                                    atol=TOL_V_PER_ATOM * scale * 10)
 
 
-@pytest.mark.parametrize("name,fp64,steps_before", [("lj255", True, 0), ("lj255", True, 12),
-                                                    ("lj255", False, 12), ("ts_small", False, 8),
-                                                    ("ts_small", True, 8)])
-def test_one_step_from_identical_state(name, fp64, steps_before):
-    kw = dict(n_images=6, max_images=6, climb_after=5, k_spring=2.0)
+@pytest.mark.parametrize("name,fp64,steps_before,extra", [
+    ("lj255", True, 0, {}), ("lj255", True, 12, {}), ("lj255", False, 12, {}), ("ts_small", False, 8, {}),
+    ("ts_small", True, 8, {}), ("ts4608", False, 3, {}),
+    ("ts_small", False, 8, dict(stress_GPa=(6.0, -3.5, 2.0, 4.0, -2.5, 5.0), pressure_GPa=3.0)),
+    ("ts_small", False, 8, dict(cell_filter=1, stress_GPa=(6.0, -3.5, 2.0, 4.0, -2.5, 5.0)))])
+def test_one_step_from_identical_state(name, fp64, steps_before, extra):
+    kw = dict(n_images=6, max_images=6, climb_after=5, k_spring=2.0, **extra)
     g, o, w, kind = make_pair(name, fp64=fp64, **kw)
     if steps_before:
         g.step(steps_before)
