@@ -4,7 +4,7 @@
 //   NEB force (Sec. II.A, Eq. (1)):  F_NEB = F - (F . t) t + k (|tau+| - |tau-|) t
 //   climbing image (cited in Sec. I):  F_CI = F - 2 (F . t) t, no spring
 //   improved tangent (cited in Sec. I): energy-weighted upwind choice of tau+ / tau-
-//   FIRE (the "standard optimizer" of Secs. II.C / III), band-global, unit mass
+//   FIRE (the usual optimizer of the band, Secs. II.C / III), band-global, unit mass
 //   adaptive images (Sec. III): after an iteration, insert an image into a long
 //   interval or delete an image between two short ones.
 #include "internal.h"

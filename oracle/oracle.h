@@ -18,11 +18,15 @@
  *   - virial V = -1/2 sum r^{ij} (x) f^{ij}:                          Sec. II.B, Eqs. (6)-(8)
  *   - deformation gradient D = h0^-1 h, R~ = R D^-1:                  Sec. II.C, Eqs. (10)-(11)
  *   - rotation-free filter B = D D^T, lattice force D^-T V D^-1:      Sec. II.C, Eqs. (15)-(17)
+ *   - D-variant filter, coordinates D, lattice force D^-T V:          Sec. II.C, Eqs. (11)-(14)
+ *   - applied anisotropic stress (a constant second Piola-Kirchhoff
+ *     stress referred to h0; non-hydrostatic loading is named in
+ *     Sec. I as the reason for finite-deformation NEB):              a reading, not in the paper
  *   - NEB force = perpendicular true force + spring:                  Sec. II.A, Eq. (1)
  *   - improved tangent / climbing image (cited by the paper,
  *     Henkelman & Jonsson 2000; Henkelman, Uberuaga & Jonsson 2000)   Sec. I / II.A
  *   - adaptive insertion / deletion of images after each iteration:   Sec. III
- *   - FIRE (Bitzek et al. 2006) as the "standard optimizer":          Sec. II.C / III
+ *   - FIRE (Bitzek et al. 2006), the usual optimizer of the band:     Sec. II.C / III
  *   - energy profile, enthalpy against the normalized path
  *     coordinate, as the transitions are reported (Hermite
  *     interpolant with tangential-force slopes):                     Sec. III figures
