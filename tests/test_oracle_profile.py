@@ -159,3 +159,30 @@ def test_coincident_images_give_a_zero_length_interval(orc):
     H0[3] = H0[2]
     s1, sl1 = orc.profile(X, H0, Fg, natoms)
     assert s1[3] == s1[2] and np.isfinite(sl1).all()
+
+
+def test_profile_of_the_analytic_surface_peaks_at_its_saddle(orc):
+    # V(x, y) = (1 - x^2)^2 + kappa (y - x^2)^2 on a curved path: a converged
+    # climbing-image band sits on the saddle (0, 0) with V = 1.  With the closed-form
+    # gradient as forces (no atoms, no translation to remove), the slopes vanish at
+    # the two minima and at the saddle, and the interpolant's maximum is the saddle's
+    kappa, M = 2.0, 9
+    t = np.linspace(0, 1, M)
+    xy = np.stack([-1 + 2 * t, 1.0 + 0.3 * np.sin(np.pi * t)], axis=1)
+    xy[0], xy[-1] = [-1, 1], [1, 1]
+    out = orc.neb2d(kappa, xy, k_spring=1.0, climb_after=20, dt0=0.01, dtmax=0.05, maxstep=0.05,
+                    max_steps=50000, f_tol=1e-9)
+    P = out["xy"]
+    x, y = P[:, 0], P[:, 1]
+    V = (1 - x**2) ** 2 + kappa * (y - x**2) ** 2
+    gx = -4 * x * (1 - x**2) - 4 * kappa * x * (y - x**2)
+    gy = 2 * kappa * (y - x**2)
+    F = -np.stack([gx, gy], axis=1)
+    s, sl = orc.profile(P, V, F, 0)
+    ci = (M - 1) // 2
+    assert abs(sl[0]) < 1e-12 and abs(sl[-1]) < 1e-12 and abs(sl[ci]) < 1e-8
+    hm, at = orc.spline_max(s, V, sl)
+    assert hm == pytest.approx(1.0, abs=1e-8)
+    assert at == pytest.approx(s[ci], abs=1e-6)
+    # uphill then downhill along the path
+    assert np.all(sl[1:ci] > 0) and np.all(sl[ci + 1:-1] < 0)
