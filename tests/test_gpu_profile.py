@@ -176,3 +176,27 @@ def test_profile_with_coincident_images():
     np.testing.assert_allclose(pr["slope"], ref["slope"], rtol=0, atol=tol_slope)
     np.testing.assert_allclose(pr["samples"], ref["samples"], rtol=0, atol=tol_samp)
     assert abs(pr["barrier"] - ref["barrier"]) <= 2 * tol_samp
+
+
+def test_profile_of_a_band_stepped_in_a_batch():
+    # a band stepped inside a batch (between batch calls) reads out the same profile
+    # as the oracle computes from its coordinates
+    from paper_2510_16721_amd import cfneb
+    kw = dict(n_images=7, max_images=9, climb_after=10, pressure_GPa=2.0)
+    g, _, w, kind = make_pair("ts_small", oracle_too=False, **kw)
+    other, _, _, _ = make_pair("lj_ragged", oracle_too=False, n_images=5, max_images=5)
+    batch = cfneb.Batch(4)
+    batch.attach(g)
+    batch.attach(other)
+    batch.step(12)
+    pr = g.profile(n_samples=129)
+    X = g.get_state()["X"]
+    ref = _oracle_profile(oracle_params_like(kind, **kw), w["cell_init"], X, g.n, 129)
+    tol_h, tol_slope, tol_samp = _tolerances(g.n, ref["s"])
+    np.testing.assert_allclose(pr["s"], ref["s"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(pr["H"], ref["H"], rtol=0, atol=tol_h)
+    np.testing.assert_allclose(pr["samples"], ref["samples"], rtol=0, atol=tol_samp)
+    # the batch goes on stepping after the readout
+    steps, conv, errs = batch.step(3)
+    assert not errs.any()
+    batch.close()
