@@ -208,7 +208,11 @@ int cfneb_energies(const cfneb_band* b, double* H, int cap, int* n_images, doubl
  * 2 .. CFNEB_PROFILE_MAX_SAMPLES; *barrier = its maximum minus H_0; *xi_max = the
  * normalized coordinate of that maximum.  Overwrites the images' stored energies
  * and forces with those of the current coordinates (what a following step computes
- * first anyway); not during a cfneb_batch_step call of a batch holding the band. */
+ * first anyway); not during a cfneb_batch_step call of a batch holding the band.
+ * Errors: CFNEB_EINVAL for n_samples outside that range (or samples NULL with
+ * n_samples > 0) or cap < M; the band's own error code if its last call failed or
+ * the evaluation finds a non-finite energy, force or virial (outputs untouched).
+ * Synchronises the band's stream before returning. */
 #define CFNEB_PROFILE_MAX_SAMPLES 4096
 int cfneb_profile(cfneb_band* b, int n_samples, double* s, double* H, double* slope, int cap, int* n_images,
                   double* samples, double* barrier, double* xi_max);
