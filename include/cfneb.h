@@ -24,6 +24,9 @@
  *     for the last failure of a band is in cfneb_last_error.  A step that fails
  *     leaves the band at its pre-step state.
  *   - Threading: one host thread per band handle at a time.
+ *   - Environment: CFNEB_NO_GRAPH=1 launches every step kernel by kernel instead of
+ *     through captured hipGraphs (same results); CFNEB_FORCE_GRID=persistent|tile
+ *     fixes the force kernels' grid instead of choosing it by timing (same results).
  */
 #ifndef CFNEB_H
 #define CFNEB_H
