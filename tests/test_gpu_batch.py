@@ -206,3 +206,16 @@ def test_force_grid_shapes_give_identical_batches(monkeypatch):
         runs.append(bands)
     for a, b in zip(*runs):
         _same_state(a, b)
+
+
+def test_graph_and_direct_launches_give_identical_bands(monkeypatch):
+    # CFNEB_NO_GRAPH=1 launches the step kernel by kernel: the same band bit for bit,
+    # refinements included
+    runs = []
+    for no_graph in ("1", "0"):
+        monkeypatch.setenv("CFNEB_NO_GRAPH", no_graph)
+        g, _, _, _ = make_pair("ts_small", oracle_too=False, n_images=6, max_images=8, refine_every=5,
+                               climb_after=8)
+        assert g.step(23)[0] == 23
+        runs.append(g)
+    _same_state(runs[0], runs[1])
