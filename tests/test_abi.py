@@ -100,3 +100,19 @@ def test_product_never_reaches_the_oracle():
             if f.endswith((".py", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"\bimport\s+oracle\b|\bfrom\s+oracle\b|oracle\.h|liborc", text), f
+
+
+def test_applied_stress_is_validated_on_the_host(L):
+    # the six stress components sit at the end of cfneb_params: a non-finite one is
+    # refused, finite ones are accepted (and the default is no stress)
+    from paper_2510_16721_amd import cfneb
+    p = cfneb.default_params(cfneb.CFNEB_TERSOFF_C)
+    assert list(p.stress_GPa) == [0.0] * 6
+    ok = cfneb.default_params(cfneb.CFNEB_TERSOFF_C, stress_GPa=(1.0, -2.0, 0.5, 0.0, 3.0, -1.0))
+    assert cfneb.band_bytes(ok, 100) > 0
+    for q in range(6):
+        s = [0.0] * 6
+        s[q] = float("inf") if q % 2 else float("nan")
+        bad = cfneb.default_params(cfneb.CFNEB_TERSOFF_C, stress_GPa=tuple(s))
+        with pytest.raises(cfneb.CfnebError):
+            cfneb.band_bytes(bad, 100)
