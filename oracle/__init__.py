@@ -106,6 +106,9 @@ def _declare(L):
                             c_int, c_double, _dp, ctypes.POINTER(c_int), _dp]
     L.orc_relax.argtypes = [ctypes.POINTER(Params), c_int, _dp, _dp, c_int, c_double,
                             ctypes.POINTER(c_int), _dp]
+    L.orc_path_coord.argtypes = [c_int, c_int, c_int, _dp, _dp]
+    L.orc_fire_step.argtypes = [c_int, c_int, c_int, _dp, _dp, _dp, ctypes.POINTER(FireState),
+                                c_double, c_double, c_int, c_double, c_double, c_double, c_double]
 
 
 def _d(a):
@@ -280,6 +283,34 @@ def profile(X, H, Fg, natoms):
     _check(lib().orc_profile(M, int(natoms), X.shape[1], _d(X), _d(_f64(H, M)), _d(Fg), _d(s), _d(sl)),
            "profile")
     return s, sl
+
+
+def path_coord(X, natoms):
+    """Normalized path coordinate xi_k = s_k / s_{M-1} of a band X (M x dim; the first
+    natoms rows of 3 are atoms, taken modulo a rigid translation)."""
+    X = _f64(X)
+    M = X.shape[0]
+    X = X.reshape(M, -1)
+    xi = np.zeros(M)
+    _check(lib().orc_path_coord(M, int(natoms), X.shape[1], _d(X), _d(xi)), "path_coord")
+    return xi
+
+
+def fire_step(X, v, F, dt, alpha, n_pos, fresh, dtmax, maxstep, nmin=5, finc=1.1, fdec=0.5,
+              astart=0.1, fa=0.99, roww=3):
+    """One FIRE move of the band's moving images (the band step's own routine).
+    X, v, F: M x dim (images 0 and M-1 fixed).  Returns (X, v, dt, alpha, n_pos, fresh)."""
+    X = _f64(X).copy()
+    M = X.shape[0]
+    shape = X.shape
+    X = X.reshape(M, -1)
+    v = _f64(v).reshape(M, -1).copy()
+    F = _f64(F).reshape(M, -1)
+    st = FireState(float(dt), float(alpha), int(n_pos), int(fresh), 0, -1)
+    _check(lib().orc_fire_step(M, X.shape[1], int(roww), _d(X), _d(v), _d(F), ctypes.byref(st),
+                               float(dtmax), float(maxstep), int(nmin), float(finc), float(fdec),
+                               float(astart), float(fa)), "fire_step")
+    return X.reshape(shape), v.reshape(shape), st.dt, st.alpha, st.n_pos, st.fresh
 
 
 def spline_eval(s, H, slope, sq):

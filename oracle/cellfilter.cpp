@@ -6,7 +6,7 @@
 // Generalized forces (Eqs. (12), (14), (16), (17)):
 //     atoms:   F D^T
 //     lattice: D^-T V_eff D^-1 / c_f     (V_eff = V - P Omega I, enthalpy H = U + P Omega)
-// c_f is the cell factor (default: number of atoms).  The lattice force is the
+// c_f is the cell factor (default: |det h0|^(1/3) n^(1/6), cell_factor_of).  The lattice force is the
 // printed expression; the exact virtual-work conjugate of B is half of it, a
 // factor that changes the path metric but no fixed point.
 #include "internal.h"

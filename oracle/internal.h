@@ -46,6 +46,10 @@ int cell_gauge(const orc_params* p, const double* C, double* D);
 // over those rows (removes a rigid translation of the atoms; later rows untouched).
 void remove_translation(std::vector<double>& a, int natoms);
 
+// Arc lengths s_k of a band of M images (row-major M x dim) in the band's metric:
+// Euclidean lengths of consecutive differences with the atoms' rigid translation removed.
+void arc_lengths(int M, int natoms, int dim, const double* X, double* s);
+
 }  // namespace orc
 
 #endif

@@ -181,6 +181,44 @@ void fire_move(NebCore& c, double dtmax, double maxstep, int nmin, double finc, 
         for (int i = 0; i < c.dim; ++i) c.X[k][i] += scale * (st.dt * c.v[k][i]);
 }
 
+}  // namespace orc
+
+// One FIRE move of a band of M images (the endpoints, images 0 and M-1, stay fixed)
+// from the NEB forces F: the same routine the band step uses, exposed for pinning.
+extern "C" int orc_fire_step(int M, int dim, int roww, double* X, double* v, const double* F,
+                             orc_fire_state* st, double dtmax, double maxstep, int nmin, double finc,
+                             double fdec, double astart, double fa)
+{
+    if (M < 3 || dim <= 0 || roww <= 0 || dim % roww != 0) return ORC_EINVAL;
+    orc::NebCore c;
+    c.M = M;
+    c.dim = dim;
+    c.roww = roww;
+    c.X.assign(M, std::vector<double>(dim));
+    c.v.assign(M, std::vector<double>(dim));
+    c.Fneb.assign(M, std::vector<double>(dim));
+    for (int k = 0; k < M; ++k)
+        for (int i = 0; i < dim; ++i) {
+            c.X[k][i] = X[size_t(k) * dim + i];
+            c.v[k][i] = v[size_t(k) * dim + i];
+            c.Fneb[k][i] = F[size_t(k) * dim + i];
+        }
+    c.fire = {st->dt, st->alpha, st->n_pos, st->fresh};
+    orc::fire_move(c, dtmax, maxstep, nmin, finc, fdec, astart, fa);
+    for (int k = 0; k < M; ++k)
+        for (int i = 0; i < dim; ++i) {
+            X[size_t(k) * dim + i] = c.X[k][i];
+            v[size_t(k) * dim + i] = c.v[k][i];
+        }
+    st->dt = c.fire.dt;
+    st->alpha = c.fire.alpha;
+    st->n_pos = c.fire.n_pos;
+    st->fresh = c.fire.fresh;
+    return ORC_OK;
+}
+
+namespace orc {
+
 // ---- exact integer spacings for the refine decision ------------------------
 using u128 = unsigned __int128;
 
@@ -503,23 +541,9 @@ extern "C" int orc_band_energies(const orc_band* b, double* H, int cap, int* n_i
     *barrier = hmax - c.H[0];
     *ci_index = c.ci;
     if (path_coord) {
-        std::vector<double> seg(c.M - 1);
-        double tot = 0.0;
-        for (int k = 0; k + 1 < c.M; ++k) {
-            double s = 0.0;
-            for (int i = 0; i < c.dim; ++i) {
-                const double d = c.X[k + 1][i] - c.X[k][i];
-                s += d * d;
-            }
-            seg[k] = std::sqrt(s);
-            tot += seg[k];
-        }
-        double acc = 0.0;
-        path_coord[0] = 0.0;
-        for (int k = 1; k < c.M; ++k) {
-            acc += seg[k - 1];
-            path_coord[k] = tot > 0.0 ? acc / tot : 0.0;
-        }
+        std::vector<double> X(size_t(c.M) * c.dim);
+        for (int k = 0; k < c.M; ++k) std::copy(c.X[k].begin(), c.X[k].end(), X.begin() + size_t(k) * c.dim);
+        orc_path_coord(c.M, c.natoms, c.dim, X.data(), path_coord);
     }
     return ORC_OK;
 }

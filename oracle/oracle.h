@@ -183,7 +183,21 @@ int  orc_spline_max(int M, const double* s, const double* H, const double* slope
 int  orc_band_profile(orc_band* b, int n_samples, double* s, double* H, double* slope,
                       double* samples, double* barrier, double* xi_max);
 
+/* Normalized path coordinate of a band (M x dim row-major, the first natoms rows
+ * of 3 are atoms): xi_k = s_k / s_{M-1} with the arc length s of orc_profile
+ * (translation-free differences).  orc_band_energies reports the same. */
+int  orc_path_coord(int M, int natoms, int dim, const double* X, double* xi);
+
 /* ---------------- pieces exposed for pinning ----------------------------- */
+/* One band-global FIRE move (the band step's own routine) of the moving images
+ * 1..M-2 of X (M x dim, rows of roww entries) driven by the NEB forces F (M x dim):
+ * unless st->fresh, the power P = F.v decides between mixing v toward F (P > 0;
+ * dt and alpha grow only after more than nmin such steps in a row) and a reset
+ * (v = 0, alpha = astart, dt *= fdec, n_pos = 0); then v += dt F and X += dt v,
+ * the step scaled so that no row moves farther than maxstep.  X, v, st in/out. */
+int  orc_fire_step(int M, int dim, int roww, double* X, double* v, const double* F,
+                   orc_fire_state* st, double dtmax, double maxstep, int nmin, double finc,
+                   double fdec, double astart, double fa);
 /* Improved tangent coefficients: tau = a tau+ + b tau-. */
 void orc_tangent_coeffs(double Hm, double H0, double Hp, double* a, double* b);
 /* Refine decision on a band of M images, each of dimension dim (row-major M x dim).

@@ -45,18 +45,41 @@ double hermite(double H0, double H1, double m0, double m1, double d, double t)
 
 }  // namespace
 
+namespace orc {
+
+// Arc length along the band: s_0 = 0, s_{k+1} = s_k + |X_{k+1} - X_k| with the rigid
+// translation of the first natoms rows removed from each difference.
+void arc_lengths(int M, int natoms, int dim, const double* X, double* s)
+{
+    std::vector<double> d(dim);
+    s[0] = 0.0;
+    for (int k = 0; k + 1 < M; ++k) {
+        for (int i = 0; i < dim; ++i) d[i] = X[size_t(k + 1) * dim + i] - X[size_t(k) * dim + i];
+        remove_translation(d, natoms);
+        s[k + 1] = s[k] + std::sqrt(dotv(d, d));
+    }
+}
+
+}  // namespace orc
+
+// Normalized path coordinate xi_k = s_k / s_{M-1}: the axis against which the
+// transitions of Sec. III are drawn, in the same metric as the profile's arc length.
+extern "C" int orc_path_coord(int M, int natoms, int dim, const double* X, double* xi)
+{
+    if (M < 2 || dim <= 0 || natoms < 0 || 3 * natoms > dim) return ORC_EINVAL;
+    orc::arc_lengths(M, natoms, dim, X, xi);
+    const double S = xi[M - 1];
+    for (int k = 0; k < M; ++k) xi[k] = S > 0.0 ? xi[k] / S : 0.0;
+    return ORC_OK;
+}
+
 extern "C" int orc_profile(int M, int natoms, int dim, const double* X, const double* H, const double* Fg,
                            double* s, double* slope)
 {
     if (M < 2 || dim <= 0 || natoms < 0 || 3 * natoms > dim) return ORC_EINVAL;
     std::vector<double> tp(dim), tm(dim), tau(dim), F(dim);
     auto row = [&](int k) { return X + size_t(k) * dim; };
-    s[0] = 0.0;
-    for (int k = 0; k + 1 < M; ++k) {
-        for (int i = 0; i < dim; ++i) tp[i] = row(k + 1)[i] - row(k)[i];
-        orc::remove_translation(tp, natoms);
-        s[k + 1] = s[k] + std::sqrt(dotv(tp, tp));
-    }
+    orc::arc_lengths(M, natoms, dim, X, s);
     for (int k = 0; k < M; ++k) {
         for (int i = 0; i < dim; ++i) {
             tp[i] = k + 1 < M ? row(k + 1)[i] - row(k)[i] : 0.0;

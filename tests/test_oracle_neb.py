@@ -1,7 +1,9 @@
 """Pins of the oracle's NEB pieces: the improved tangent's branches, the
 projection's orthogonality (Eq. (1)), a climbing-image band on an analytic
-surface with a closed-form saddle, the symmetry of the vacancy-hop band, and
-brute-force cases of the adaptive-image decision."""
+surface with a closed-form saddle, the symmetry of the vacancy-hop band,
+brute-force cases of the adaptive-image decision, hand-worked FIRE moves, the
+path coordinate of known spacings, and a converged vacancy barrier that does not
+depend on the number of images."""
 import numpy as np
 import pytest
 
@@ -206,3 +208,180 @@ def test_refine_threshold_is_exact(orc):
         x = [0, a, a + 1, a + 2, a + 3]
         ins, dele, _ = orc.refine_decide(_band_1d(x), -1, 20, 5)
         assert ins == expect
+
+
+# ------------------------------------------------------------------ FIRE
+# Hand-built states of one FIRE move (Bitzek et al. 2006, the band-global form of
+# the band step): every expected value below was worked out by hand from the rules
+# (power test, mixing with the old alpha, growth only after more than N_min positive
+# steps, reset, v += dt F, X += dt v clamped by the largest row displacement).
+def _fire_band(moving_rows, M=3):
+    """X, v, F of M images whose moving images have the given rows (lists of 3-vectors)."""
+    rows = len(moving_rows[0])
+    X = np.zeros((M, rows, 3))
+    X[:, :, 0] = 10.0  # endpoints and images sit away from zero
+    return X
+
+
+def _one_image(v_rows, f_rows):
+    X = _fire_band([v_rows])
+    v = np.zeros_like(X)
+    F = np.zeros_like(X)
+    v[1] = v_rows
+    F[1] = f_rows
+    return X, v, F
+
+
+def test_fire_fresh_step_skips_the_power_test(orc):
+    # P = F.v = -2 < 0 would reset; right after creation or a refine it is not tested
+    X, v, F = _one_image([[1, 0, 0], [0, 0, 0]], [[-2, 0, 0], [0, 0, 0]])
+    X1, v1, dt, alpha, n_pos, fresh = orc.fire_step(X, v, F, 0.1, 0.07, 3, 1, dtmax=1.0, maxstep=1.0)
+    assert (dt, alpha, n_pos, fresh) == (0.1, 0.07, 3, 0)
+    assert v1[1, 0, 0] == pytest.approx(0.8, abs=1e-15)          # 1 + 0.1 * (-2)
+    assert X1[1, 0, 0] - X[1, 0, 0] == pytest.approx(0.08, abs=1e-14)
+    # endpoints never move
+    np.testing.assert_array_equal(X1[[0, 2]], X[[0, 2]])
+    np.testing.assert_array_equal(v1[[0, 2]], 0.0)
+
+
+@pytest.mark.parametrize("F_row", [[-2, 0, 0], [0, 2, 0]])
+def test_fire_non_positive_power_resets(orc, F_row):
+    # P < 0 and P = 0 exactly (F perpendicular to v): v = 0, alpha = alpha_start,
+    # dt halved, N_P = 0; then v = dt F with the halved dt
+    X, v, F = _one_image([[1, 0, 0], [0, 0, 0]], [F_row, [0, 0, 0]])
+    X1, v1, dt, alpha, n_pos, fresh = orc.fire_step(X, v, F, 0.1, 0.05, 3, 0, dtmax=1.0, maxstep=1.0,
+                                                    astart=0.1, fdec=0.5)
+    assert (dt, alpha, n_pos, fresh) == (0.05, 0.1, 0, 0)
+    expect_v = 0.05 * np.array(F_row, float)
+    np.testing.assert_allclose(v1[1, 0], expect_v, rtol=0, atol=1e-16)
+    np.testing.assert_allclose(X1[1, 0] - X[1, 0], 0.05 * expect_v, rtol=0, atol=1e-15)
+
+
+def test_fire_mixing_without_growth_up_to_nmin(orc):
+    # v = (0, 5, 0), F = (3, 4, 0): P = 20, |v| = |F| = 5; alpha 0.1 mixes to
+    # 0.9 (0, 5, 0) + 0.1 (3, 4, 0) = (0.3, 4.9, 0).  N_P = 5 = N_min: no growth yet.
+    # Then v += 0.1 F = (0.6, 5.3, 0) and X += 0.1 v = (0.06, 0.53, 0).
+    X, v, F = _one_image([[0, 5, 0], [0, 0, 0]], [[3, 4, 0], [0, 0, 0]])
+    X1, v1, dt, alpha, n_pos, fresh = orc.fire_step(X, v, F, 0.1, 0.1, 5, 0, dtmax=1.0, maxstep=1.0,
+                                                    nmin=5)
+    assert (dt, alpha, n_pos) == (0.1, 0.1, 6)
+    np.testing.assert_allclose(v1[1, 0], [0.6, 5.3, 0.0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(X1[1, 0] - X[1, 0], [0.06, 0.53, 0.0], rtol=0, atol=1e-14)
+
+
+def test_fire_growth_after_nmin_mixes_with_the_old_alpha(orc):
+    # N_P = 6 > N_min = 5: the mix still uses alpha = 0.1, giving (0.3, 4.9, 0); then
+    # dt = 0.1 * 1.1 = 0.11 and alpha = 0.1 * 0.99 = 0.099; v = (0.3, 4.9, 0) +
+    # 0.11 (3, 4, 0) = (0.63, 5.34, 0); X += 0.11 v = (0.0693, 0.5874, 0)
+    X, v, F = _one_image([[0, 5, 0], [0, 0, 0]], [[3, 4, 0], [0, 0, 0]])
+    X1, v1, dt, alpha, n_pos, fresh = orc.fire_step(X, v, F, 0.1, 0.1, 6, 0, dtmax=1.0, maxstep=1.0,
+                                                    nmin=5, finc=1.1, fa=0.99)
+    assert dt == pytest.approx(0.11, abs=1e-16) and alpha == pytest.approx(0.099, abs=1e-16)
+    assert n_pos == 7
+    np.testing.assert_allclose(v1[1, 0], [0.63, 5.34, 0.0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(X1[1, 0] - X[1, 0], [0.0693, 0.5874, 0.0], rtol=0, atol=1e-14)
+
+
+def test_fire_dt_is_capped_at_dtmax(orc):
+    X, v, F = _one_image([[0, 5, 0], [0, 0, 0]], [[3, 4, 0], [0, 0, 0]])
+    _, _, dt, alpha, n_pos, _ = orc.fire_step(X, v, F, 0.95, 0.1, 10, 0, dtmax=1.0, maxstep=10.0)
+    assert dt == 1.0 and n_pos == 11
+
+
+def test_fire_power_and_norms_are_band_global(orc):
+    # image 1: v = (3, 0, 0), F = (12, 0, 0), P_1 = 36; image 2: v = (0, 4, 0),
+    # F = (0, -5, 0), P_2 = -20.  The band's P = 16 > 0: both images are mixed (none is
+    # reset) with |v| = 5 and |F| = 13: v_mix = 0.9 v + 0.1 (5 / 13) F.
+    X = _fire_band([[[0, 0, 0]]], M=4)
+    v = np.zeros_like(X)
+    F = np.zeros_like(X)
+    v[1, 0] = [3, 0, 0]
+    F[1, 0] = [12, 0, 0]
+    v[2, 0] = [0, 4, 0]
+    F[2, 0] = [0, -5, 0]
+    X1, v1, dt, alpha, n_pos, _ = orc.fire_step(X, v, F, 0.01, 0.1, 0, 0, dtmax=1.0, maxstep=10.0)
+    assert (dt, alpha, n_pos) == (0.01, 0.1, 1)
+    np.testing.assert_allclose(v1[1, 0], [2.7 + 6.0 / 13.0 + 0.12, 0, 0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(v1[2, 0], [0, 3.6 - 2.5 / 13.0 - 0.05, 0], rtol=0, atol=1e-14)
+
+
+def test_fire_step_clamp_uses_the_largest_row(orc):
+    # fresh, v = 0, dt = 1: v = F and dr = F with rows of length 0.5, 0.1 and 0.2.
+    # maxstep 0.25 scales dr by 0.25 / 0.5 = 1/2 (a global norm, sqrt(0.3), would give
+    # 0.456; the largest component, 0.4, would give 0.625); v itself is not scaled.
+    rows = np.array([[0.3, 0.4, 0.0], [0.1, 0.0, 0.0], [0.0, 0.0, 0.2]])
+    X = _fire_band([rows])
+    v = np.zeros_like(X)
+    F = np.zeros_like(X)
+    F[1] = rows
+    X1, v1, dt, *_ = orc.fire_step(X, v, F, 1.0, 0.1, 0, 1, dtmax=1.0, maxstep=0.25)
+    np.testing.assert_allclose(X1[1] - X[1], [[0.15, 0.2, 0.0], [0.05, 0.0, 0.0], [0.0, 0.0, 0.1]],
+                               rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(v1[1], rows)
+    # below the limit nothing is scaled
+    X1, *_ = orc.fire_step(X, v, F, 1.0, 0.1, 0, 1, dtmax=1.0, maxstep=0.5000001)
+    np.testing.assert_allclose(X1[1] - X[1], rows, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------ path coordinate
+def test_path_coordinate_of_known_spacings(orc):
+    # four atoms and three cell rows; interval k moves the atoms by (+a, -a, +a, -a)
+    # along x (length 2a once the mean is removed) and cell entry (0, 0) by b, with
+    # a = 0.3 L_k and b = 0.8 L_k (length L_k), on top of a rigid translation of all
+    # atoms that the coordinate ignores.  L = (1, 2, 3): xi = (0, 1/6, 1/2, 1).
+    L = [1.0, 2.0, 3.0]
+    X = np.zeros((4, 7, 3))
+    X[0, :4] = [[0.1, 0.2, 0.3], [1.1, 0.2, 0.3], [0.1, 1.2, 0.3], [0.1, 0.2, 1.3]]
+    X[0, 4:] = 5.0 * np.eye(3)
+    sign = np.array([1.0, -1.0, 1.0, -1.0])
+    for k, Lk in enumerate(L):
+        X[k + 1] = X[k]
+        X[k + 1, :4, 0] += 0.3 * Lk * sign
+        X[k + 1, 4, 0] += 0.8 * Lk
+        X[k + 1, :4] += np.array([0.7, -0.4, 0.25]) * [1.0, 0.0, 2.0][k]  # rigid translation
+    xi = orc.path_coord(X, 4)
+    np.testing.assert_allclose(xi, [0.0, 1.0 / 6.0, 0.5, 1.0], rtol=0, atol=1e-14)
+    # the raw differences (translation included) would place the images elsewhere
+    raw = np.concatenate([[0.0], np.cumsum(np.linalg.norm(np.diff(X.reshape(4, -1), axis=0), axis=1))])
+    assert np.abs(raw / raw[-1] - xi).max() > 1e-2
+    # without atom rows (natoms = 0) the translation counts
+    np.testing.assert_allclose(orc.path_coord(X, 0), raw / raw[-1], rtol=0, atol=1e-14)
+
+
+def test_band_reports_the_profile_coordinate(orc):
+    # the band's readout uses the same coordinate as its energy profile
+    b = _lj_band(orc, M=6, steps=20, climb_after=10)
+    e = b.energies()
+    X = b.get_state()["X"]
+    np.testing.assert_array_equal(e["xi"], orc.path_coord(X, b.n))
+    prof = b.profile()
+    np.testing.assert_allclose(e["xi"], prof["s"] / prof["s"][-1], rtol=0, atol=1e-15)
+    assert e["xi"][0] == 0.0 and e["xi"][-1] == 1.0 and np.all(np.diff(e["xi"]) > 0)
+
+
+# ------------------------------------------- barrier independent of the image count
+@pytest.mark.slow
+def test_vacancy_barrier_is_independent_of_the_image_count(orc):
+    # The 255-atom LJ vacancy hop (4x4x4 FCC cells) from relaxed endpoints: with the
+    # climbing image converged (fmax < 1e-3 eV/A) the barrier is the saddle's enthalpy
+    # minus the initial minimum's, whatever the number of images.  The climbing image
+    # sits on the symmetric midpoint of the hop.
+    w = W.lj_fcc_hop_255()
+    p0 = orc.default_params(orc.LJ)
+    A = orc.relax(p0, w["pos_init"], w["cell_init"], 20000, 1e-6)
+    B = orc.relax(p0, w["pos_final"], w["cell_final"], 20000, 1e-6)
+    assert A[3] < 1e-6 and B[3] < 1e-6
+    # the two relaxed endpoints are images of each other under the hop's symmetry
+    assert orc.evaluate(p0, A[0], A[1])[0] == pytest.approx(orc.evaluate(p0, B[0], B[1])[0], abs=1e-9)
+    barriers = []
+    for M in (7, 9, 11):
+        p = orc.default_params(orc.LJ, n_images=M, max_images=M, climb_after=50, k_spring=1.0,
+                               fire_dt0=0.005)
+        b = orc.Band(p, A[0], A[1], B[0], B[1])
+        d, fmax, conv = b.step(20000, 1e-3)
+        assert conv
+        e = b.energies()
+        assert e["ci"] == (M - 1) // 2
+        barriers.append(e["barrier"])
+    assert max(barriers) - min(barriers) <= 1e-3, barriers
+    assert 5.0 < barriers[0] < 6.5
