@@ -134,16 +134,22 @@ enum {
 
 typedef struct cfneb_band cfneb_band;
 
-/* Fill *out with the defaults for a potential: LJ eps = sigma = 1, rc = 2.5,
- * shifted; Tersoff 1988 carbon (R = 1.8, S = 2.1); 7 images, k = 1, climbing after
- * 50 steps, rotation-free filter, c_f = n_atoms; FIRE dt0 0.005 (LJ) / 0.05
- * (Tersoff), dtmax = 10 dt0, maxstep 0.1, Nmin 5, finc 1.1, fdec 0.5, alpha 0.1,
- * f_alpha 0.99; refine off with thresholds 9/4 and 1/4; nbr_cap 128 (LJ) / 16;
- * nbr_skin 0.3. */
+/* Fill *out with the defaults for a potential (the short-range potentials of the
+ * per-atom form of Sec. II.B, Eq. (4); the band, filter and optimizer settings of
+ * Secs. II.A, II.C and III, where the paper leaves values open): LJ eps = sigma = 1,
+ * rc = 2.5, shifted; Tersoff 1988 carbon (R = 1.8, S = 2.1); 7 images, k = 1,
+ * climbing after 50 steps, rotation-free filter (Eq. (17)), c_f = 0 (that is,
+ * |det h0|^(1/3) n_atoms^(1/6)); FIRE dt0 0.005 (LJ) / 0.05 (Tersoff), dtmax =
+ * 10 dt0, maxstep 0.1, Nmin 5, finc 1.1, fdec 0.5, alpha 0.1, f_alpha 0.99; refine
+ * off with thresholds 9/4 and 1/4; nbr_cap 128 (LJ) / 16; nbr_skin 0.3.
+ * CFNEB_EINVAL for an unknown potential or NULL out. */
 int cfneb_params_default(int potential, cfneb_params* out);
 
 /* Device workspace bytes for a band of n_atoms atoms and up to max_images images
- * (max_images <= 0: p->max_images).  This is also the band's HBM footprint. */
+ * (max_images <= 0: p->max_images), the storage of the images, lists and scratch
+ * that one band step of Secs. II and III needs.  This is also the band's HBM
+ * footprint (what a request loop admits by).  CFNEB_EINVAL for bad parameters,
+ * n_atoms outside [1, 2^20) or max_images outside [3, 64]. */
 int cfneb_band_bytes(const cfneb_params* p, int64_t n_atoms, int max_images, size_t* bytes);
 
 /* Build a band (Secs. II.C, III): h0 = cell_init is the reference cell of every
@@ -187,10 +193,16 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
  * the new or removed image, -1 for none. */
 int cfneb_refine(cfneb_band* b, int* inserted_at, int* deleted_at);
 
-/* Readout: H[k] for the n_images current images (cap >= n_images), the barrier
- * max_k H_k - H_0, the climbing image (-1 if none) and the path coordinate
- * xi_k = sum_{j<k} |X_{j+1} - X_j| / sum_j |X_{j+1} - X_j| (path_coord may be NULL).
- * A freshly inserted image reports the mean of its neighbours until evaluated. */
+/* Readout (Sec. III, which reports each transition as image enthalpies against a
+ * normalized path coordinate, the barrier being the highest image minus the
+ * initial state): H[k] for the n_images current images (cap >= n_images), the
+ * barrier max_k H_k - H_0, the climbing image (-1 if none) and the path coordinate
+ * xi_k = s_k / s_{M-1}, s_0 = 0, s_{k+1} = s_k + |X_{k+1} - X_k| with the atoms'
+ * rigid translation removed from each difference (the arc length of cfneb_profile;
+ * path_coord may be NULL).  H values are those of the last evaluation; a freshly
+ * inserted image reports the mean of its neighbours until evaluated.  Launches two
+ * small kernels on the band's stream and synchronises it.  Errors: CFNEB_EINVAL for
+ * a NULL band or cap < n_images (H given). */
 int cfneb_energies(const cfneb_band* b, double* H, int cap, int* n_images, double* barrier,
                    int* ci_index, double* path_coord);
 
@@ -220,8 +232,11 @@ int cfneb_energies(const cfneb_band* b, double* H, int cap, int* n_images, doubl
 int cfneb_profile(cfneb_band* b, int n_samples, double* s, double* H, double* slope, int cap, int* n_images,
                   double* samples, double* barrier, double* xi_max);
 
-/* Cartesian positions (n_atoms x 3) and cell (3x3) of current image k:
- * h = h0 D, R = R~ D with D = symsqrt(B). */
+/* Cartesian positions (n_atoms x 3) and cell (3x3) of current image k, mapped back
+ * from the filter's coordinates (Sec. II.C, Eqs. (10)-(11), (15)): h = h0 D and
+ * R = R~ D with D = symsqrt(B) (rotation-free filter) or the stored D (D-variant).
+ * Host outputs; CFNEB_EINVAL for k outside [0, n_images).  Synchronises the
+ * band's stream. */
 int cfneb_get_image(const cfneb_band* b, int k, double* pos, double* cell);
 
 /* Relax one structure with the cell filter (Sec. II.C, which introduces the filter
@@ -240,12 +255,17 @@ int cfneb_relax(const cfneb_params* p, int64_t n_atoms, const int32_t* types, do
                 int* steps_done, double* fmax, int* converged);
 
 /* Checkpoint: generalized coordinates X and velocities v of the n_images images,
- * each (n_atoms + 3) x 3 row-major (rows of R~, then rows of c_f B), into arrays
- * of cap_images images; FIRE state. */
+ * each (n_atoms + 3) x 3 row-major (rows of R~, then rows of c_f B: the coordinates
+ * of Sec. II.C, Eq. (15)), into host arrays of cap_images images; FIRE state.  X and
+ * v may be NULL (then only n_images and st are written); CFNEB_EINVAL if
+ * cap_images < n_images with X or v given. */
 int cfneb_get_state(const cfneb_band* b, double* X, double* v, int cap_images, int* n_images,
                     cfneb_fire_state* st);
 
-/* Restore a checkpoint (same layout); every image is evaluated again.  v may be NULL. */
+/* Restore a checkpoint (same layout as cfneb_get_state, Sec. II.C coordinates);
+ * every image is evaluated again.  v may be NULL (zero velocities).  CFNEB_EINVAL
+ * for n_images outside [3, max_images]; an evaluation error leaves the band failed
+ * with that code. */
 int cfneb_set_state(cfneb_band* b, int n_images, const double* X, const double* v,
                     const cfneb_fire_state* st);
 
@@ -257,8 +277,9 @@ int cfneb_set_state(cfneb_band* b, int n_images, const double* X, const double* 
 int cfneb_image_data(const cfneb_band* b, int k, double* E, double* H, double* V, double* F,
                      double* Fg, double* Fneb, double* R, double* h);
 
-/* Keep the NEB force of every moving image in device memory at each step so
- * that cfneb_image_data can return it (costs one extra store per row). */
+/* Keep the NEB force of Eq. (1) of every moving image in device memory at each
+ * step so that cfneb_image_data can return it (costs one extra store per row).
+ * on: 0 or 1. */
 int cfneb_record_neb_force(cfneb_band* b, int on);
 
 /* Neighbour set of image k from its last evaluation: cnt[i] entries per atom,
@@ -274,6 +295,8 @@ int cfneb_record_neb_force(cfneb_band* b, int on);
 int cfneb_neighbours(const cfneb_band* b, int k, int32_t* cnt, int32_t* ent, int64_t cap,
                      int64_t* total);
 
+/* Release the handle (the caller's workspace and stream are untouched; the band's
+ * stream is synchronised first).  Not for a band attached to a batch. */
 int cfneb_destroy(cfneb_band* b);
 
 /* ---------------------------------------------------------------- batches
@@ -282,24 +305,62 @@ int cfneb_destroy(cfneb_band* b);
  * live bands, whatever their atom and image counts; the step is captured once in a
  * hipGraph, and attaching or detaching a band only rewrites a device table.  Each
  * band's result does not depend on its batch-mates (no shared reductions).
- * Ownership: the caller owns the batch workspace (cfneb_batch_bytes) and the bands;
- * a band stays owned by its creator and must outlive its membership.  While
- * attached, a band must not be stepped on its own. */
+ * Ownership: the caller owns the batch workspace (cfneb_batch_bytes) and every band
+ * it attaches (cfneb_batch_attach), which must outlive its membership; a band made
+ * with cfneb_batch_add belongs to the batch until removed.  While in a batch, a
+ * band must not be stepped on its own. */
 typedef struct cfneb_batch cfneb_batch;
 
-/* Device bytes of a batch table for up to max_bands bands (<= 128). */
+/* Device bytes of a batch table for up to max_bands bands (<= 128): a descriptor
+ * per band and the work plan of the persistent launches.  Bands keep their own
+ * workspaces.  CFNEB_EINVAL for max_bands outside [1, 128]. */
 int cfneb_batch_bytes(int max_bands, size_t* bytes);
 
-/* hip_stream: the stream every batch launch goes to (NULL: null stream). */
+/* A batch of up to max_bands independent bands, each relaxed by the band step of
+ * Secs. II and III.  workspace: >= cfneb_batch_bytes device bytes, 256-byte
+ * aligned, owned by the caller.  hip_stream: the stream every batch launch goes to
+ * (NULL: null stream).  CFNEB_EINVAL / CFNEB_ENOMEM / CFNEB_EHIP on bad arguments, a
+ * small workspace or a failing HIP call. */
 int cfneb_batch_create(int max_bands, void* workspace, size_t workspace_bytes, void* hip_stream,
                        cfneb_batch** out);
 
-/* Add a band (created with cfneb_create_band); *slot receives its table index.
- * Returns CFNEB_ECAPACITY when the table is full. */
+/* Add a band (created with cfneb_create_band; it stays the caller's); *slot
+ * receives its table index.  Synchronises the band's stream.  Returns
+ * CFNEB_ECAPACITY when the table is full, CFNEB_EINVAL if the band is already in
+ * the table. */
 int cfneb_batch_attach(cfneb_batch* batch, cfneb_band* band, int* slot);
 
-/* Remove the band in table slot `slot` (the band itself is untouched). */
+/* Remove the band in table slot `slot` (the band itself is untouched).  A band that
+ * cfneb_batch_add made passes to the caller here (take its handle from
+ * cfneb_batch_band first; destroy it with cfneb_destroy). */
 int cfneb_batch_detach(cfneb_batch* batch, int slot);
+
+/* Create a band (exactly as cfneb_create_band, Secs. II.C and III; the band's device
+ * work goes to the batch's stream) and attach it in one call.  The band belongs to
+ * the batch: cfneb_batch_remove or cfneb_batch_destroy destroys it.  The caller
+ * still owns `workspace` (>= cfneb_band_bytes(p, n_atoms, 0) bytes, 256-byte
+ * aligned), which must stay allocated until the band is removed.  *slot receives
+ * the table index.  Errors: those of cfneb_create_band (nothing is attached), or
+ * CFNEB_ECAPACITY when the table is full (nothing is created). */
+int cfneb_batch_add(cfneb_batch* batch, const cfneb_params* p, int64_t n_atoms, const int32_t* types,
+                    const double* pos_init, const double* cell_init, const double* pos_final,
+                    const double* cell_final, void* workspace, size_t workspace_bytes, int* slot);
+
+/* Detach the band in `slot` and, if cfneb_batch_add made it, destroy it (its
+ * workspace is then free for the caller).  A band attached with cfneb_batch_attach
+ * is only detached.  CFNEB_EINVAL for an empty slot. */
+int cfneb_batch_remove(cfneb_batch* batch, int slot);
+
+/* Handle of the band in `slot` (NULL for an empty slot), for the per-band calls
+ * (cfneb_energies, cfneb_profile, cfneb_get_image, cfneb_get_state ...) between
+ * batch steps.  A band the batch owns must not be destroyed through it. */
+cfneb_band* cfneb_batch_band(cfneb_batch* batch, int slot);
+
+/* Readout of the band in `slot` after batch steps: the outputs of cfneb_energies
+ * (Sec. III: image enthalpies, barrier = highest image minus the initial state,
+ * climbing image, normalized path coordinate).  CFNEB_EINVAL for an empty slot. */
+int cfneb_batch_energies(cfneb_batch* batch, int slot, double* H, int cap, int* n_images, double* barrier,
+                         int* ci_index, double* path_coord);
 
 /* Up to max_steps steps of every attached band with the same f_tol; a band that
  * converges or fails stops moving while the others go on, and the call returns
@@ -309,9 +370,14 @@ int cfneb_batch_detach(cfneb_batch* batch, int slot);
 int cfneb_batch_step(cfneb_batch* batch, int max_steps, double f_tol, int* steps_done,
                      uint8_t* converged, int* errors);
 
+/* Release the batch: bands made by cfneb_batch_add are destroyed, attached bands
+ * are left as they are (no longer in a table); the workspace stays the caller's. */
 int cfneb_batch_destroy(cfneb_batch* batch);
 
+/* Static text of a CFNEB_E* code. */
 const char* cfneb_strerror(int code);
+/* Text of the band's last failure ("" if none; "no band" for NULL); valid until
+ * the band's next call. */
 const char* cfneb_last_error(const cfneb_band* b);
 
 #ifdef __cplusplus

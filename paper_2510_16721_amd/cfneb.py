@@ -22,10 +22,12 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECELL", -5: "ENE
 # exported entry points declared in include/cfneb.h
 SYMBOLS = ["cfneb_params_default", "cfneb_band_bytes", "cfneb_create_band", "cfneb_step",
            "cfneb_step_profiled",
-           "cfneb_refine", "cfneb_energies", "cfneb_profile", "cfneb_get_image", "cfneb_relax", "cfneb_get_state",
+           "cfneb_refine", "cfneb_energies", "cfneb_profile", "cfneb_get_image", "cfneb_relax",
+           "cfneb_get_state",
            "cfneb_set_state", "cfneb_image_data", "cfneb_record_neb_force", "cfneb_neighbours",
            "cfneb_destroy", "cfneb_strerror", "cfneb_last_error", "cfneb_batch_bytes",
-           "cfneb_batch_create", "cfneb_batch_attach", "cfneb_batch_detach", "cfneb_batch_step",
+           "cfneb_batch_create", "cfneb_batch_attach", "cfneb_batch_detach", "cfneb_batch_add",
+           "cfneb_batch_remove", "cfneb_batch_band", "cfneb_batch_energies", "cfneb_batch_step",
            "cfneb_batch_destroy"]
 
 
@@ -117,6 +119,13 @@ def _declare(L):
     L.cfneb_batch_create.argtypes = [c_int, c_void, c_size, c_void, ctypes.POINTER(c_void)]
     L.cfneb_batch_attach.argtypes = [c_void, c_void, ctypes.POINTER(c_int)]
     L.cfneb_batch_detach.argtypes = [c_void, c_int]
+    L.cfneb_batch_add.argtypes = [c_void, ctypes.POINTER(Params), c_int64, _ip, _dp, _dp, _dp, _dp,
+                                  c_void, c_size, ctypes.POINTER(c_int)]
+    L.cfneb_batch_remove.argtypes = [c_void, c_int]
+    L.cfneb_batch_band.argtypes = [c_void, c_int]
+    L.cfneb_batch_band.restype = c_void
+    L.cfneb_batch_energies.argtypes = [c_void, c_int, _dp, c_int, ctypes.POINTER(c_int), _dp,
+                                       ctypes.POINTER(c_int), _dp]
     L.cfneb_batch_step.argtypes = [c_void, c_int, c_double, _ip, ctypes.POINTER(ctypes.c_uint8), _ip]
     L.cfneb_batch_destroy.argtypes = [c_void]
 
@@ -349,6 +358,21 @@ class Band:
         return cnt, [ent[off[i]:off[i + 1]].copy() for i in range(n)]
 
 
+class _OwnedBand(Band):
+    """Per-band calls on a band that a batch made (cfneb_batch_add): the batch destroys it."""
+
+    def __init__(self, handle, p, n, workspace, stream):
+        self.p = p
+        self.n = n
+        self._ws = workspace
+        self._ws_bytes = workspace.numel()
+        self.stream = stream
+        self._h = ctypes.c_void_p(handle)
+
+    def close(self):
+        self._h = None  # owned by the batch
+
+
 def batch_bytes(max_bands):
     out = ctypes.c_size_t()
     rc = lib().cfneb_batch_bytes(int(max_bands), ctypes.byref(out))
@@ -390,6 +414,51 @@ class Batch:
             raise CfnebError(rc, "cfneb_batch_detach")
         self.bands[slot] = None
 
+    def add(self, p, pos_init, cell_init, pos_final, cell_final, workspace=None):
+        """Create a band owned by the batch (cfneb_batch_add); returns its slot.  The
+        workspace tensor is kept alive until the band is removed."""
+        import torch
+        pos_init = _f64(pos_init, (-1, 3))
+        n = pos_init.shape[0]
+        if workspace is None:
+            workspace = torch.empty(band_bytes(p, n) + 256, dtype=torch.uint8, device="cuda")
+        base = workspace.data_ptr()
+        ptr = (base + 255) // 256 * 256
+        slot = ctypes.c_int()
+        rc = lib().cfneb_batch_add(self._h, ctypes.byref(p), n, None, _d(pos_init), _d(_f64(cell_init, 9)),
+                                   _d(_f64(pos_final, (-1, 3))), _d(_f64(cell_final, 9)),
+                                   ctypes.c_void_p(ptr), workspace.numel() - (ptr - base),
+                                   ctypes.byref(slot))
+        if rc != 0:
+            raise CfnebError(rc, "cfneb_batch_add")
+        self.bands[slot.value] = _OwnedBand(lib().cfneb_batch_band(self._h, slot.value), p, n, workspace,
+                                            self.stream)
+        return slot.value
+
+    def remove(self, slot):
+        """Detach the band in `slot`; a band made by add() is destroyed."""
+        rc = lib().cfneb_batch_remove(self._h, int(slot))
+        if rc != 0:
+            raise CfnebError(rc, "cfneb_batch_remove")
+        b = self.bands[slot]
+        if isinstance(b, _OwnedBand):
+            b._h = None  # destroyed by the library
+        self.bands[slot] = None
+
+    def energies(self, slot):
+        """cfneb_batch_energies: H, barrier, climbing image and path coordinate of a slot."""
+        cap = 64
+        H = np.zeros(cap)
+        xi = np.zeros(cap)
+        M = ctypes.c_int()
+        bar = ctypes.c_double()
+        ci = ctypes.c_int()
+        rc = lib().cfneb_batch_energies(self._h, int(slot), _d(H), cap, ctypes.byref(M), ctypes.byref(bar),
+                                        ctypes.byref(ci), _d(xi))
+        if rc != 0:
+            raise CfnebError(rc, "cfneb_batch_energies")
+        return dict(H=H[:M.value].copy(), barrier=bar.value, ci=ci.value, xi=xi[:M.value].copy())
+
     def step(self, max_steps, f_tol=0.0):
         """Returns (steps per slot, converged per slot, error code per slot)."""
         steps = np.zeros(self.cap, dtype=np.int32)
@@ -406,6 +475,9 @@ class Batch:
         if getattr(self, "_h", None):
             lib().cfneb_batch_destroy(self._h)
             self._h = None
+            for b in self.bands:
+                if isinstance(b, _OwnedBand):
+                    b._h = None  # destroyed with the batch
 
     def __del__(self):
         try:

@@ -16,6 +16,24 @@ __global__ void __launch_bounds__(CFNEB_MAX_BANDS) k_plan(BatchDev bd, int all_i
     plan_block(bd, all_images, ignore_stop);
 }
 
+// Zero `bytes` bytes (a multiple of 16, 16-byte aligned) with vector stores: clears a
+// workspace without a memset.
+__global__ void k_fill_zero(uint4* p, size_t n16)
+{
+    const uint4 z = {0u, 0u, 0u, 0u};
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += size_t(gridDim.x) * blockDim.x)
+        p[i] = z;
+}
+
+void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_fill_zero<<<unsigned(blocks), 256, 0, s>>>(static_cast<uint4*>(ptr), n16);
+}
+
 // Per-band status for the host: done, err, steps of the call, M (4 ints per band).
 __global__ void k_summary(BatchDev bd, int* out)
 {

@@ -663,6 +663,8 @@ __device__ inline void image_reduce_item(const BandDev& b, BandState* st, int sl
 }
 
 
+// Zero a workspace of `bytes` bytes (a multiple of 256 at a 256-byte aligned address).
+void launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 void launch_init_endpoints(const BandDev& b, hipStream_t s);
 void launch_init_images(const BandDev& b, int M, hipStream_t s);
 void launch_init_state(const BandDev& b, int M, hipStream_t s);

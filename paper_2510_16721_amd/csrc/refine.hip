@@ -158,7 +158,7 @@ __device__ void dist_item(const BandDev& b, BandState* st, int k, int tile)
     __syncthreads();
 }
 
-// mode 0: only when the step set refine_due; mode 1: always (readout / explicit call)
+// mode 0: only when the step set refine_due; mode 1: always (explicit call)
 __global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BatchDev bd, int mode)
 {
     if (mode == 0 && *refine_flag(bd) == 0) return;  // no band is due this step
@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_dist(BatchDev bd, int mod
     }
 }
 
-// mode 0 / 1: decide and apply to the slot table; mode 2: spacings only (readout).
+// mode 0: step-end check of the bands due; mode 1: forced decision.  Both apply the
+// decision to the slot table.
 __device__ void decide_item(const BandDev& b, BandState* st, int mode)
 {
     __shared__ U128 d2[CFNEB_MAX_IMAGES];
@@ -194,7 +195,7 @@ __device__ void decide_item(const BandDev& b, BandState* st, int mode)
         }
     }
     __syncthreads();
-    if (t == 0 && mode != 2) {
+    if (t == 0) {
         st->ins = -1;
         st->del = -1;
         st->changed = 0;
@@ -308,31 +309,74 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_refine_apply(BatchDev bd, int mo
     }
 }
 
-// H in logical order, barrier, path coordinate (from the exact spacings).
-__global__ void k_readout(BatchDev bd)
+// Readout partials of interval k, one 256-row tile: the sum of d^2 over every row and
+// the atom-row sums of each component of d = X_{k+1} - X_k (fixed-order block sums),
+// at dotpart[(k * ntR + tile) * 4 ...] (the band dots' partials are free outside a step).
+__global__ void __launch_bounds__(CFNEB_TILE) k_readout_dist(BatchDev bd)
+{
+    __shared__ double lds[(CFNEB_TILE / 64) * 4];
+    ItemLoop loop(bd, KIND_IVAL, 0);
+    Item it;
+    while (loop.next(it)) {
+        const BandDev& b = bd.bands[it.band];
+        const BandState* st = b.st;
+        const int r = it.tile * CFNEB_TILE + threadIdx.x;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (r < b.N + 3) {
+            const double* Xa = Xs(b, st->slot[it.image]);
+            const double* Xb = Xs(b, st->slot[it.image + 1]);
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * b.ld + r;
+                const double d = Xb[o] - Xa[o];
+                v[0] += d * d;
+                if (r < b.N) v[1 + c] = d;
+            }
+        }
+        block_sum<4>(v, lds);
+        if (threadIdx.x == 0) {
+            double* out = b.dotpart + (size_t(it.image) * b.ntR + it.tile) * 4;
+            for (int q = 0; q < 4; ++q) out[q] = v[q];
+        }
+    }
+}
+
+// H in logical order, barrier, and the path coordinate xi_k = s_k / s_{M-1}, where
+// s is the arc length of the translation-free image differences (the metric of the
+// band's springs, tangent and energy profile): |d - mean_atoms(d)|^2 =
+// sum d^2 - |sum_atoms d|^2 / N.  One wave per band; lanes sum the tiles of an
+// interval in a fixed order.
+__global__ void __launch_bounds__(64) k_readout(BatchDev bd)
 {
     ItemLoop loop(bd, KIND_BAND, 0);
     Item it;
     while (loop.next(it)) {
-        if (threadIdx.x != 0) continue;
         const BandDev& b = bd.bands[it.band];
         BandState* st = b.st;
         const int M = st->M;
-        double hmax = b.scal[st->slot[0]].H;
-        for (int k = 0; k < M; ++k) {
-            const double h = b.scal[st->slot[k]].H;
-            st->Hlog[k] = h;
-            hmax = fmax(hmax, h);
+        const int lane = threadIdx.x;
+        if (lane == 0) {
+            double hmax = b.scal[st->slot[0]].H;
+            for (int k = 0; k < M; ++k) {
+                const double h = b.scal[st->slot[k]].H;
+                st->Hlog[k] = h;
+                hmax = fmax(hmax, h);
+            }
+            st->barrier = hmax - st->Hlog[0];
+            st->xi[0] = 0.0;
         }
-        st->barrier = hmax - st->Hlog[0];
-        double tot = 0.0;
-        for (int k = 0; k < M - 1; ++k) tot += sqrt(st->d2[k]);
         double acc = 0.0;
-        st->xi[0] = 0.0;
-        for (int k = 1; k < M; ++k) {
-            acc += sqrt(st->d2[k - 1]);
-            st->xi[k] = tot > 0.0 ? acc / tot : 0.0;
+        for (int k = 0; k < M - 1; ++k) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            const double* part = b.dotpart + size_t(k) * b.ntR * 4;
+            for (int t = lane; t < b.ntR; t += 64)
+                for (int q = 0; q < 4; ++q) v[q] += part[size_t(t) * 4 + q];
+            for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+            const double tr = (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / double(b.N);
+            acc += sqrt(fmax(v[0] - tr, 0.0));
+            if (lane == 0) st->xi[k + 1] = acc;
         }
+        if (lane == 0)
+            for (int k = 1; k < M; ++k) st->xi[k] = acc > 0.0 ? st->xi[k] / acc : 0.0;
     }
 }
 
@@ -349,8 +393,7 @@ void launch_refine(const Launch& L, int forced, hipStream_t s)
 // Readout after launch_plan(..., ignore_stop = 1).
 void launch_readout(const Launch& L, hipStream_t s)
 {
-    k_refine_dist<<<L.g[KIND_IVAL], CFNEB_TILE, 0, s>>>(L.bd, 1);
-    k_refine_decide<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd, 2);
+    k_readout_dist<<<L.g[KIND_IVAL], CFNEB_TILE, 0, s>>>(L.bd);
     k_readout<<<L.g[KIND_BAND], 64, 0, s>>>(L.bd);
 }
 

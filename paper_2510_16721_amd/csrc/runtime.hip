@@ -535,6 +535,39 @@ int cfneb_band_bytes(const cfneb_params* p, int64_t n_atoms, int max_images, siz
 
 namespace {
 
+// Device set-up of a band whose handle, host state and layout are in place: clear
+// the workspace, upload the endpoints, build and evaluate every image.  A fill kernel
+// clears the workspace when zero_kernel is set (no memset node if a caller captures).
+int init_band(cfneb_band* b, const double* pos_init, const double* cell_init, const double* pos_final,
+              const double* cell_final, void* workspace, int zero_kernel)
+{
+    const size_t N = size_t(b->L.N);
+    if (zero_kernel)
+        launch_fill_zero(workspace, b->L.total, b->stream);
+    else
+        HIP_TRY(b, hipMemsetAsync(workspace, 0, b->L.total, b->stream));
+    // upload the endpoints to the staging area: RA | RB | hA | hB
+    double* stg = b->d.staging;
+    HIP_TRY(b, hipMemcpyAsync(stg, pos_init, 3 * N * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(b, hipMemcpyAsync(stg + 3 * N, pos_final, 3 * N * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(b, hipMemcpyAsync(stg + 6 * N, cell_init, 9 * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(b, hipMemcpyAsync(stg + 6 * N + 9, cell_final, 9 * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    static const int one = 1;
+    HIP_TRY(b, hipMemcpyAsync(const_cast<BandDev*>(b->launch.bd.bands), &b->d, sizeof(BandDev),
+                              hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(b, hipMemcpyAsync(const_cast<int*>(b->launch.bd.live), &one, sizeof(int), hipMemcpyHostToDevice,
+                              b->stream));
+    launch_init_endpoints(b->d, b->stream);
+    launch_init_images(b->d, b->p.n_images, b->stream);
+    launch_init_state(b->d, b->p.n_images, b->stream);
+    launch_evaluate(b->launch, 1, b->stream);
+    int rc = check_kernels(b, "create");
+    if (rc == CFNEB_OK) rc = read_state(b);
+    if (rc != CFNEB_OK) return rc;
+    if (b->host_state->err != 0) return b->host_state->err;
+    return CFNEB_OK;
+}
+
 int create_impl(const cfneb_params* p, int64_t n_atoms, const double* pos_init, const double* cell_init,
                 const double* pos_final, const double* cell_final, void* workspace,
                 size_t workspace_bytes, void* hip_stream, int relax, cfneb_band** out)
@@ -568,33 +601,23 @@ int create_impl(const cfneb_params* p, int64_t n_atoms, const double* pos_init, 
         return bail(CFNEB_EHIP);
     if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(CFNEB_EHIP);
-    const size_t N = size_t(n_atoms);
-    if (hipMemsetAsync(workspace, 0, b->L.total, b->stream) != hipSuccess) return bail(CFNEB_EHIP);
-    // upload the endpoints to the staging area: RA | RB | hA | hB
-    std::vector<double> stage(6 * N + 18);
-    std::memcpy(stage.data(), pos_init, 3 * N * sizeof(double));
-    std::memcpy(stage.data() + 3 * N, pos_final, 3 * N * sizeof(double));
-    std::memcpy(stage.data() + 6 * N, cell_init, 9 * sizeof(double));
-    std::memcpy(stage.data() + 6 * N + 9, cell_final, 9 * sizeof(double));
-    if (hipMemcpyAsync(b->d.staging, stage.data(), stage.size() * sizeof(double), hipMemcpyHostToDevice,
-                       b->stream) != hipSuccess)
-        return bail(CFNEB_EHIP);
-    static const int one = 1;
-    if (hipMemcpyAsync(const_cast<BandDev*>(b->launch.bd.bands), &b->d, sizeof(BandDev), hipMemcpyHostToDevice,
-                       b->stream) != hipSuccess ||
-        hipMemcpyAsync(const_cast<int*>(b->launch.bd.live), &one, sizeof(int), hipMemcpyHostToDevice,
-                       b->stream) != hipSuccess)
-        return bail(CFNEB_EHIP);
-    launch_init_endpoints(b->d, b->stream);
-    launch_init_images(b->d, p->n_images, b->stream);
-    launch_init_state(b->d, p->n_images, b->stream);
-    launch_evaluate(b->launch, 1, b->stream);
-    if (hipGetLastError() != hipSuccess) return bail(CFNEB_EHIP);
-    rc = read_state(b);
+    rc = init_band(b, pos_init, cell_init, pos_final, cell_final, workspace, 0);
     if (rc != CFNEB_OK) return bail(rc);
-    if (b->host_state->err != 0) return bail(b->host_state->err);
     *out = b;
     return CFNEB_OK;
+}
+
+// One moving image between two fixed copies of itself, no projection, no climbing
+// image, no refinement: FIRE on (R~, c_f B) down the generalized force.
+cfneb_params relax_params(const cfneb_params* p)
+{
+    cfneb_params q = *p;
+    q.n_images = 3;
+    q.max_images = 3;
+    q.min_images = 3;
+    q.climb_after = -1;
+    q.refine_every = 0;
+    return q;
 }
 
 }  // namespace
@@ -617,14 +640,7 @@ int cfneb_relax(const cfneb_params* p, int64_t n_atoms, const int32_t* types, do
 {
     (void)types;
     if (!p || !pos || !cell || max_steps < 0) return CFNEB_EINVAL;
-    // one moving image between two fixed copies of itself, no projection, no
-    // climbing image, no refinement: FIRE on (R~, c_f B) down the generalized force
-    cfneb_params q = *p;
-    q.n_images = 3;
-    q.max_images = 3;
-    q.min_images = 3;
-    q.climb_after = -1;
-    q.refine_every = 0;
+    const cfneb_params q = relax_params(p);
     cfneb_band* b = nullptr;
     int rc = create_impl(&q, n_atoms, pos, cell, pos, cell, workspace, workspace_bytes, hip_stream, 1, &b);
     if (rc != CFNEB_OK) return rc;
@@ -1044,6 +1060,7 @@ struct cfneb_batch {
     int* summary = nullptr;
     int* host_summary = nullptr;  // pinned, per table entry: done, err, steps this call, step
     std::vector<cfneb_band*> bands;
+    std::vector<char> owned;  // 1: the band was made by cfneb_batch_add and is the batch's
     unsigned graph_variants = 0;
     hipGraph_t graph = nullptr;  // a whole step
     hipGraphExec_t exec = nullptr;
@@ -1153,6 +1170,7 @@ int cfneb_batch_create(int max_bands, void* workspace, size_t workspace_bytes, v
     B->plan = reinterpret_cast<int*>(base + BL.plan);
     B->summary = reinterpret_cast<int*>(base + BL.summary);
     B->bands.assign(max_bands, nullptr);
+    B->owned.assign(max_bands, 0);
     B->launch.bd.bands = B->table;
     B->launch.bd.live = B->live;
     B->launch.bd.plan = B->plan;
@@ -1206,11 +1224,61 @@ int cfneb_batch_detach(cfneb_batch* B, int slot)
         hipStreamSynchronize(B->stream) != hipSuccess)
         return CFNEB_EHIP;
     B->bands[slot] = nullptr;
+    B->owned[slot] = 0;  // a band of cfneb_batch_add detached here passes to the caller
     unsigned v = 0;
     for (auto* bb : B->bands)
         if (bb) v |= 1u << band_variant(bb->d);
     B->launch.variants = v;
     return CFNEB_OK;
+}
+
+int cfneb_batch_add(cfneb_batch* B, const cfneb_params* p, int64_t n_atoms, const int32_t* types,
+                    const double* pos_init, const double* cell_init, const double* pos_final,
+                    const double* cell_final, void* workspace, size_t workspace_bytes, int* slot)
+{
+    if (!B) return CFNEB_EINVAL;
+    int free_slot = -1;
+    for (int q = 0; q < B->cap && free_slot < 0; ++q)
+        if (!B->bands[q]) free_slot = q;
+    if (free_slot < 0) return CFNEB_ECAPACITY;
+    cfneb_band* band = nullptr;
+    int rc = cfneb_create_band(p, n_atoms, types, pos_init, cell_init, pos_final, cell_final, workspace,
+                               workspace_bytes, B->stream, &band);
+    if (rc != CFNEB_OK) return rc;
+    int s = -1;
+    rc = cfneb_batch_attach(B, band, &s);
+    if (rc != CFNEB_OK) {
+        cfneb_destroy(band);
+        return rc;
+    }
+    B->owned[s] = 1;
+    if (slot) *slot = s;
+    return CFNEB_OK;
+}
+
+int cfneb_batch_remove(cfneb_batch* B, int slot)
+{
+    if (!B || slot < 0 || slot >= B->cap || !B->bands[slot]) return CFNEB_EINVAL;
+    cfneb_band* band = B->bands[slot];
+    const bool own = B->owned[slot] != 0;
+    const int rc = cfneb_batch_detach(B, slot);
+    if (rc != CFNEB_OK) return rc;
+    B->owned[slot] = 0;
+    if (own) cfneb_destroy(band);
+    return CFNEB_OK;
+}
+
+cfneb_band* cfneb_batch_band(cfneb_batch* B, int slot)
+{
+    if (!B || slot < 0 || slot >= B->cap) return nullptr;
+    return B->bands[slot];
+}
+
+int cfneb_batch_energies(cfneb_batch* B, int slot, double* H, int cap, int* n_images, double* barrier,
+                         int* ci_index, double* path_coord)
+{
+    if (!B || slot < 0 || slot >= B->cap || !B->bands[slot]) return CFNEB_EINVAL;
+    return cfneb_energies(B->bands[slot], H, cap, n_images, barrier, ci_index, path_coord);
 }
 
 int cfneb_batch_step(cfneb_batch* B, int max_steps, double f_tol, int* steps_done, uint8_t* converged,
@@ -1267,6 +1335,11 @@ int cfneb_batch_destroy(cfneb_batch* B)
 {
     if (!B) return CFNEB_EINVAL;
     (void)hipStreamSynchronize(B->stream);
+    for (int q = 0; q < B->cap; ++q)
+        if (B->bands[q] && B->owned[q]) {
+            cfneb_destroy(B->bands[q]);
+            B->bands[q] = nullptr;
+        }
     drop_graph(B);
     if (B->capture_stream) (void)hipStreamDestroy(B->capture_stream);
     if (B->host_summary) (void)hipHostFree(B->host_summary);

@@ -3,9 +3,10 @@
 Requests (a band to relax to a force tolerance) arrive over time.  The loop
 admits waiting requests in arrival order while a batch slot is free and the sum of
 the admitted bands' device footprints (cfneb_band_bytes) stays within the HBM
-budget; every admitted band stays on the device, attached to one batch, until it
-converges or fails; between batch calls finished bands are read out, detached and
-freed, and new arrivals are admitted.  All band arithmetic runs in the HIP
+budget; every admitted band is made inside one batch (cfneb_batch_add) and stays
+on the device until it converges, fails or reaches the step cap; between batch
+calls finished bands are read out (cfneb_batch_energies) and removed
+(cfneb_batch_remove), and new arrivals are admitted.  All band arithmetic runs in the HIP
 library; this module only schedules.
 """
 import time
@@ -70,16 +71,21 @@ class Server:
                 break
             self.waiting.popleft()
             e = req.endpoints
+            slot = -1
             try:
-                band = cfneb.Band(req.params, e["pos_init"], e["cell_init"], e["pos_final"], e["cell_final"])
+                # the band is made inside the batch (cfneb_batch_add) on the batch's stream
+                slot = self.batch.add(req.params, e["pos_init"], e["cell_init"], e["pos_final"],
+                                      e["cell_final"])
+                band = self.batch.bands[slot]
                 if req.displace is not None:
                     band.displace_interior(req.displace)
             except cfneb.CfnebError as err:  # the request fails alone; the others go on
+                if slot >= 0:
+                    self.batch.remove(slot)
                 req.error = err.code
                 req.finished = self.clock() - self.t0
                 self.done.append(req)
                 continue
-            slot = self.batch.attach(band)
             req.admitted = self.clock() - self.t0
             self.in_use += req.bytes
             self.active[slot] = (req, band)
@@ -87,14 +93,13 @@ class Server:
     def _retire(self, slot, now):
         req, band = self.active.pop(slot)
         if req.error == 0:
-            e = band.energies()
+            e = self.batch.energies(slot)
             req.barrier = e["barrier"]
-            req.info = dict(ci=e["ci"], n_images=len(e["H"]))
+            req.info = dict(ci=e["ci"], n_images=len(e["H"]), H=e["H"])
         st = band.get_state()
         req.moving_image_steps = int(st["image_steps"])
         req.finished = now
-        self.batch.detach(slot)
-        band.close()
+        self.batch.remove(slot)  # destroys the band; its workspace returns to the pool
         self.in_use -= req.bytes
         self.done.append(req)
 
@@ -135,17 +140,27 @@ class Server:
 
 
 def summarize(done, wall):
-    """Latency percentiles over the requests that reached a converged barrier; requests
-    that failed or hit the step cap are counted apart."""
+    """Latency percentiles from arrival to the end of each request.
+
+    p50_s / p99_s cover every request: a request that reached the step cap or failed is
+    counted at its time to that end, a lower bound of its time to a converged barrier.
+    p50_converged_s / p99_converged_s cover the converged requests alone."""
+    lat_all = np.array([r.finished - r.arrival for r in done])
     lat = np.array([r.finished - r.arrival for r in done if r.error == 0 and r.converged])
     work = sum(r.n_atoms * r.moving_image_steps for r in done)
+
+    def pct(a, q):
+        return float(np.percentile(a, q)) if len(a) else None
+
     return dict(
         requests=len(done),
         converged=sum(r.converged for r in done),
         failed=sum(r.error != 0 for r in done),
         capped=sum((not r.converged) and r.error == 0 for r in done),
-        p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
-        p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
+        p50_s=pct(lat_all, 50),
+        p99_s=pct(lat_all, 99),
+        p50_converged_s=pct(lat, 50),
+        p99_converged_s=pct(lat, 99),
         atom_steps_per_s=work / wall if wall > 0 else None,
         wall_s=wall,
     )

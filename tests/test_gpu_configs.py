@@ -1,0 +1,196 @@
+"""The stated workloads against the oracle at their stated sizes, through the C ABI.
+
+* The 255-atom LJ vacancy hop (4x4x4 FCC cells, a = 1.5496) from endpoints relaxed
+  by the oracle with the cell filter to fmax < 1e-6: 7 images, climbing image after
+  50 steps, spring 1, FIRE dt 0.005, FP64 arithmetic, 300 steps.  Both sides start
+  from the same relaxed endpoints; barrier, enthalpies, climbing image, path
+  coordinate and coordinates are compared after the 300 steps, and the converged
+  barrier in FP64 and FP32.
+* Adaptive images on bands of many row tiles (4,608 and 98,304 atoms): decisions
+  and inserted midpoints bit-exact against the oracle's decision on the device's
+  own coordinates, through the forced call and inside the captured step.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL_BARRIER, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+
+
+@pytest.fixture(scope="module")
+def lj255_relaxed():
+    import oracle
+    import workloads as W
+    w = W.lj_fcc_hop_255()
+    p = oracle.default_params(oracle.LJ)
+    A = oracle.relax(p, w["pos_init"], w["cell_init"], 20000, 1e-6)
+    B = oracle.relax(p, w["pos_final"], w["cell_final"], 20000, 1e-6)
+    assert A[3] < 1e-6 and B[3] < 1e-6
+    return dict(pos_init=A[0], cell_init=A[1], pos_final=B[0], cell_final=B[1], n=w["n"])
+
+
+CONFIG0 = dict(n_images=7, max_images=7, climb_after=50, k_spring=1.0, fire_dt0=0.005)
+
+
+def _config0_pair(w, fp64):
+    import oracle
+    from paper_2510_16721_amd import cfneb
+    g = cfneb.Band(cfneb.default_params(cfneb.CFNEB_LJ, force_fp64=1 if fp64 else 0, **CONFIG0),
+                   w["pos_init"], w["cell_init"], w["pos_final"], w["cell_final"])
+    o = oracle.Band(oracle.default_params(oracle.LJ, **CONFIG0), w["pos_init"], w["cell_init"],
+                    w["pos_final"], w["cell_final"])
+    return g, o
+
+
+def test_lj255_vacancy_band_300_steps_fp64(lj255_relaxed):
+    # the stated run: both trajectories agree to rounding over all 300 steps
+    g, o = _config0_pair(lj255_relaxed, fp64=True)
+    print("lj255: 300 FP64 steps from relaxed endpoints", flush=True)
+    assert g.step(300)[0] == o.step(300)[0] == 300
+    ge, oe = g.energies(), o.energies()
+    gs, os_ = g.get_state(), o.get_state()
+    n = g.n
+    print(f"lj255 300 steps: barrier {ge['barrier']:.9f} vs {oe['barrier']:.9f}; "
+          f"max|dH| {np.abs(ge['H'] - oe['H']).max():.3e} eV, max|dxi| {np.abs(ge['xi'] - oe['xi']).max():.3e}, "
+          f"max|dX| {np.abs(gs['X'] - os_['X']).max():.3e}", flush=True)
+    assert ge["ci"] == oe["ci"] == 3
+    assert abs(ge["barrier"] - oe["barrier"]) <= 1e-6, (ge["barrier"], oe["barrier"])
+    # enthalpies of every image within the energy bound per atom
+    np.testing.assert_allclose(ge["H"], oe["H"], rtol=0, atol=1e-6 * n)
+    np.testing.assert_allclose(ge["xi"], oe["xi"], rtol=0, atol=1e-6)
+    assert ge["xi"][0] == 0.0 and ge["xi"][-1] == 1.0
+    np.testing.assert_allclose(gs["X"], os_["X"], rtol=0, atol=1e-5)
+    assert (gs["n_pos"], gs["step"]) == (os_["n_pos"], os_["step"])
+    assert gs["dt"] == pytest.approx(os_["dt"], rel=1e-12)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_lj255_converged_barrier(lj255_relaxed, fp64):
+    # converged climbing image: the saddle's enthalpy, within 1 meV of the oracle's
+    g, o = _config0_pair(lj255_relaxed, fp64=fp64)
+    gd, gf, gc = g.step(5000, 1e-3)
+    od, of, oc = o.step(5000, 1e-3)
+    print(f"lj255 fp64={fp64}: converged in {gd} (device) and {od} (oracle) steps", flush=True)
+    assert gc and oc
+    ge, oe = g.energies(), o.energies()
+    assert ge["ci"] == oe["ci"] == 3
+    assert abs(ge["barrier"] - oe["barrier"]) <= TOL_BARRIER, (ge["barrier"], oe["barrier"])
+    for k in (0, 3, 6):
+        assert abs(ge["H"][k] - oe["H"][k]) <= TOL_BARRIER
+    # the path coordinate of the device's own band equals the oracle's on those coordinates
+    import oracle
+    np.testing.assert_allclose(ge["xi"], oracle.path_coord(g.get_state()["X"], g.n), rtol=0, atol=1e-12)
+
+
+def test_path_coordinate_on_the_device_coordinates():
+    # a Tersoff band under pressure after some FP32 steps, with a rigid translation of
+    # one image added: the device's xi equals the oracle's on the same coordinates
+    import oracle
+    g, _, w, _ = make_pair("ts_small", n_images=7, max_images=7, pressure_GPa=5.0, oracle_too=False)
+    g.step(30)
+    s = g.get_state()
+    X = s["X"].copy()
+    X[3, :g.n] += np.array([0.3, -0.2, 0.1])
+    g.set_state(X, s["v"], s["dt"], s["alpha"], s["n_pos"], s["fresh"], s["step"], s["ci"])
+    xi = g.energies()["xi"]
+    np.testing.assert_allclose(xi, oracle.path_coord(g.get_state()["X"], g.n), rtol=0, atol=1e-12)
+    # the translation does not move the image along the path
+    X0 = s["X"]
+    np.testing.assert_allclose(xi, oracle.path_coord(X0, g.n), rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------ adaptive images, many tiles
+def _check_forced_refine(g, X, ci):
+    # the band's own image limits decide on both sides
+    import oracle
+    s = g.get_state()
+    g.set_state(X, None, s["dt"], s["alpha"], 0, 1, s["step"], ci)
+    st = g.get_state()
+    ins_ref, del_ref, _ = oracle.refine_decide(st["X"], st["ci"], g.p.max_images, g.p.min_images)
+    Xb = st["X"]
+    ins, dele = g.refine()
+    assert (ins, dele) == (ins_ref, del_ref)
+    Xa = g.get_state()["X"]
+    if ins >= 0:
+        mid = Xb[ins - 1] + 0.5 * (Xb[ins] - Xb[ins - 1])
+        np.testing.assert_array_equal(Xa[ins], mid)
+        np.testing.assert_array_equal(np.delete(Xa, ins, axis=0), Xb)
+    elif dele >= 0:
+        np.testing.assert_array_equal(Xa, np.delete(Xb, dele, axis=0))
+    else:
+        np.testing.assert_array_equal(Xa, Xb)
+    return ins, dele
+
+
+@pytest.mark.parametrize("name,M", [("ts4608", 8), ("ts98304", 6)])
+def test_refine_decisions_on_many_tiles(name, M):
+    # 4,611 rows (19 tiles of 256) and 98,307 rows (385 tiles): the exact spacings are
+    # summed tile by tile on the device; insert, delete and no-change cases
+    g, _, w, _ = make_pair(name, n_images=M, max_images=M + 2, min_images=3, climb_after=-1,
+                           oracle_too=False)
+    print(f"{name}: refine decisions on {g.n + 3} rows", flush=True)
+    X0 = g.get_state()["X"].copy()
+    # uniform spacing: no change
+    assert _check_forced_refine(g, X0.copy(), -1) == (-1, -1)
+    # a gap: image 2 moved 0.9 of the way to image 3 leaves interval 1 long
+    X = X0.copy()
+    X[2] = X[1] + 1.9 * (X[2] - X[1])
+    assert _check_forced_refine(g, X, -1) == (2, -1)
+    g.close()
+    # two crowded images and no room to insert: images 3 and 4 at 0.01 and 0.02 of
+    # interval 2, so image 3 sits between two short intervals and is deleted, unless it
+    # is the climbing image
+    g, _, w, _ = make_pair(name, n_images=M, max_images=M, min_images=3, climb_after=-1,
+                           oracle_too=False)
+    d = X0[3] - X0[2]
+    X = X0.copy()
+    X[3] = X0[2] + 0.01 * d
+    X[4] = X0[2] + 0.02 * d
+    assert _check_forced_refine(g, X.copy(), -1) == (-1, 3)
+    assert _check_forced_refine(g, X.copy(), 3) == (-1, -1)
+
+
+def test_refine_inside_the_captured_step_at_full_size():
+    # The benchmark's band (98,304 atoms, 24 images up to 40, 15 GPa, refine every 20
+    # steps): the check at step 20 runs inside the captured step.  Its decision and
+    # midpoint are compared bit for bit with the oracle's decision on the device's
+    # coordinates just before the check (the band after the check minus an inserted
+    # image; unchanged when nothing is inserted or deleted).
+    import oracle
+    kw = dict(n_images=24, max_images=40, min_images=5, pressure_GPa=15.0, refine_every=20,
+              climb_after=100)
+    for ins_num in (9, 0):  # the benchmark's threshold; 0 inserts at every check
+        g, _, w, _ = make_pair("ts98304", oracle_too=False, ins_num=ins_num, **kw)
+        print(f"ts98304 in-step refine, ins_num={ins_num}", flush=True)
+        assert g.step(19)[0] == 19
+        M0 = g.get_state()["X"].shape[0]
+        assert g.step(1)[0] == 1
+        s = g.get_state()
+        Xa = s["X"]
+        M1 = Xa.shape[0]
+        assert M1 in (M0, M0 + 1), "a deletion cannot be reconstructed here"
+        if M1 == M0 + 1:
+            # the inserted image is the one that is the exact midpoint of its neighbours
+            cand = [i for i in range(1, M1 - 1)
+                    if np.array_equal(Xa[i], Xa[i - 1] + 0.5 * (Xa[i + 1] - Xa[i - 1]))]
+            assert cand, "no inserted midpoint found"
+            i = cand[0]
+            Xb = np.delete(Xa, i, axis=0)
+            ins_ref, del_ref, _ = oracle.refine_decide(Xb, -1, 40, 5, ins=(ins_num, 4))
+            assert (ins_ref, del_ref) == (i, -1)
+            assert s["fresh"] == 1 and s["n_pos"] == 0 and not np.any(s["v"])
+        else:
+            ins_ref, del_ref, _ = oracle.refine_decide(Xa, -1, 40, 5, ins=(ins_num, 4))
+            assert (ins_ref, del_ref) == (-1, -1)
+        if ins_num == 0:
+            assert M1 == M0 + 1
+        g.close()

@@ -84,6 +84,48 @@ def test_served_results_equal_alone():
         assert conv and barrier == r.barrier, (r.rid, barrier, r.barrier)
     s = serving.summarize(done, 1.0)
     assert s["converged"] == len(reqs) and s["p99_s"] >= s["p50_s"] > 0
+    assert s["p99_s"] == s["p99_converged_s"]
+
+
+def test_served_barriers_match_oracle():
+    # every served request (LJ and Tersoff vacancy hops, climbing image from step 30,
+    # FP64 arithmetic) against the oracle converging the same band from the same
+    # endpoints: barriers within 1 meV
+    import oracle
+    from paper_2510_16721_amd import serving
+    from gpu_cases import TOL_BARRIER
+    reqs = _requests()
+    srv = serving.Server(hbm_budget_bytes=10**12, max_bands=8, f_tol=0.02, steps_per_call=16,
+                         max_steps=3000)
+    done = sorted(srv.run(reqs), key=lambda r: r.rid)
+    assert max(o[1] for o in srv.occupancy) >= 2
+    for r in done:
+        assert r.error == 0 and r.converged
+        p = r.params
+        kind = oracle.LJ if p.potential == 1 else oracle.TERSOFF
+        op = oracle.default_params(kind, n_images=p.n_images, max_images=p.max_images,
+                                   climb_after=p.climb_after)
+        e = r.endpoints
+        o = oracle.Band(op, e["pos_init"], e["cell_init"], e["pos_final"], e["cell_final"])
+        od, of, oc = o.step(3000, 0.02)
+        oe = o.energies()
+        print(f"served request {r.rid}: barrier {r.barrier:.6f}, oracle {oe['barrier']:.6f}", flush=True)
+        assert oc
+        assert abs(r.barrier - oe["barrier"]) <= TOL_BARRIER, (r.rid, r.barrier, oe["barrier"])
+        assert r.info["ci"] == oe["ci"]
+
+
+def test_summary_counts_capped_requests():
+    # a request that reaches the step cap enters p50 / p99 at its time to the cap
+    from paper_2510_16721_amd import serving
+    reqs = _requests()[:4]
+    srv = serving.Server(hbm_budget_bytes=10**12, max_bands=4, f_tol=1e-9, steps_per_call=16,
+                         max_steps=64)
+    done = srv.run(reqs)
+    s = serving.summarize(done, 1.0)
+    assert s["capped"] == 4 and s["converged"] == 0
+    assert s["p99_converged_s"] is None and s["p99_s"] > 0
+    assert all(r.steps >= 64 and r.finished > r.arrival for r in done)
 
 
 def test_failing_and_oversized_requests_fail_alone():
