@@ -254,6 +254,24 @@ int cfneb_relax(const cfneb_params* p, int64_t n_atoms, const int32_t* types, do
                 int max_steps, double f_tol, void* workspace, size_t workspace_bytes, void* hip_stream,
                 int* steps_done, double* fmax, int* converged);
 
+/* cfneb_relax for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same relaxation and the same
+ * kernels, with the band's device memory taken from a static array of
+ * CFNEB_RELAX_SCRATCH_BYTES on each GPU (held until the process ends) instead of a
+ * caller workspace, and no allocation of any kind (no device or pinned host memory,
+ * no graph, stream or event).  Kernels are launched one by one on hip_stream; the call
+ * synchronises it before returning.  Arguments and results as cfneb_relax.  Errors:
+ * CFNEB_ENOMEM when cfneb_band_bytes(p, n_atoms, 3) exceeds
+ * CFNEB_RELAX_SCRATCH_BYTES (about 13,000 atoms for LJ, 16,000 for FP32 Tersoff
+ * carbon), CFNEB_EHIP if the array's address cannot be found; otherwise those of
+ * cfneb_relax.  Every call on one GPU uses that GPU's array and clears it first; two
+ * calls that overlap on one GPU (two host threads, or two streams) race and must not
+ * be made. */
+#define CFNEB_RELAX_SCRATCH_BYTES (64u << 20)
+int cfneb_relax_noalloc(const cfneb_params* p, int64_t n_atoms, const int32_t* types, double* pos,
+                        double* cell, int max_steps, double f_tol, void* hip_stream, int* steps_done,
+                        double* fmax, int* converged);
+
 /* Checkpoint: generalized coordinates X and velocities v of the n_images images,
  * each (n_atoms + 3) x 3 row-major (rows of R~, then rows of c_f B: the coordinates
  * of Sec. II.C, Eq. (15)), into host arrays of cap_images images; FIRE state.  X and

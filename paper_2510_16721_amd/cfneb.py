@@ -23,7 +23,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECELL", -5: "ENE
 SYMBOLS = ["cfneb_params_default", "cfneb_band_bytes", "cfneb_create_band", "cfneb_step",
            "cfneb_step_profiled",
            "cfneb_refine", "cfneb_energies", "cfneb_profile", "cfneb_get_image", "cfneb_relax",
-           "cfneb_get_state",
+           "cfneb_relax_noalloc", "cfneb_get_state",
            "cfneb_set_state", "cfneb_image_data", "cfneb_record_neb_force", "cfneb_neighbours",
            "cfneb_destroy", "cfneb_strerror", "cfneb_last_error", "cfneb_batch_bytes",
            "cfneb_batch_create", "cfneb_batch_attach", "cfneb_batch_detach", "cfneb_batch_add",
@@ -104,6 +104,8 @@ def _declare(L):
     L.cfneb_relax.argtypes = [ctypes.POINTER(Params), c_int64, _ip, _dp, _dp, c_int, c_double,
                               c_void, c_size, c_void, ctypes.POINTER(c_int), _dp,
                               ctypes.POINTER(c_int)]
+    L.cfneb_relax_noalloc.argtypes = [ctypes.POINTER(Params), c_int64, _ip, _dp, _dp, c_int, c_double,
+                                      c_void, ctypes.POINTER(c_int), _dp, ctypes.POINTER(c_int)]
     L.cfneb_get_state.argtypes = [c_void, _dp, _dp, c_int, ctypes.POINTER(c_int),
                                   ctypes.POINTER(FireState)]
     L.cfneb_set_state.argtypes = [c_void, c_int, _dp, _dp, ctypes.POINTER(FireState)]
@@ -186,6 +188,27 @@ def relax(p, pos, cell, max_steps=20000, f_tol=1e-4, stream=None):
                            ctypes.byref(conv))
     if rc != 0:
         raise CfnebError(rc, "cfneb_relax")
+    return R, h.reshape(3, 3), steps.value, fmax[0], bool(conv.value)
+
+
+# device bytes of the static array behind cfneb_relax_noalloc
+RELAX_SCRATCH_BYTES = 64 << 20
+
+
+def relax_noalloc(p, pos, cell, max_steps=20000, f_tol=1e-4, stream=None):
+    """cfneb_relax_noalloc: the relaxation of relax() with the library's static device
+    array instead of a workspace (nothing is allocated).  Same return value."""
+    import torch
+    R = _f64(pos, (-1, 3)).copy()
+    h = _f64(cell, 9).copy()
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    steps, conv = ctypes.c_int(), ctypes.c_int()
+    fmax = np.zeros(1)
+    rc = lib().cfneb_relax_noalloc(ctypes.byref(p), R.shape[0], None, _d(R), _d(h), int(max_steps),
+                                   float(f_tol), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(steps),
+                                   _d(fmax), ctypes.byref(conv))
+    if rc != 0:
+        raise CfnebError(rc, "cfneb_relax_noalloc")
     return R, h.reshape(3, 3), steps.value, fmax[0], bool(conv.value)
 
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -649,6 +650,71 @@ int cfneb_relax(const cfneb_params* p, int64_t n_atoms, const int32_t* types, do
     if (rc == CFNEB_OK) rc = cfneb_get_image(b, 1, pos, cell);
     if (converged) *converged = conv;
     cfneb_destroy(b);
+    return rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- relaxation without allocation
+// Device memory of cfneb_relax_noalloc: one array per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel or a copy: the device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[CFNEB_RELAX_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch array (looked up on the first call on that
+// device, with it current); nullptr on failure.
+void* scratch_of_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfneb_relax_noalloc(const cfneb_params* p, int64_t n_atoms, const int32_t* types, double* pos, double* cell,
+                        int max_steps, double f_tol, void* hip_stream, int* steps_done, double* fmax,
+                        int* converged)
+{
+    (void)types;
+    if (!p || !pos || !cell || max_steps < 0) return CFNEB_EINVAL;
+    const cfneb_params q = relax_params(p);
+    int rc = validate(&q, n_atoms);
+    if (rc != CFNEB_OK) return rc;
+    // the band lives on this stack frame: handle, pageable host state, no graphs, no
+    // capture stream, kernels launched one by one
+    cfneb_band b;
+    b.p = q;
+    if (!make_layout(&q, n_atoms, q.max_images, &b.L)) return CFNEB_EINVAL;
+    if (b.L.total > size_t(CFNEB_RELAX_SCRATCH_BYTES)) return CFNEB_ENOMEM;
+    void* ws = scratch_of_current_device();
+    if (!ws) return CFNEB_EHIP;
+    BandState host_state;
+    b.host_state = &host_state;
+    b.use_graph = false;
+    b.stream = static_cast<hipStream_t>(hip_stream);
+    fill_dev(&b, ws, cell, 1);
+    rc = init_band(&b, pos, cell, pos, cell, ws, 1);
+    int conv = 0;
+    if (rc == CFNEB_OK) rc = cfneb_step(&b, max_steps, f_tol, steps_done, fmax, &conv);
+    if (rc == CFNEB_OK) rc = cfneb_get_image(&b, 1, pos, cell);
+    if (converged) *converged = conv;
+    (void)hipStreamSynchronize(b.stream);
+    b.host_state = nullptr;  // nothing of this band is freed: it owns nothing
     return rc;
 }
 
