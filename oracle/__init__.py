@@ -107,6 +107,10 @@ def _declare(L):
     L.orc_relax.argtypes = [ctypes.POINTER(Params), c_int, _dp, _dp, c_int, c_double,
                             ctypes.POINTER(c_int), _dp]
     L.orc_path_coord.argtypes = [c_int, c_int, c_int, _dp, _dp]
+    L.orc_set_threads.argtypes = [c_int]
+    L.orc_set_threads.restype = None
+    L.orc_max_threads.argtypes = []
+    L.orc_max_threads.restype = c_int
     L.orc_fire_step.argtypes = [c_int, c_int, c_int, _dp, _dp, _dp, ctypes.POINTER(FireState),
                                 c_double, c_double, c_int, c_double, c_double, c_double, c_double]
 
@@ -283,6 +287,15 @@ def profile(X, H, Fg, natoms):
     _check(lib().orc_profile(M, int(natoms), X.shape[1], _d(X), _d(_f64(H, M)), _d(Fg), _d(s), _d(sl)),
            "profile")
     return s, sl
+
+
+def set_threads(n):
+    """Threads over which band images are evaluated (OpenMP); results do not depend on it."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return lib().orc_max_threads()
 
 
 def path_coord(X, natoms):

@@ -9,6 +9,8 @@
 //   interval or delete an image between two short ones.
 #include "internal.h"
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -618,6 +620,11 @@ extern "C" int orc_band_image(const orc_band* b, int k, double* E, double* H, do
 }
 
 extern "C" void orc_band_destroy(orc_band* b) { delete b; }
+
+// Threads of the image loop (the band's images are evaluated in parallel; each image
+// is sequential, so results do not depend on the count).
+extern "C" void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+extern "C" int orc_max_threads(void) { return omp_get_max_threads(); }
 
 // Energy profile of the band at its current coordinates: every image is evaluated
 // afresh, then the Hermite interpolant of H over the path coordinate is sampled at

@@ -161,6 +161,9 @@ int  orc_band_set_state(orc_band* b, int n_images, const double* X, const double
 int  orc_band_image(const orc_band* b, int k, double* E, double* H, double* V,
                     double* F, double* Fg, double* Fneb, double* R, double* h);
 void orc_band_destroy(orc_band* b);
+/* Threads over which a band's images are evaluated (results do not depend on it). */
+void orc_set_threads(int n);
+int  orc_max_threads(void);
 
 /* ---------------- energy profile (readout) ------------------------------ */
 /* The transitions of Sec. III are shown as enthalpy against a normalized path

@@ -184,13 +184,20 @@ def diamond_hop_near(n_target):
     return diamond_vacancy_hop(nx, ny, nz)
 
 
-def band_mix(seed, count, n_lo, n_hi, m_lo, m_hi):
+def band_mix(seed, count, n_lo, n_hi, m_lo, m_hi, size_classes=0):
     """Independent bands: atom counts log-uniform in [n_lo, n_hi], image counts uniform in
-    [m_lo, m_hi], LJ vacancy hops (even index) and Tersoff diamond vacancy hops (odd)."""
+    [m_lo, m_hi], LJ vacancy hops (even index) and Tersoff diamond vacancy hops (odd).
+    size_classes > 0 snaps each drawn count to the nearest (in log) of that many
+    log-spaced class sizes in [n_lo, n_hi], so that endpoints come from a pool of at
+    most size_classes structures per family."""
     rng = np.random.default_rng(seed)
+    classes = (np.exp(np.linspace(np.log(n_lo), np.log(n_hi), size_classes)) if size_classes > 0
+               else None)
     out = []
     for q in range(count):
         n_target = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        if classes is not None:
+            n_target = float(classes[np.argmin(np.abs(np.log(classes) - np.log(n_target)))])
         m = int(rng.integers(m_lo, m_hi + 1))
         kind = "lj" if q % 2 == 0 else "ts"
         w = lj_hop_near(n_target) if kind == "lj" else diamond_hop_near(n_target)
