@@ -11,9 +11,9 @@
 //   bins   [slot][...]    int   counts, starts; bpos: atoms in bin order (R, packed id)
 //   nbr    [slot][cap][N] u32   packed neighbour entries, entry-major (coalesced)
 //   ncnt   [slot][N]      int   neighbour count (may exceed cap: overflow)
-//   dvec   [slot][cap][N] T4    Tersoff: bond vector and length
-//   bo     [slot][cap][N] T2    Tersoff: b_ij and db/dzeta
-//   P      [slot][cap][N] T4    Tersoff: dU_i/dr^ij per bond
+//   dvec   [slot][cap][N] T4    Tersoff: bond vector and length (bonds past the fourth)
+//   bo     [slot][cap][N] T2    Tersoff: b_ij and db/dzeta (same)
+//   P      [slot][ccap][N] T4   Tersoff: dU_i/dr^ij per candidate (zero if not a bond)
 //   geom / scal [slot]          per-image 3x3 geometry and reduced scalars
 //   partial buffers             fixed-order block partials of every reduction
 //   state                       band scalars (FIRE, slot table, flags)
@@ -24,6 +24,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "cfneb.h"
 
@@ -155,13 +157,13 @@ struct BandDev {
     int* ncand;         // [slot][N]
     double* Rref;       // [slot][3][ld] positions at the candidate build
     SkinState* skst;    // [slot]
-    // Tersoff bond scratch: bond vectors and bond orders past the fourth bond
-    // ([slot][cap][N]), the candidate slot of each such bond, the per-candidate
-    // derivatives P ([slot][ccap][N], zero for candidates that are not bonds) and the
-    // reverse candidate of each candidate (the slot of (i, -n) in j's list).
+    // Tersoff bond scratch: bond vectors, bond orders and candidate slots of bonds
+    // past the fourth ([slot][cap][N]); the per-candidate derivatives P
+    // ([slot][ccap][N], zero for candidates that are not bonds) and the reverse
+    // candidate of each candidate (the slot of (i, -n) in j's list).
     void* dvec;
     void* bo;
-    uint16_t* bcid;
+    void* bcid;
     void* P;
     uint16_t* crev;
     ImageGeom* geom;
@@ -594,6 +596,70 @@ __host__ __device__ inline void mm3(const double* a, const double* b, double* c)
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             c[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+}
+
+// Tersoff force gather of atoms i0 + q * stride (q < Q, those below N): F_i =
+// sum_c (P_c - P_rev(c)) over i's candidates c in increasing order, four at a time, P_c
+// from i's own slot and P_rev(c) from the reverse candidate (i, -n) of j's list; both
+// vanish unless the pair is a bond.  All loads of one round (slots, reverse slots,
+// own P of every atom), then every reverse P, are in flight together.
+template <typename T>
+using vec4_of = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+
+template <typename T, int Q>
+__device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int stride, T (&f)[Q][3])
+{
+    const size_t N = b.N;
+    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
+    const gmem<const uint16_t>* __restrict__ crev = gp<const uint16_t>(b.crev + size_t(slot) * b.ccap * N);
+    const gmem<const vec4_of<T>>* __restrict__ Pb =
+        gp<const vec4_of<T>>(reinterpret_cast<const vec4_of<T>*>(b.P) + size_t(slot) * b.ccap * N);
+    const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
+    constexpr int U = 4;
+    int nc[Q], ii[Q], nmax = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = i0 + q * stride;
+        ii[q] = i < b.N ? i : b.N - 1;
+        nc[q] = i < b.N ? ncand[ii[q]] : 0;
+        f[q][0] = f[q][1] = f[q][2] = T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) nmax = max(nmax, nc[q]);
+    for (int c0 = 0; c0 < nmax; c0 += U) {
+        uint32_t ent[Q][U];
+        int rv[Q][U];
+        vec4_of<T> pe[Q][U], pr[Q][U];
+        // past an atom's last candidate the loads repeat it (always in bounds, no
+        // branch between the loads) and its sum below stops
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t o = size_t(max(min(c0 + u, nc[q] - 1), 0)) * N + ii[q];
+                ent[q][u] = cand[o];
+                rv[q][u] = int(crev[o]);
+                pe[q][u] = load4(Pb, o);
+            }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads of the round ahead of their uses
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) pr[q][u] = load4(Pb, size_t(rv[q][u]) * N + nbr_j(ent[q][u]));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (c0 + u >= nc[q]) break;
+                f[q][0] += pe[q][u].x;
+                f[q][1] += pe[q][u].y;
+                f[q][2] += pe[q][u].z;
+                f[q][0] -= pr[q][u].x;
+                f[q][1] -= pr[q][u].y;
+                f[q][2] -= pr[q][u].z;
+            }
+    }
 }
 
 // ---------------------------------------------------------------- launchers

@@ -77,7 +77,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->skin = take(M * sizeof(SkinState));
     L->dvec = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
     L->bo = take(L->tersoff ? M * size_t(L->cap) * N * 2 * tsz : 0);
-    L->bcid = take(L->tersoff ? M * size_t(L->cap) * N * 2 : 0);
+    L->bcid = take(L->tersoff ? M * size_t(L->cap) * N * 4 : 0);
     L->P = take(L->tersoff ? M * size_t(L->ccap) * N * 4 * tsz : 0);
     L->crev = take(L->tersoff ? M * size_t(L->ccap) * N * 2 : 0);
     L->geom = take(M * sizeof(ImageGeom));
@@ -296,7 +296,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.skst = reinterpret_cast<SkinState*>(base + L.skin);
     d.dvec = L.tersoff ? base + L.dvec : nullptr;
     d.bo = L.tersoff ? base + L.bo : nullptr;
-    d.bcid = L.tersoff ? reinterpret_cast<uint16_t*>(base + L.bcid) : nullptr;
+    d.bcid = L.tersoff ? base + L.bcid : nullptr;
     d.P = L.tersoff ? base + L.P : nullptr;
     d.crev = L.tersoff ? reinterpret_cast<uint16_t*>(base + L.crev) : nullptr;
     d.geom = reinterpret_cast<ImageGeom*>(base + L.geom);

@@ -28,12 +28,13 @@ namespace cfneb {
 __device__ inline float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ inline double qdiv(double a, double b) { return a / b; }
 
-// FP64 natural logarithm and exponential for the FP32 bond order.  FP64 vector
-// operations run at the FP32 rate on this GPU, so two short polynomial evaluations
-// cost a fraction of two accurately rounded FP32 powers, and their results are far
-// more accurate than FP32 before the final rounding.
+// FP64 natural logarithm and exponential for the FP32 bond order and the bond
+// energies.  FP64 vector operations run at the FP32 rate on this GPU, so two short
+// polynomial evaluations cost a fraction of two accurately rounded FP32 powers, and
+// their results are far more accurate than FP32 before the final rounding.
 // ln: u = m 2^e with m in [1/sqrt 2, sqrt 2); ln m = 2 atanh(s), s = (m - 1)/(m + 1),
-// |s| <= 0.1716, by its series through s^13 (absolute error below 5e-13).
+// |s| <= 0.1716, by its series through s^11 (absolute error below 2e-11); the
+// quotient takes the hardware reciprocal refined by two Newton steps.
 __device__ inline double ln64(double u)
 {
     int e;
@@ -42,10 +43,13 @@ __device__ inline double ln64(double u)
         m *= 2.0;
         e -= 1;
     }
-    const double s = (m - 1.0) / (m + 1.0);
+    const double den = m + 1.0;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(fma(-den, r, 1.0), r, r);
+    r = fma(fma(-den, r, 1.0), r, r);
+    const double s = (m - 1.0) * r;
     const double s2 = s * s;
-    double p = 1.0 / 13.0;
-    p = fma(p, s2, 1.0 / 11.0);
+    double p = 1.0 / 11.0;
     p = fma(p, s2, 1.0 / 9.0);
     p = fma(p, s2, 1.0 / 7.0);
     p = fma(p, s2, 1.0 / 5.0);
@@ -54,14 +58,13 @@ __device__ inline double ln64(double u)
     return fma(double(e), 0.69314718055994531, 2.0 * s * p);
 }
 // exp: y = k ln 2 + r with ln 2 in two parts (k ln2_hi exact), |r| <= ln 2 / 2; exp r
-// by its Taylor series through r^10 / 10! (relative error below 3e-13), then 2^k.
+// by its Taylor series through r^9 / 9! (relative error below 3e-11), then 2^k.
 __device__ inline double exp64(double y)
 {
     const double k = rint(y * 1.4426950408889634);
     double r = fma(-k, 6.93147180369123816490e-01, y);
     r = fma(-k, 1.90821492927058770002e-10, r);
-    double p = 1.0 / 3628800.0;
-    p = fma(p, r, 1.0 / 362880.0);
+    double p = 1.0 / 362880.0;
     p = fma(p, r, 1.0 / 40320.0);
     p = fma(p, r, 1.0 / 5040.0);
     p = fma(p, r, 1.0 / 720.0);
@@ -144,11 +147,10 @@ struct TersoffT {
     // the energy is summed in FP64 from FP64 terms of the FP32 bond length: in a
     // perfect crystal every bond rounds alike, so FP32 terms would add their roundings
     // coherently (about 2e-6 eV/atom on diamond).  Both terms take the same FP32 r, so
-    // its rounding cancels in fr - b fa near the bond's minimum.  The repulsive term is
-    // formed once in FP64 (the force takes it rounded) and its energy half added at
-    // once; the attractive one is formed in FP32 for the force and again in FP64 for the
-    // energy once the bond order is known.  On the FP64 path the whole bond energy is
-    // added with the attractive half.
+    // its rounding cancels in fr - b fa near the bond's minimum.  Each term is formed
+    // once in FP64 and rounded for the force; the repulsive energy half is added at
+    // once, the attractive one when the bond order is known.  On the FP64 path the
+    // whole bond energy is added with the attractive half.
     __device__ T repulsive(T r) const
     {
         if constexpr (sizeof(T) == 4)
@@ -166,10 +168,21 @@ struct TersoffT {
             return repulsive(r);
         }
     }
-    __device__ void attractive_energy(T r, T fcr, T fa, T bb, double b64, T fr, double& e) const
+    // B exp(-l2 r): the FP64 value (FP32 path; for the energy) and its rounding
+    __device__ T attractive(T r, double& fa64) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            fa64 = B64 * exp64(-l2_64 * double(r));
+            return T(fa64);
+        } else {
+            fa64 = 0.0;
+            return B * exp(-l2 * r);
+        }
+    }
+    __device__ void attractive_energy(T fcr, T fa, T bb, double b64, double fa64, T fr, double& e) const
     {
         if constexpr (sizeof(T) == 4)
-            e -= 0.5 * double(fcr) * (b64 * (B64 * exp64(-l2_64 * double(r))));
+            e -= 0.5 * double(fcr) * (b64 * fa64);
         else
             e += double(T(0.5) * fcr * (fr - bb * fa));
     }
@@ -196,15 +209,18 @@ __device__ inline void add_virial(double* acc, T dx, T dy, T dz, T px, T py, T p
     acc[9] -= z * double(pz);
 }
 
+
 // Atoms with at most MAXB bonds: every bond quantity lives in registers.  cos,
 // g(cos) and g'(cos) are symmetric in the two bonds, so each unordered bond pair is
-// evaluated once: it adds to both zetas, and its derivative to both P's.
+// evaluated once: it adds to both zetas, and its derivative to both P's.  P_ij goes
+// to the bond's candidate slot cid (LDS, one per bond at the given stride).
 template <typename T, int MAXB>
-__device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB], const int (&cid)[MAXB],
+__device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB], const int* cid, int stride,
                              gmem<vec4_t<T>>* Pout, size_t N, int i, int cnt, double* acc)
 {
     constexpr int NP = MAXB * (MAXB - 1) / 2;
     T dx[MAXB], dy[MAXB], dz[MAXB], ir[MAXB], fc[MAXB], dfc[MAXB], fr[MAXB], fa[MAXB];
+    double fa64[MAXB];
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
         if (e < cnt) {
@@ -216,11 +232,12 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
             fc[e] = P.fc(d.w);
             dfc[e] = P.dfc(d.w);
             fr[e] = P.repulsive(d.w, fc[e], acc[0]);
-            fa[e] = P.B * exp(-P.l2 * d.w);
+            fa[e] = P.attractive(d.w, fa64[e]);
         } else {
             dx[e] = dy[e] = dz[e] = T(0);
             ir[e] = T(1);
             fc[e] = dfc[e] = fr[e] = fa[e] = T(0);
+            fa64[e] = 0.0;
         }
     }
     // pass 1: zeta of every bond from the unordered pairs (each zeta sums its pairs in
@@ -257,7 +274,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
             T bb, db;
             double b64;
             P.bond_order(z[e], bb, db, b64);
-            P.attractive_energy(bond[e].w, fc[e], fa[e], bb, b64, fr[e], acc[0]);
+            P.attractive_energy(fc[e], fa[e], bb, b64, fa64[e], fr[e], acc[0]);
             dV[e] = dfc[e] * (fr[e] - bb * fa[e]) + fc[e] * (-P.l1 * fr[e] + bb * P.l2 * fa[e]);
             pre[e] = fc[e] * fa[e] * db;
         }
@@ -307,14 +324,15 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
         o.y = py[e];
         o.z = pz[e];
         o.w = T(0);
-        store4(Pout, size_t(cid[e]) * N + i, o);
+        store4(Pout, size_t(cid[e * stride]) * N + i, o);
         add_virial<T>(acc, dx[e], dy[e], dz[e], px[e], py[e], pz[e]);
     }
 }
 
-// Any number of bonds: bond orders go through the per-bond scratch array.
+// Any number of bonds: bond orders go through the per-bond scratch array; bcid holds
+// each bond's candidate slot.
 template <typename T>
-__device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_t<T>* bo, const uint16_t* bcid,
+__device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_t<T>* bo, const int* bcid,
                                 vec4_t<T>* Pout, size_t N, int i, int cnt, double* acc)
 {
     for (int e = 0; e < cnt; ++e) {
@@ -329,12 +347,12 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
             z += P.fc(dq.w) * g;
         }
         vec2_t<T> o;
-        double b64;
+        double b64, fa64;
         P.bond_order(z, o.x, o.y, b64);
         bo[size_t(e) * N + i] = o;
         const T fce = P.fc(de.w);
-        const T fr = P.repulsive(de.w, fce, acc[0]), fa = P.B * exp(-P.l2 * de.w);
-        P.attractive_energy(de.w, fce, fa, o.x, b64, fr, acc[0]);
+        const T fr = P.repulsive(de.w, fce, acc[0]), fa = P.attractive(de.w, fa64);
+        P.attractive_energy(fce, fa, o.x, b64, fa64, fr, acc[0]);
     }
     for (int e = 0; e < cnt; ++e) {
         const vec4_t<T> de = dv[size_t(e) * N + i];
@@ -342,7 +360,8 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
         const T re = de.w, ire = T(1) / re;
         const T hx = de.x * ire, hy = de.y * ire, hz = de.z * ire;
         const T fce = P.fc(re), dfce = P.dfc(re);
-        const T fre = P.repulsive(re), fae = P.B * exp(-P.l2 * re);
+        double fa64;
+        const T fre = P.repulsive(re), fae = P.attractive(re, fa64);
         const T dV = dfce * (fre - be.x * fae) + fce * (-P.l1 * fre + be.x * P.l2 * fae);
         T px = T(0.5) * dV * hx, py = T(0.5) * dV * hy, pz = T(0.5) * dV * hz;
         const T pre_e = fce * fae * be.y;
@@ -358,7 +377,8 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
             T g, dg;
             P.g_dg(cs, g, dg);
             const T fcq = P.fc(rq);
-            const T pre_q = fcq * (P.B * exp(-P.l2 * rq)) * bq.y;
+            double faq64;
+            const T pre_q = fcq * P.attractive(rq, faq64) * bq.y;
             const T ang = T(0.5) * (pre_e * fcq + pre_q * fce) * dg;
             const T rad = T(0.5) * pre_q * dfce * g;
             px -= ang * cx + rad * hx;
@@ -404,15 +424,22 @@ __device__ void ts_reverse_candidates(const BandDev& b, BandState* st, int slot,
     if (missing) set_error(st, CFNEB_ENEIGH);
 }
 
+// Bonds held in LDS per thread, for atoms with at most this many (carbon: 3 or 4).
+#define TS_LDS_BONDS 4
+
 // Neighbours of atom i by the exact test of its candidates (as the candidate filter
 // does for LJ), then u_i, P_ij and the per-atom virial from the bond vectors; block
-// partials of (E, V) in FP64.  Up to four bonds never leave registers; an atom with
-// more writes its bond vectors and takes the general path.
+// partials of (E, V) in FP64.  The first four bonds go to this thread's LDS slots
+// (an LDS store at a per-lane index, where registers would need a select per slot)
+// and then to registers; an atom with more bonds writes them to global scratch and
+// takes the general path.
 template <typename T>
-__device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
+__device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, int tile, double* lds,
+                                     vec4_t<T>* lbond, int* lcid)
 {
-    constexpr int MB = 4;
-    const int i = tile * CFNEB_TILE + threadIdx.x;
+    constexpr int MB = TS_LDS_BONDS;
+    const int tid = threadIdx.x;
+    const int i = tile * CFNEB_TILE + tid;
     const size_t N = b.N;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < b.N) {
@@ -422,7 +449,7 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
         vec4_t<T>* Praw = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.ccap * N;
         gmem<vec4_t<T>>* __restrict__ Pout = gp(Praw);
         vec4_t<T>* dv = reinterpret_cast<vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
-        uint16_t* bcid = b.bcid + size_t(slot) * b.cap * N;
+        int* bcid = reinterpret_cast<int*>(b.bcid) + size_t(slot) * b.cap * N;
         double h[9];
         for (int q = 0; q < 9; ++q) h[q] = g.h[q];
         const double4 r4 = load4(R, i);
@@ -431,18 +458,11 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
         const double rc2 = b.rc2;
         const int cap = b.cap;
         if (b.skst[slot].rebuild) ts_reverse_candidates(b, st, slot, i, nc);
-        vec4_t<T> bond[MB];
-        int cid[MB];
-#pragma unroll
-        for (int s2 = 0; s2 < MB; ++s2) {
-            bond[s2] = vec4_t<T>{};
-            cid[s2] = 0;
-        }
-        vec4_t<T> zero{};
+        const vec4_t<T> zero{};
         int cnt = 0;
-        // two candidates at a time: carbon atoms have three or four, and a wider
-        // batch runs the whole exact test and bond insertion for slots most lanes lack
-        constexpr int U = 2;
+        // four candidates at a time (carbon atoms have three or four): one round of
+        // dependent loads for most atoms; the tests stop at the atom's last candidate
+        constexpr int U = 4;
         for (int e0 = 0; e0 < nc; e0 += U) {
             uint32_t ent[U];
             double4 rj[U];
@@ -468,16 +488,13 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
                     v.x = T(d[0]);
                     v.y = T(d[1]);
                     v.z = T(d[2]);
-                    v.w = T(sqrt(rr));
-#pragma unroll
-                    for (int s2 = 0; s2 < MB; ++s2)
-                        if (s2 == cnt) {
-                            bond[s2] = v;
-                            cid[s2] = e0 + u;
-                        }
-                    if (cnt >= MB) {
+                    v.w = sqrt(T(rr));  // the FP32 bond length from the rounded r^2
+                    if (cnt < MB) {
+                        lbond[cnt * CFNEB_TILE + tid] = v;
+                        lcid[cnt * CFNEB_TILE + tid] = e0 + u;
+                    } else {
                         dv[size_t(cnt) * N + i] = v;
-                        bcid[size_t(cnt) * N + i] = uint16_t(e0 + u);
+                        bcid[size_t(cnt) * N + i] = e0 + u;
                     }
                 }
                 ++cnt;
@@ -487,12 +504,14 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
         const int nb = min(cnt, cap);
         const TersoffT<T> P(b);
         if (nb <= MB) {
-            ts_atom_regs<T, MB>(P, bond, cid, Pout, N, i, nb, acc);
-        } else {
+            vec4_t<T> bond[MB];
 #pragma unroll
-            for (int s2 = 0; s2 < MB; ++s2) {
-                dv[size_t(s2) * N + i] = bond[s2];
-                bcid[size_t(s2) * N + i] = uint16_t(cid[s2]);
+            for (int e = 0; e < MB; ++e) bond[e] = (e < nb) ? lbond[e * CFNEB_TILE + tid] : zero;
+            ts_atom_regs<T, MB>(P, bond, lcid + tid, CFNEB_TILE, Pout, N, i, nb, acc);
+        } else {
+            for (int e = 0; e < MB; ++e) {
+                dv[size_t(e) * N + i] = lbond[e * CFNEB_TILE + tid];
+                bcid[size_t(e) * N + i] = lcid[e * CFNEB_TILE + tid];
             }
             vec2_t<T>* bo = reinterpret_cast<vec2_t<T>*>(b.bo) + size_t(slot) * b.cap * N;
             ts_atom_generic<T>(P, dv, bo, bcid, Praw, N, i, nb, acc);
@@ -509,12 +528,14 @@ template <typename T>
 __device__ void ts_filter_bonds_loop(const BatchDev& bd, int all_images, int variant)
 {
     __shared__ double lds[4 * 10];
+    __shared__ vec4_t<T> lbond[TS_LDS_BONDS * CFNEB_TILE];
+    __shared__ int lcid[TS_LDS_BONDS * CFNEB_TILE];
     ItemLoop loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         if (band_variant(b) != variant || band_stopped(b.st)) continue;  // uniform over the block
-        ts_filter_bonds_item<T>(b, b.st, b.st->slot[it.image], it.tile, lds);
+        ts_filter_bonds_item<T>(b, b.st, b.st->slot[it.image], it.tile, lds, lbond, lcid);
     }
 }
 
@@ -524,8 +545,8 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_filter_bonds(BatchDev bd, int
     ts_filter_bonds_loop<T>(bd, all_images, variant);
 }
 
-// FP32 bonds: four waves per SIMD (at most 128 VGPRs, a few bytes of spill); left
-// alone the FP64 energy terms take 135 VGPRs and the kernel runs 15% slower at three.
+// FP32 bonds: four waves per SIMD (at most 128 VGPRs); left alone the FP64 energy
+// terms take more registers and the kernel runs slower at three.
 template <>
 __global__ void __launch_bounds__(CFNEB_TILE) __attribute__((amdgpu_waves_per_eu(4)))
 k_ts_filter_bonds<float>(BatchDev bd, int all_images, int variant)
@@ -533,54 +554,18 @@ k_ts_filter_bonds<float>(BatchDev bd, int all_images, int variant)
     ts_filter_bonds_loop<float>(bd, all_images, variant);
 }
 
-// F_i = sum_c (P_c - P_rev(c)) over i's candidates, rev(c) = the slot of (i, -n) in
-// j's candidates; both P vanish unless the pair is a bond.  Four candidates at a
-// time: their slots, reverse slots and own P, then the reverse P, are in flight
-// together.
+// F_i = sum_c (P_c - P_rev(c)) over i's candidates (tersoff_gather), one atom per
+// thread.
 template <typename T>
 __device__ void ts_gather_item(const BandDev& b, BandState* st, int slot, int i)
 {
-    const size_t N = b.N;
-    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
-    const gmem<const uint16_t>* __restrict__ crev = gp<const uint16_t>(b.crev + size_t(slot) * b.ccap * N);
-    const gmem<const vec4_t<T>>* __restrict__ Pb =
-        gp<const vec4_t<T>>(reinterpret_cast<const vec4_t<T>*>(b.P) + size_t(slot) * b.ccap * N);
-    const int nc = gp<const int>(b.ncand)[size_t(slot) * N + i];
-    T fx = 0, fy = 0, fz = 0;
-    constexpr int U = 4;
-    for (int c0 = 0; c0 < nc; c0 += U) {
-        uint32_t ent[U];
-        int rv[U];
-        vec4_t<T> pe[U], pr[U];
-        // past the last candidate the loads repeat it (always in bounds, no branch
-        // between the loads) and the sum below stops
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t o = size_t(min(c0 + u, nc - 1)) * N + i;
-            ent[u] = cand[o];
-            rv[u] = int(crev[o]);
-            pe[u] = load4(Pb, o);
-        }
-        __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of their uses
-#pragma unroll
-        for (int u = 0; u < U; ++u) pr[u] = load4(Pb, size_t(rv[u]) * N + nbr_j(ent[u]));
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (c0 + u >= nc) break;
-            fx += pe[u].x;
-            fy += pe[u].y;
-            fz += pe[u].z;
-            fx -= pr[u].x;
-            fy -= pr[u].y;
-            fz -= pr[u].z;
-        }
-    }
+    T f[1][3];
+    tersoff_gather<T, 1>(b, slot, i, 0, f);
     gmem<T>* F = gp(reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b));
-    F[i] = fx;
-    F[b.ld + i] = fy;
-    F[2 * size_t(b.ld) + i] = fz;
-    if (!isfinite(double(fx) + double(fy) + double(fz))) set_error(st, CFNEB_ENONFINITE);
+    F[i] = f[0][0];
+    F[b.ld + i] = f[0][1];
+    F[2 * size_t(b.ld) + i] = f[0][2];
+    if (!isfinite(double(f[0][0]) + double(f[0][1]) + double(f[0][2]))) set_error(st, CFNEB_ENONFINITE);
 }
 
 // stage 0: bond orders, P_ij, energy and virial; stage 1: force gather
