@@ -306,10 +306,10 @@ int cfneb_record_neb_force(cfneb_band* b, int on);
  * The entries of atom i are every (j, n) != (i, 0) with
  *     r = (R_j - R_i) + ((n0 h_0 + n1 h_1) + n2 h_2),  (r_x r_x + r_y r_y) + r_z r_z < rc^2
  * each operation rounded on its own in FP64.  *total is the number of entries
- * (may exceed cap; then ent holds the first cap).  A Tersoff band's step keeps
- * per-candidate data only, so for it this call first re-runs the exact test of the
- * current candidates on the positions and cell of the last evaluation (one launch on
- * the band's stream, then a synchronisation); the set is the same. */
+ * (may exceed cap; then ent holds the first cap).  A step keeps per-candidate data
+ * only, so this call first re-runs the exact test of the current candidates on the
+ * positions and cell of the last evaluation (one launch on the band's stream, then a
+ * synchronisation); the set is the one the step's force kernels used. */
 int cfneb_neighbours(const cfneb_band* b, int k, int32_t* cnt, int32_t* ent, int64_t cap,
                      int64_t* total);
 

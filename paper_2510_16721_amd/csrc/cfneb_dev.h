@@ -9,7 +9,8 @@
 //   FN     [slot][3][ld]  FP64  NEB force (only when recording is on)
 //   binfo  [slot][N]      int4  (bin, rank in bin, packed lattice image) per atom
 //   bins   [slot][...]    int   counts, starts; bpos: atoms in bin order (R, packed id)
-//   nbr    [slot][cap][N] u32   packed neighbour entries, entry-major (coalesced)
+//   nbr    [slot][cap][N] u32   packed neighbour entries, entry-major (readouts only)
+//   cand   [slot][ccap][N] u32  candidates within rc + skin (atom index and shifts)
 //   ncnt   [slot][N]      int   neighbour count (may exceed cap: overflow)
 //   dvec   [slot][cap][N] T4    Tersoff: bond vector and length (bonds past the fourth)
 //   bo     [slot][cap][N] T2    Tersoff: b_ij and db/dzeta (same)
@@ -128,6 +129,7 @@ struct BandDev {
     double rc, rc2;
     double skin, rcl, rcl2;  // candidate skin, list cutoff rc + skin and its square
     double lj_eps, lj_sig2, lj_eshift;
+    int lj_lanes;  // lanes sharing an atom in the LJ force kernel (1, 2, 4 or 8)
     double ts_A, ts_B, ts_l1, ts_l2, ts_beta, ts_bn, ts_lnbeta, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
     double k_spring;
     int climb_after, cell_filter;

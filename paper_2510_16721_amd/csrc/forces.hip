@@ -19,45 +19,98 @@ namespace cfneb {
 
 // ------------------------------------------------------------ Lennard-Jones
 // U_i = 1/2 sum_j phi(r_ij), phi = 4 eps [(s/r)^12 - (s/r)^6] - phi(rc)
-template <typename T>
-__device__ void lj_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
+// Lennard-Jones straight from the candidates (Verlet skin): each candidate gets the
+// exact inclusion test and, if it is a neighbour, its pair term, so neither a packed
+// neighbour list nor a second gather of the positions is needed in a step.  K lanes
+// share an atom, taking candidates l, l + K, l + 2K, ... (lane l); the atom's force
+// is the fixed butterfly sum of its lanes, energy and virial go into the block sums.
+// A tile of 256 atoms is covered in K passes of 256 / K atoms.
+//
+// The inclusion test decides on the exact FP64 r^2 (every operation rounded on its
+// own): the separation d is formed in FP64 (a candidate without a lattice shift, most
+// of them in a large cell, skips the shift arithmetic, which adds an exact zero), and
+// its FP32 square, within 3e-7 of r^2 relative, settles every pair outside a 1e-6
+// band around rc^2; only pairs inside the band square d in FP64.  The virial of a
+// pair is symmetric (f parallel to d): six FP32 components, added to the FP64 sums once
+// per batch of four candidates.
+__device__ inline void separation(const double* ri, const double4& rj, const double* h, uint32_t ent,
+                                  double* d)
 {
-    const int i = tile * CFNEB_TILE + threadIdx.x;
+#pragma clang fp contract(off)
+    if ((ent >> 20) == 0x888u) {  // no lattice shift
+        d[0] = rj.x - ri[0];
+        d[1] = rj.y - ri[1];
+        d[2] = rj.z - ri[2];
+    } else {
+        const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
+        const double r[3] = {rj.x, rj.y, rj.z};
+        for (int c = 0; c < 3; ++c) {
+            const double sh = (double(n0) * h[c] + double(n1) * h[3 + c]) + double(n2) * h[6 + c];
+            d[c] = (r[c] - ri[c]) + sh;
+        }
+    }
+}
+
+__device__ inline bool exact_inside(const double* d, float r2f, float lo, float hi, double rc2)
+{
+#pragma clang fp contract(off)
+    if (r2f < lo) return true;
+    if (r2f >= hi) return false;
+    const double rr = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    return rr < rc2;
+}
+
+template <typename T, int K>
+__device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
+{
     const size_t N = b.N;
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // u, then V row-major
-    if (i < b.N) {
-        const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
-        const ImageGeom& g = b.geom[slot];
-        double h[9];
-        for (int q = 0; q < 9; ++q) h[q] = g.h[q];
-        const double4 ri = load4(R, i);
-        const double ri0 = ri.x, ri1 = ri.y, ri2 = ri.z;
-        const gmem<const uint32_t>* __restrict__ nbr = gp<const uint32_t>(b.nbr + size_t(slot) * b.cap * N);
-        const int cnt = min(gp<const int>(b.ncnt)[size_t(slot) * N + i], b.cap);
-        const T eps4 = T(4.0 * b.lj_eps), eps24 = T(24.0 * b.lj_eps), sig2 = T(b.lj_sig2),
-                esh = T(b.lj_eshift);
+    const int lane = int(threadIdx.x) % K;
+    const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
+    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
+    const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
+    gmem<T>* F = gp(reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b));
+    const ImageGeom& g = b.geom[slot];
+    double h[9];
+    for (int q = 0; q < 9; ++q) h[q] = g.h[q];
+    const double rc2 = b.rc2;
+    const float lo = float(rc2 * (1.0 - 1e-6)), hi = float(rc2 * (1.0 + 1e-6));
+    const T eps4 = T(4.0 * b.lj_eps), eps24 = T(24.0 * b.lj_eps), sig2 = T(b.lj_sig2), esh = T(b.lj_eshift);
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // u, then V xx yy zz xy xz yz
+    bool over = false, bad = false;
+#pragma unroll 1
+    for (int sub = 0; sub < K; ++sub) {
+        const int i = tile * CFNEB_TILE + sub * (CFNEB_TILE / K) + int(threadIdx.x) / K;
+        const bool in = i < b.N;
+        const int ii = in ? i : 0;
+        const double4 r4 = load4(R, ii);
+        const double ri[3] = {r4.x, r4.y, r4.z};
+        const int nc = in ? ncand[ii] : 0;
         T fx = 0, fy = 0, fz = 0;
-        // four neighbours at a time: their entries, then their positions, are in flight
-        // together (past the last neighbour the loads repeat it; the sums stop there)
+        int cnt = 0;
+        // four of the lane's candidates at a time: entries, then positions, in flight
+        // together (past the last candidate the loads repeat it; the tests stop there)
         constexpr int U = 4;
-        for (int e0 = 0; e0 < cnt; e0 += U) {
-            uint32_t ents[U];
-            double4 rjs[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) ents[u] = nbr[size_t(min(e0 + u, cnt - 1)) * N + i];
-#pragma unroll
-            for (int u = 0; u < U; ++u) rjs[u] = load4(R, nbr_j(ents[u]));
-            __builtin_amdgcn_sched_barrier(0);
+        for (int e0 = lane; e0 < nc; e0 += U * K) {
+            uint32_t ent[U];
+            double4 rj[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (e0 + u >= cnt) break;
-                const uint32_t ent = ents[u];
-                const int n0 = nbr_n(ent, 0), n1 = nbr_n(ent, 1), n2 = nbr_n(ent, 2);
-                const double4 rj = rjs[u];
-                const double d0 = (rj.x - ri0) + ((n0 * h[0] + n1 * h[3]) + n2 * h[6]);
-                const double d1 = (rj.y - ri1) + ((n0 * h[1] + n1 * h[4]) + n2 * h[7]);
-                const double d2 = (rj.z - ri2) + ((n0 * h[2] + n1 * h[5]) + n2 * h[8]);
-                const T dx = T(d0), dy = T(d1), dz = T(d2);
+                const int c = e0 + u * K;
+                ent[u] = cand[size_t(c < nc ? c : e0) * N + ii];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) rj[u] = load4(R, nbr_j(ent[u]));
+            __builtin_amdgcn_sched_barrier(0);
+            T w[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (e0 + u * K >= nc) break;
+                double d[3];
+                separation(ri, rj[u], h, ent[u], d);
+                const T dx = T(d[0]), dy = T(d[1]), dz = T(d[2]);
+                const float fdx = float(dx), fdy = float(dy), fdz = float(dz);
+                if (!exact_inside(d, fdx * fdx + fdy * fdy + fdz * fdz, lo, hi, rc2)) continue;
+                ++cnt;
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const T ir2 = T(1) / r2;
                 T s6 = sig2 * ir2;
@@ -70,32 +123,44 @@ __device__ void lj_item(const BandDev& b, BandState* st, int slot, int tile, dou
                 acc[0] += double(T(0.5) * phi);
                 const T hf = T(-0.5) * fr;
                 const T wx = hf * dx, wy = hf * dy, wz = hf * dz;
-                acc[1] += double(wx * dx);
-                acc[2] += double(wx * dy);
-                acc[3] += double(wx * dz);
-                acc[4] += double(wy * dx);
-                acc[5] += double(wy * dy);
-                acc[6] += double(wy * dz);
-                acc[7] += double(wz * dx);
-                acc[8] += double(wz * dy);
-                acc[9] += double(wz * dz);
+                w[0] += wx * dx;
+                w[1] += wy * dy;
+                w[2] += wz * dz;
+                w[3] += wx * dy;
+                w[4] += wx * dz;
+                w[5] += wy * dz;
             }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) acc[1 + q] += double(w[q]);
         }
-        gmem<T>* F = gp(reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b));
-        F[i] = fx;
-        F[b.ld + i] = fy;
-        F[2 * size_t(b.ld) + i] = fz;
-        if (!isfinite(double(fx) + double(fy) + double(fz))) set_error(st, CFNEB_ENONFINITE);
+        // the atom's lanes: fixed butterfly (K consecutive, aligned lanes)
+#pragma unroll
+        for (int off = K / 2; off > 0; off >>= 1) {
+            fx += __shfl_xor(fx, off, 64);
+            fy += __shfl_xor(fy, off, 64);
+            fz += __shfl_xor(fz, off, 64);
+            cnt += __shfl_xor(cnt, off, 64);
+        }
+        if (in && lane == 0) {
+            F[i] = fx;
+            F[b.ld + i] = fy;
+            F[2 * size_t(b.ld) + i] = fz;
+            over = over || cnt > b.cap;
+            bad = bad || !isfinite(double(fx) + double(fy) + double(fz));
+        }
     }
-    block_sum_t<10>(acc, lds);
+    if (over) set_error(st, CFNEB_ENEIGH);
+    if (bad) set_error(st, CFNEB_ENONFINITE);
+    double v[10] = {acc[0], acc[1], acc[4], acc[5], acc[4], acc[2], acc[6], acc[5], acc[6], acc[3]};
+    block_sum_t<10>(v, lds);
     if (threadIdx.x == 0) {
         double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
-        for (int q = 0; q < 10; ++q) out[q] = acc[q];
+        for (int q = 0; q < 10; ++q) out[q] = v[q];
     }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(CFNEB_TILE) k_lj(BatchDev bd, int all_images, int variant)
+__global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_images, int variant)
 {
     __shared__ double lds[4 * 10];
     ItemLoop loop(bd, KIND_ATOM, all_images);
@@ -104,7 +169,14 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj(BatchDev bd, int all_images, 
         const BandDev& b = bd.bands[it.band];
         BandState* st = b.st;
         if (band_variant(b) != variant || band_stopped(st)) continue;  // uniform over the block
-        lj_item<T>(b, st, st->slot[it.image], it.tile, lds);
+        const int slot = st->slot[it.image];
+        switch (b.lj_lanes) {  // uniform over the block
+        case 1: lj_cand_item<T, 1>(b, st, slot, it.tile, lds); break;
+        case 2: lj_cand_item<T, 2>(b, st, slot, it.tile, lds); break;
+        case 4: lj_cand_item<T, 4>(b, st, slot, it.tile, lds); break;
+        case 8: lj_cand_item<T, 8>(b, st, slot, it.tile, lds); break;
+        default: lj_cand_item<T, 1>(b, st, slot, it.tile, lds); break;
+        }
     }
 }
 
@@ -123,13 +195,16 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BatchDev bd, int al
     }
 }
 
-// stage 0: LJ, or Tersoff bond orders and dU_i/dr^ij; 1: Tersoff gather
+// stage 0: LJ from the candidates, or Tersoff bond orders and dU_i/dr^ij; 1: Tersoff
+// gather
 void launch_force_stage(const Launch& L, int all_images, int stage, hipStream_t s)
 {
     const unsigned g = L.g_force;
     if (stage == 0) {
-        if (L.variants & (1u << VARIANT_LJ32)) k_lj<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ32);
-        if (L.variants & (1u << VARIANT_LJ64)) k_lj<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ64);
+        if (L.variants & (1u << VARIANT_LJ32))
+            k_lj_cand<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ32);
+        if (L.variants & (1u << VARIANT_LJ64))
+            k_lj_cand<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ64);
     }
     launch_tersoff_stage(L, all_images, stage, s);
 }

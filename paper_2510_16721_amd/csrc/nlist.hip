@@ -24,9 +24,9 @@
 //   k_bin_sort     (rebuilds) sort each bin by atom id, so lists are deterministic
 //   k_cand         (rebuilds) stencil walk over bin-ordered records, pairs within rcl,
 //                  packed entry-major candidate lists; R_ref = R
-//   k_filter       (LJ; Tersoff for a host readout only: its bond kernel tests the
-//                  candidates itself) exact test of every candidate, packed
-//                  entry-major neighbour lists (entry e of atom i at [e][i])
+//   k_filter       (host readouts only: the force kernels test their candidates
+//                  themselves) exact test of every candidate, packed entry-major
+//                  neighbour lists (entry e of atom i at [e][i])
 #include <type_traits>
 
 #include "cfneb_dev.h"
@@ -517,23 +517,22 @@ void launch_list(const Launch& L, int all_images, hipStream_t s)
     k_cand<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, all_images);
 }
 
-// LJ bands; Tersoff bands test their candidates inside the bond kernel.
+// The force kernels of both potentials test their candidates themselves; a step
+// writes no packed neighbour list.
 void launch_filter(const Launch& L, int all_images, hipStream_t s)
 {
-    const unsigned g = L.g[KIND_ATOM];
-    const unsigned lj = L.variants & ((1u << VARIANT_LJ32) | (1u << VARIANT_LJ64));
-    if (lj) k_filter<<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, lj, 0);
+    (void)L;
+    (void)all_images;
+    (void)s;
 }
 
-// Packed neighbour lists of every image of the table's Tersoff bands, for a host
-// readout (their step path keeps per-candidate data only): the exact test of the
-// current candidates on the positions and cell of the last evaluation.
+// Packed neighbour lists of every image of the table, for a host readout (the step
+// path keeps candidates only): the exact test of the current candidates on the
+// positions and cell of the last evaluation.
 void launch_neighbour_lists(const Launch& L, hipStream_t s)
 {
-    const unsigned ts = L.variants & ((1u << VARIANT_TS32) | (1u << VARIANT_TS64));
-    if (!ts) return;
     launch_plan(L, 1, 1, s);
-    k_filter<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, 1, ts, 1);
+    k_filter<<<L.g[KIND_ATOM], CFNEB_TILE, 0, s>>>(L.bd, 1, (1u << NVARIANT) - 1u, 1);
 }
 
 }  // namespace cfneb

@@ -197,6 +197,19 @@ double default_cell_factor(const double* h0, int n)
     return std::cbrt(std::fabs(det)) * std::pow(double(n), 1.0 / 6.0);
 }
 
+// Lanes sharing an atom in the LJ force kernel, by the band's size class (a fixed
+// rule, so a band takes the same path alone and in a batch).
+int lj_lanes_for(int n_atoms)
+{
+    const char* v = std::getenv("CFNEB_LJ_LANES");
+    if (v) {
+        const int k = std::atoi(v);
+        if (k == 1 || k == 2 || k == 4 || k == 8) return k;
+    }
+    (void)n_atoms;
+    return 1;
+}
+
 void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
 {
     const cfneb_params* p = &b->p;
@@ -224,6 +237,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.rcl = d.rc + d.skin;
     d.rcl2 = d.rcl * d.rcl;
     d.lj_eps = p->lj_eps;
+    d.lj_lanes = lj_lanes_for(L.N);
     d.lj_sig2 = p->lj_sigma * p->lj_sigma;
     if (p->lj_shift) {
         const double q = d.lj_sig2 / (p->lj_rc * p->lj_rc);
@@ -1074,11 +1088,9 @@ int cfneb_neighbours(const cfneb_band* cb, int k, int32_t* cnt, int32_t* ent, in
     const int slot = image_slot(b, k);
     if (slot < 0) return CFNEB_EINVAL;
     const size_t N = size_t(b->L.N), C = size_t(b->L.cap);
-    if (b->L.tersoff) {
-        launch_neighbour_lists(b->launch, b->stream);
-        HIP_TRY(b, hipGetLastError());
-        HIP_TRY(b, hipStreamSynchronize(b->stream));
-    }
+    launch_neighbour_lists(b->launch, b->stream);
+    HIP_TRY(b, hipGetLastError());
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
     std::vector<uint32_t> nb(C * N);
     HIP_TRY(b, hipMemcpy(cnt, b->d.ncnt + size_t(slot) * N, N * 4, hipMemcpyDeviceToHost));
     HIP_TRY(b, hipMemcpy(nb.data(), b->d.nbr + size_t(slot) * C * N, nb.size() * 4, hipMemcpyDeviceToHost));

