@@ -4,7 +4,9 @@
 //   X      [slot][3][ld]  FP64  generalized coordinates: rows 0..N-1 = R~ (SoA),
 //                               rows N..N+2 = the three rows of c_f B
 //   V      [2][slot][3][ld] FP64 FIRE velocities, ping-pong (vcur selects)
-//   R      [slot][3][ld]  FP64  Cartesian positions R = R~ D of the last evaluation
+//   R      [slot][ld]     32 B  Cartesian positions R = R~ D of the last evaluation
+//   S      [slot][ld]     16 B  FP32 LJ bands: fractional coordinates of R in the
+//                               image's cell, wrapped to [0, 1), as 32-bit fixed point
 //   F      [slot][3][ld]  T     Cartesian forces (T = float, or double for FP64 bands)
 //   FN     [slot][3][ld]  FP64  NEB force (only when recording is on)
 //   binfo  [slot][N]      int4  (bin, rank in bin, packed lattice image) per atom
@@ -69,6 +71,13 @@ struct ImageGeom {
     // strain since the last candidate build: h = h_ref (I + E), and |E|_F
     double E[9];
     double enorm;
+    // Fixed-point separations (FP32 LJ bands): wrap = 1 when every candidate's
+    // fractional separation stays within half a cell on each axis, so the wrapped
+    // 32-bit difference of two fixed-point coordinates is the separation itself; an
+    // FP32 r^2 from it below r2lo is inside rc, at or above r2hi outside, and between
+    // the two the exact FP64 test decides.
+    int wrap;
+    float r2lo, r2hi;
 };
 
 // Candidate lists of one image slot (Verlet skin).  The candidates are every pair
@@ -129,7 +138,6 @@ struct BandDev {
     double rc, rc2;
     double skin, rcl, rcl2;  // candidate skin, list cutoff rc + skin and its square
     double lj_eps, lj_sig2, lj_eshift;
-    int lj_lanes;  // lanes sharing an atom in the LJ force kernel (1, 2, 4 or 8)
     double ts_A, ts_B, ts_l1, ts_l2, ts_beta, ts_bn, ts_lnbeta, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
     double k_spring;
     int climb_after, cell_filter;
@@ -147,6 +155,7 @@ struct BandDev {
     double* X;
     double* V;
     double* R;
+    uint4* S;           // FP32 LJ bands, else null
     void* F;
     double* FN;
     int4* binfo;
@@ -230,6 +239,7 @@ __device__ inline double* Vs(const BandDev& b, int buf, int slot)
 // Cartesian positions R = R~ D, one 32-byte record (x, y, z, 0) per atom, so a
 // neighbour's position is one aligned load.
 __device__ inline double4* Rs(const BandDev& b, int slot) { return reinterpret_cast<double4*>(b.R) + size_t(slot) * b.ld; }
+__device__ inline uint4* Ss(const BandDev& b, int slot) { return b.S + size_t(slot) * b.ld; }
 
 __device__ inline uint32_t pack_nbr(int j, int n0, int n1, int n2)
 {
@@ -466,6 +476,7 @@ struct Launch {
     // slots free first; chosen by timing before the step graphs are captured
     unsigned g_force, g_force_tile;
     unsigned variants;
+    int lj_lanes;  // lanes sharing an atom in the LJ force kernel (1, 2, 4 or 8)
 };
 
 __device__ inline void set_error(BandState* st, int code)

@@ -51,13 +51,18 @@ __device__ inline void separation(const double* ri, const double4& rj, const dou
     }
 }
 
-__device__ inline bool exact_inside(const double* d, float r2f, float lo, float hi, double rc2)
+// r^2 as the definition rounds it: each product and sum on its own
+__device__ inline double exact_r2(const double* d)
 {
 #pragma clang fp contract(off)
+    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+__device__ inline bool exact_inside(const double* d, float r2f, float lo, float hi, double rc2)
+{
     if (r2f < lo) return true;
     if (r2f >= hi) return false;
-    const double rr = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-    return rr < rc2;
+    return exact_r2(d) < rc2;
 }
 
 template <typename T, int K>
@@ -159,7 +164,124 @@ __device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile
     }
 }
 
-template <typename T>
+// FP32 bands whose cell is wide enough (ImageGeom::wrap): the separation comes from
+// the fixed-point fractional coordinates, one 16-byte gather per candidate and no
+// lattice-shift arithmetic: the wrapped 32-bit difference of two coordinates is the
+// fractional separation times 2^32, and d = (that difference) (h 2^-32) in FP64, then
+// rounded to FP32 per pair (an FP32 h would scale every separation by the same
+// rounding error, a strain of ~1e-7 that the virial sum multiplies by the stiffness).
+// The FP32 r^2 settles the pair outside [r2lo, r2hi); inside that band the exact FP64
+// test runs on the FP64 positions.
+template <int K>
+__device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
+{
+    const size_t N = b.N;
+    const int lane = int(threadIdx.x) % K;
+    const gmem<const uint4>* __restrict__ S = gp<const uint4>(Ss(b, slot));
+    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
+    const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
+    gmem<float>* F = gp(reinterpret_cast<float*>(b.F) + size_t(slot) * slot_rows(b));
+    const gmem<const ImageGeom>* g = gp<const ImageGeom>(b.geom + slot);
+    double H[9];  // h 2^-32, exact
+#pragma unroll
+    for (int q = 0; q < 9; ++q) H[q] = g->h[q] * 0x1p-32;
+    const float lo = g->r2lo, hi = g->r2hi;
+    const double rc2 = b.rc2;
+    const float eps4 = float(4.0 * b.lj_eps), eps24 = float(24.0 * b.lj_eps), sig2 = float(b.lj_sig2),
+                esh = float(b.lj_eshift);
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // u, then V xx yy zz xy xz yz
+    bool over = false, bad = false;
+#pragma unroll 1
+    for (int sub = 0; sub < K; ++sub) {
+        const int i = tile * CFNEB_TILE + sub * (CFNEB_TILE / K) + int(threadIdx.x) / K;
+        const bool in = i < b.N;
+        const int ii = in ? i : 0;
+        const uint4 si = load4(S, ii);
+        const int nc = in ? ncand[ii] : 0;
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        int cnt = 0;
+        constexpr int U = 4;
+        for (int e0 = lane; e0 < nc; e0 += U * K) {
+            uint32_t ent[U];
+            uint4 sj[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = e0 + u * K;
+                ent[u] = cand[size_t(c < nc ? c : e0) * N + ii];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) sj[u] = load4(S, nbr_j(ent[u]));
+            __builtin_amdgcn_sched_barrier(0);
+            float w[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (e0 + u * K >= nc) break;
+                const double a0 = double(int(sj[u].x - si.x));
+                const double a1 = double(int(sj[u].y - si.y));
+                const double a2 = double(int(sj[u].z - si.z));
+                const float dx = float(a0 * H[0] + a1 * H[3] + a2 * H[6]);
+                const float dy = float(a0 * H[1] + a1 * H[4] + a2 * H[7]);
+                const float dz = float(a0 * H[2] + a1 * H[5] + a2 * H[8]);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= hi) continue;
+                if (r2 >= lo) {  // rare: the exact FP64 test on the FP64 positions
+                    const gmem<const double4>* R = gp<const double4>(Rs(b, slot));
+                    const double4 r4 = load4(R, ii);
+                    const double ri[3] = {r4.x, r4.y, r4.z};
+                    double h[9];
+                    for (int q = 0; q < 9; ++q) h[q] = g->h[q];
+                    double d[3];
+                    separation(ri, load4(R, nbr_j(ent[u])), h, ent[u], d);
+                    if (!(exact_r2(d) < rc2)) continue;
+                }
+                ++cnt;
+                const float ir2 = 1.f / r2;
+                float s6 = sig2 * ir2;
+                s6 = s6 * s6 * s6;
+                const float fr = eps24 * (s6 - 2.f * s6 * s6) * ir2;  // phi'(r) / r
+                fx += fr * dx;
+                fy += fr * dy;
+                fz += fr * dz;
+                w[0] += eps4 * (s6 * s6 - s6) - esh;
+                const float hf = -0.5f * fr;
+                const float wx = hf * dx, wy = hf * dy, wz = hf * dz;
+                w[1] += wx * dx;
+                w[2] += wy * dy;
+                w[3] += wz * dz;
+                w[4] += wx * dy;
+                w[5] += wx * dz;
+                w[6] += wy * dz;
+            }
+            acc[0] += 0.5 * double(w[0]);
+#pragma unroll
+            for (int q = 1; q < 7; ++q) acc[q] += double(w[q]);
+        }
+#pragma unroll
+        for (int off = K / 2; off > 0; off >>= 1) {
+            fx += __shfl_xor(fx, off, 64);
+            fy += __shfl_xor(fy, off, 64);
+            fz += __shfl_xor(fz, off, 64);
+            cnt += __shfl_xor(cnt, off, 64);
+        }
+        if (in && lane == 0) {
+            F[i] = fx;
+            F[b.ld + i] = fy;
+            F[2 * size_t(b.ld) + i] = fz;
+            over = over || cnt > b.cap;
+            bad = bad || !isfinite(double(fx) + double(fy) + double(fz));
+        }
+    }
+    if (over) set_error(st, CFNEB_ENEIGH);
+    if (bad) set_error(st, CFNEB_ENONFINITE);
+    double v[10] = {acc[0], acc[1], acc[4], acc[5], acc[4], acc[2], acc[6], acc[5], acc[6], acc[3]};
+    block_sum_t<10>(v, lds);
+    if (threadIdx.x == 0) {
+        double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
+        for (int q = 0; q < 10; ++q) out[q] = v[q];
+    }
+}
+
+template <typename T, int K>
 __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_images, int variant)
 {
     __shared__ double lds[4 * 10];
@@ -170,13 +292,25 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_ima
         BandState* st = b.st;
         if (band_variant(b) != variant || band_stopped(st)) continue;  // uniform over the block
         const int slot = st->slot[it.image];
-        switch (b.lj_lanes) {  // uniform over the block
-        case 1: lj_cand_item<T, 1>(b, st, slot, it.tile, lds); break;
-        case 2: lj_cand_item<T, 2>(b, st, slot, it.tile, lds); break;
-        case 4: lj_cand_item<T, 4>(b, st, slot, it.tile, lds); break;
-        case 8: lj_cand_item<T, 8>(b, st, slot, it.tile, lds); break;
-        default: lj_cand_item<T, 1>(b, st, slot, it.tile, lds); break;
+        if constexpr (std::is_same<T, float>::value) {
+            if (b.geom[slot].wrap) {  // uniform over the block
+                lj_fixed_item<K>(b, st, slot, it.tile, lds);
+                continue;
+            }
         }
+        lj_cand_item<T, K>(b, st, slot, it.tile, lds);
+    }
+}
+
+template <typename T>
+void launch_lj(const Launch& L, int all_images, int variant, hipStream_t s)
+{
+    const unsigned g = L.g_force;
+    switch (L.lj_lanes) {
+    case 2: k_lj_cand<T, 2><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
+    case 4: k_lj_cand<T, 4><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
+    case 8: k_lj_cand<T, 8><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
+    default: k_lj_cand<T, 1><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
     }
 }
 
@@ -199,12 +333,9 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_image_reduce(BatchDev bd, int al
 // gather
 void launch_force_stage(const Launch& L, int all_images, int stage, hipStream_t s)
 {
-    const unsigned g = L.g_force;
     if (stage == 0) {
-        if (L.variants & (1u << VARIANT_LJ32))
-            k_lj_cand<float><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ32);
-        if (L.variants & (1u << VARIANT_LJ64))
-            k_lj_cand<double><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, VARIANT_LJ64);
+        if (L.variants & (1u << VARIANT_LJ32)) launch_lj<float>(L, all_images, VARIANT_LJ32, s);
+        if (L.variants & (1u << VARIANT_LJ64)) launch_lj<double>(L, all_images, VARIANT_LJ64, s);
     }
     launch_tersoff_stage(L, all_images, stage, s);
 }

@@ -127,6 +127,32 @@ __device__ __forceinline__ bool image_geometry(const BandDev& b, const double* X
     return true;
 }
 
+// Between candidate builds every candidate is closer than rcl + skin (the skin test
+// rebuilds before 2 max|displacement| + rcl |E| reaches the skin), so when that stays
+// under half of each perpendicular width w_k, every candidate's fractional separation
+// is inside (-1/2, 1/2) and the wrapped 32-bit fixed-point difference is exact.
+// The separation from such a difference (3x3 product with h 2^-32 in FP64, within
+// 3 2^-53 kappa |d|, kappa = |h|_F |h^-1|_F; 2^-32 sqrt(3) |h|_F from rounding the
+// coordinates), rounded to FP32 and squared in FP32 (u = 2^-24: within 8u relative
+// in r^2), gives an r^2 within twice that relative bound (taken at |d| = rc) of the
+// exact one; the band around rc^2 where the FP64 test decides is twice that again.
+__device__ __forceinline__ void fixed_point_bounds(const BandDev& b, ImageGeom& g)
+{
+    double hf = 0.0, hif = 0.0;
+    for (int q = 0; q < 9; ++q) {
+        hf += g.h[q] * g.h[q];
+        hif += g.hinv[q] * g.hinv[q];
+    }
+    hf = sqrt(hf);
+    hif = sqrt(hif);
+    const double u = 0x1p-24;
+    const double rel = 2.0 * (8.0 * u + 2.0 * (3.0 * 0x1p-53 * hf * hif + 0x1p-32 * 1.7320508075688772 * hf / b.rc));
+    const double wmin = fmin(g.w[0], fmin(g.w[1], g.w[2]));
+    g.wrap = (g.err == 0 && rel < 1e-3 && (b.rcl + b.skin) * (1.0 + 1e-6) < 0.5 * wmin) ? 1 : 0;
+    g.r2lo = float(b.rc2 * (1.0 - rel));
+    g.r2hi = float(b.rc2 * (1.0 + rel));
+}
+
 // Geometry of image k of band b and its strain since the candidate build.
 __device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int k)
 {
@@ -148,6 +174,7 @@ __device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int 
     } else {
         for (int q = 0; q < 9; ++q) g.E[q] = 0.0;
     }
+    fixed_point_bounds(b, g);
     b.geom[slot] = g;
 }
 

@@ -13,7 +13,8 @@
 // (r + d_i + d_j) / (1 - |E|), so 2 max d_i + rcl |E| < skin keeps the list complete.
 //
 // Kernels, in order (each a persistent walk over the items of every live band):
-//   k_skin_check   R = R~ D; max_i d_i^2 per 1024-atom tile
+//   k_skin_check   R = R~ D (and its fixed-point fractional coordinates); max_i d_i^2
+//                  per 1024-atom tile
 //   k_skin_decide  max over an image's tiles, rebuild flag per image; a rebuild takes
 //                  the current cell as reference
 //   k_bin_assign   (rebuilds) wrapped fractional coordinate, bin id; the count atomic
@@ -43,10 +44,26 @@ __device__ inline long long pack_info(int j, int n0, int n1, int n2)
 __device__ inline int info_j(long long v) { return int(v & 0xFFFFF); }
 __device__ inline int info_n(long long v, int k) { return int((v >> (20 + 10 * k)) & 0x3FF) - 512; }
 
+// Fractional coordinates s = R h^-1 wrapped to [0, 1) and rounded to multiples of
+// 2^-32 (1.0 wraps to 0); a non-finite coordinate gives 0 (the energy check reports
+// the band).
+__device__ inline uint4 fixed_fraction(const double* r, const double* hi)
+{
+    uint32_t u[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double s = (r[0] * hi[q] + r[1] * hi[3 + q]) + r[2] * hi[6 + q];
+        const double t = isfinite(s) ? s - floor(s) : 0.0;
+        u[q] = uint32_t((unsigned long long)(long long)rint(t * 0x1p32));
+    }
+    return make_uint4(u[0], u[1], u[2], 0u);
+}
+
 // 1024 atoms per item, four per thread: all loads of the four atoms are issued before
-// any position is stored.  R = R~ D; d_i^2 against the strained reference when a list
-// exists; the tile's maximum goes to its own slot (no atomics: many tiles per image
-// would contend on one address).
+// any position is stored.  R = R~ D (and its fixed-point fractional coordinates for
+// FP32 LJ bands); d_i^2 against the strained reference when a list exists; the tile's
+// maximum goes to its own slot (no atomics: many tiles per image would contend on one
+// address).
 __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_images)
 {
     __shared__ double lds[CFNEB_TILE / 64];
@@ -59,13 +76,15 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
         if (band_stopped(st)) continue;  // uniform over the block
         const int slot = st->slot[it.image];
         const gmem<const ImageGeom>* g = gp<const ImageGeom>(b.geom + slot);
-        double D[9], E[9];
+        double D[9], E[9], hi[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             D[q] = g->D[q];
             E[q] = g->E[q];
+            hi[q] = g->hinv[q];
         }
         const bool valid = b.skst[slot].valid != 0;
+        gmem<uint4>* __restrict__ S = b.S ? gp(Ss(b, slot)) : nullptr;
         const gmem<const double>* __restrict__ X = gp<const double>(Xs(b, slot));
         const gmem<const double>* __restrict__ Rr = gp<const double>(b.Rref + size_t(slot) * slot_rows(b));
         double x[Q][3], a[Q][3];
@@ -88,6 +107,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
             double r[3];
             for (int c = 0; c < 3; ++c) r[c] = (x[q][0] * D[c] + x[q][1] * D[3 + c]) + x[q][2] * D[6 + c];
             store4(R, i, make_double4(r[0], r[1], r[2], 0.0));
+            if (S) store4(S, i, fixed_fraction(r, hi));
             if (valid) {
                 double d2 = 0.0;
                 for (int c = 0; c < 3; ++c) {

@@ -24,7 +24,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     int N, ld, Mcap, ntA, ntR, ntR4, nbcap, cap, ccap, fp64, tersoff;
-    size_t X, V, R, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, bcid, P, crev, geom,
+    size_t X, V, R, S, F, FN, binfo, bcount, bstart, bpos, nbr, ncnt, cand, ncand, Rref, skin, dvec, bo, bcid, P, crev, geom,
         scal, dotred, skmax,
         evpart, dotpart, maxpart, refpart, staging, state, table, live, plan, total;
 };
@@ -63,6 +63,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->X = take(M * rows * 8);
     L->V = take(2 * M * rows * 8);
     L->R = take(M * size_t(L->ld) * 32);
+    L->S = take(L->tersoff || L->fp64 ? 0 : M * size_t(L->ld) * 16);
     L->F = take(M * rows * tsz);
     L->FN = take(M * rows * 8);
     L->binfo = take(M * N * 16);
@@ -98,6 +99,19 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     return true;
 }
 
+// Lanes sharing an atom in the LJ force kernel: one (measured fastest of 1, 2, 4 and
+// 8 on the 97,555-atom band), or CFNEB_LJ_LANES; one rule for the whole process, so a
+// band takes the same path alone and in a batch.
+int lj_lanes()
+{
+    const char* v = std::getenv("CFNEB_LJ_LANES");
+    if (v) {
+        const int k = std::atoi(v);
+        if (k == 1 || k == 2 || k == 4 || k == 8) return k;
+    }
+    return 1;
+}
+
 // Grids of a band table, bounded by the most items its bands can hold.
 void size_grids(Launch& L, long long atom_tiles, long long row_tiles, long long bin_tiles, long long images,
                 int bands, long long atom4_tiles, long long row4_tiles)
@@ -113,6 +127,7 @@ void size_grids(Launch& L, long long atom_tiles, long long row_tiles, long long 
     L.g[KIND_BAND] = grid_for(bands, CFNEB_GRID_BANDS);
     L.g_force_tile = grid_for(atom_tiles, CFNEB_GRID_FORCE);
     L.g_force = L.g_force_tile;
+    L.lj_lanes = lj_lanes();
 }
 
 const char* err_text(int code)
@@ -197,19 +212,6 @@ double default_cell_factor(const double* h0, int n)
     return std::cbrt(std::fabs(det)) * std::pow(double(n), 1.0 / 6.0);
 }
 
-// Lanes sharing an atom in the LJ force kernel, by the band's size class (a fixed
-// rule, so a band takes the same path alone and in a batch).
-int lj_lanes_for(int n_atoms)
-{
-    const char* v = std::getenv("CFNEB_LJ_LANES");
-    if (v) {
-        const int k = std::atoi(v);
-        if (k == 1 || k == 2 || k == 4 || k == 8) return k;
-    }
-    (void)n_atoms;
-    return 1;
-}
-
 void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
 {
     const cfneb_params* p = &b->p;
@@ -237,7 +239,6 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.rcl = d.rc + d.skin;
     d.rcl2 = d.rcl * d.rcl;
     d.lj_eps = p->lj_eps;
-    d.lj_lanes = lj_lanes_for(L.N);
     d.lj_sig2 = p->lj_sigma * p->lj_sigma;
     if (p->lj_shift) {
         const double q = d.lj_sig2 / (p->lj_rc * p->lj_rc);
@@ -296,6 +297,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.X = reinterpret_cast<double*>(base + L.X);
     d.V = reinterpret_cast<double*>(base + L.V);
     d.R = reinterpret_cast<double*>(base + L.R);
+    d.S = (L.tersoff || d.fp64) ? nullptr : reinterpret_cast<uint4*>(base + L.S);
     d.F = base + L.F;
     d.FN = reinterpret_cast<double*>(base + L.FN);
     d.binfo = reinterpret_cast<int4*>(base + L.binfo);

@@ -18,6 +18,19 @@ def workload(name):
         return W.fcc_vacancy_hop(2, 2, 2, 1.5496), "lj"
     if name == "lj_ragged":
         return W.fcc_vacancy_hop(5, 4, 4, 1.5496), "lj"  # 319 atoms: two tiles, ragged tail
+    if name == "lj863":
+        # 6x6x6 cells: every perpendicular width is above twice rc + 2 skin, so the FP32
+        # force kernel takes fixed-point separations; 863 atoms = 3 tiles + 95
+        return W.fcc_vacancy_hop(6, 6, 6, 1.5496), "lj"
+    if name == "lj863_sheared":
+        # the same lattice and cells under a shear (off-diagonal cell entries, a
+        # triclinic cell): the 3x3 product of the fixed-point separations
+        w = W.fcc_vacancy_hop(6, 6, 6, 1.5496)
+        S = np.array([[1.0, 0.08, -0.05], [0.0, 1.0, 0.11], [0.0, 0.0, 1.0]])
+        w = dict(w)
+        for k in ("pos_init", "pos_final", "cell_init", "cell_final"):
+            w[k] = w[k] @ S
+        return w, "lj"
     if name == "ts_small":
         return W.small_graphite(), "ts"
     if name == "ts_diamond":
