@@ -201,6 +201,27 @@ __device__ inline gmem<T>* gp(T* p)
 {
     return (gmem<T>*)p;
 }
+// Values that are the same for every lane (band fields, the potential's parameters):
+// marking them uniform lets the compiler keep them in scalar registers, and a pointer
+// so marked serves as the scalar base of a load with a 32-bit lane offset.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline unsigned long long uni(unsigned long long v)
+{
+    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(v & 0xffffffffull)));
+    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(v >> 32)));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline double uni(double v)
+{
+    return __longlong_as_double((long long)uni((unsigned long long)__double_as_longlong(v)));
+}
+template <typename T>
+__device__ inline T* uni(T* p)
+{
+    return reinterpret_cast<T*>(uni((unsigned long long)reinterpret_cast<uintptr_t>(p)));
+}
+
 // HIP's vector structs cannot be copied through such a view; these move them as
 // native 4-vectors.
 template <typename T>

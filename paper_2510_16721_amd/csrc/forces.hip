@@ -172,34 +172,54 @@ __device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile
 // rounding error, a strain of ~1e-7 that the virial sum multiplies by the stiffness).
 // The FP32 r^2 settles the pair outside [r2lo, r2hi); inside that band the exact FP64
 // test runs on the FP64 positions.
+// Loads at a 32-bit byte offset from a uniform base (one address add per load).
+__device__ inline uint32_t ld_u32(const void* base, uint32_t off)
+{
+    return *reinterpret_cast<const gmem<const uint32_t>*>(gp(static_cast<const char*>(base)) + off);
+}
+__device__ inline uint4 ld_u128(const void* base, uint32_t off)
+{
+    const nvec4<uint32_t> v =
+        *reinterpret_cast<const gmem<const nvec4<uint32_t>>*>(gp(static_cast<const char*>(base)) + off);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <int K>
 __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
 {
-    const size_t N = b.N;
+    // band fields as uniform locals: read once, held in scalar registers
+    const int Ni = uni(b.N), ld = uni(b.ld), cap = uni(b.cap);
+    const uint32_t N = uint32_t(Ni);
     const int lane = int(threadIdx.x) % K;
-    const gmem<const uint4>* __restrict__ S = gp<const uint4>(Ss(b, slot));
-    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
-    const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
-    gmem<float>* F = gp(reinterpret_cast<float*>(b.F) + size_t(slot) * slot_rows(b));
+    const uint4* S = uni(Ss(b, slot));
+    const uint32_t* cand = uni(b.cand + size_t(slot) * b.ccap * N);
+    const gmem<const int>* __restrict__ ncand = gp<const int>(uni(b.ncand + size_t(slot) * N));
+    gmem<float>* F = gp(uni(reinterpret_cast<float*>(b.F) + size_t(slot) * slot_rows(b)));
+    const gmem<const double4>* R = gp<const double4>(uni(Rs(b, slot)));
     const gmem<const ImageGeom>* g = gp<const ImageGeom>(b.geom + slot);
-    double H[9];  // h 2^-32, exact
+    double h[9], H[9];  // h, and h 2^-32 (exact)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) H[q] = g->h[q] * 0x1p-32;
-    const float lo = g->r2lo, hi = g->r2hi;
-    const double rc2 = b.rc2;
-    const float eps4 = float(4.0 * b.lj_eps), eps24 = float(24.0 * b.lj_eps), sig2 = float(b.lj_sig2),
-                esh = float(b.lj_eshift);
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // u, then V xx yy zz xy xz yz
+    for (int q = 0; q < 9; ++q) {
+        h[q] = uni(g->h[q]);
+        H[q] = h[q] * 0x1p-32;
+    }
+    const float lo = uni(g->r2lo), hi = uni(g->r2hi);
+    const double rc2 = uni(b.rc2);
+    const float eps4 = uni(float(4.0 * b.lj_eps)), eps24 = uni(float(24.0 * b.lj_eps)), sig2 = uni(float(b.lj_sig2)),
+                esh = uni(float(b.lj_eshift));
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // 2 u, then -2 V: xx yy zz xy xz yz
     bool over = false, bad = false;
 #pragma unroll 1
     for (int sub = 0; sub < K; ++sub) {
         const int i = tile * CFNEB_TILE + sub * (CFNEB_TILE / K) + int(threadIdx.x) / K;
-        const bool in = i < b.N;
-        const int ii = in ? i : 0;
-        const uint4 si = load4(S, ii);
+        const bool in = i < Ni;
+        const uint32_t ii = in ? uint32_t(i) : 0u;
+        const uint4 si = ld_u128(S, ii * 16u);
         const int nc = in ? ncand[ii] : 0;
         float fx = 0.f, fy = 0.f, fz = 0.f;
         int cnt = 0;
+        // four of the lane's candidates at a time, loads first; past the last candidate
+        // the loads repeat the batch's first and the pair is masked out
         constexpr int U = 4;
         for (int e0 = lane; e0 < nc; e0 += U * K) {
             uint32_t ent[U];
@@ -207,15 +227,14 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int c = e0 + u * K;
-                ent[u] = cand[size_t(c < nc ? c : e0) * N + ii];
+                ent[u] = ld_u32(cand, (uint32_t(c < nc ? c : e0) * N + ii) * 4u);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) sj[u] = load4(S, nbr_j(ent[u]));
+            for (int u = 0; u < U; ++u) sj[u] = ld_u128(S, uint32_t(nbr_j(ent[u])) * 16u);
             __builtin_amdgcn_sched_barrier(0);
             float w[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (e0 + u * K >= nc) break;
                 const double a0 = double(int(sj[u].x - si.x));
                 const double a1 = double(int(sj[u].y - si.y));
                 const double a2 = double(int(sj[u].z - si.z));
@@ -223,38 +242,36 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
                 const float dy = float(a0 * H[1] + a1 * H[4] + a2 * H[7]);
                 const float dz = float(a0 * H[2] + a1 * H[5] + a2 * H[8]);
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= hi) continue;
-                if (r2 >= lo) {  // rare: the exact FP64 test on the FP64 positions
-                    const gmem<const double4>* R = gp<const double4>(Rs(b, slot));
+                const bool valid = e0 + u * K < nc;
+                bool inside = valid && r2 < lo;
+                if (valid && r2 >= lo && r2 < hi) {  // rare: the exact FP64 test on the FP64 positions
                     const double4 r4 = load4(R, ii);
                     const double ri[3] = {r4.x, r4.y, r4.z};
-                    double h[9];
-                    for (int q = 0; q < 9; ++q) h[q] = g->h[q];
                     double d[3];
                     separation(ri, load4(R, nbr_j(ent[u])), h, ent[u], d);
-                    if (!(exact_r2(d) < rc2)) continue;
+                    inside = exact_r2(d) < rc2;
                 }
-                ++cnt;
-                const float ir2 = 1.f / r2;
+                // every lane takes the pair arithmetic; pairs outside rc add zeros
+                const float ir2 = __builtin_amdgcn_rcpf(r2);
                 float s6 = sig2 * ir2;
                 s6 = s6 * s6 * s6;
-                const float fr = eps24 * (s6 - 2.f * s6 * s6) * ir2;  // phi'(r) / r
-                fx += fr * dx;
-                fy += fr * dy;
-                fz += fr * dz;
-                w[0] += eps4 * (s6 * s6 - s6) - esh;
-                const float hf = -0.5f * fr;
-                const float wx = hf * dx, wy = hf * dy, wz = hf * dz;
-                w[1] += wx * dx;
-                w[2] += wy * dy;
-                w[3] += wz * dz;
-                w[4] += wx * dy;
-                w[5] += wx * dz;
-                w[6] += wy * dz;
+                const float fr = inside ? eps24 * (s6 - 2.f * s6 * s6) * ir2 : 0.f;  // phi'(r) / r
+                const float phi = inside ? eps4 * (s6 * s6 - s6) - esh : 0.f;
+                cnt += inside ? 1 : 0;
+                const float px = fr * dx, py = fr * dy, pz = fr * dz;
+                fx += px;
+                fy += py;
+                fz += pz;
+                w[0] += phi;
+                w[1] += px * dx;
+                w[2] += py * dy;
+                w[3] += pz * dz;
+                w[4] += px * dy;
+                w[5] += px * dz;
+                w[6] += py * dz;
             }
-            acc[0] += 0.5 * double(w[0]);
 #pragma unroll
-            for (int q = 1; q < 7; ++q) acc[q] += double(w[q]);
+            for (int q = 0; q < 7; ++q) acc[q] += double(w[q]);
         }
 #pragma unroll
         for (int off = K / 2; off > 0; off >>= 1) {
@@ -265,15 +282,17 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
         }
         if (in && lane == 0) {
             F[i] = fx;
-            F[b.ld + i] = fy;
-            F[2 * size_t(b.ld) + i] = fz;
-            over = over || cnt > b.cap;
+            F[ld + i] = fy;
+            F[2 * size_t(ld) + i] = fz;
+            over = over || cnt > cap;
             bad = bad || !isfinite(double(fx) + double(fy) + double(fz));
         }
     }
     if (over) set_error(st, CFNEB_ENEIGH);
     if (bad) set_error(st, CFNEB_ENONFINITE);
-    double v[10] = {acc[0], acc[1], acc[4], acc[5], acc[4], acc[2], acc[6], acc[5], acc[6], acc[3]};
+    // u_i = 1/2 sum_j phi; V = -1/2 sum_ij (phi'/r) d (x) d
+    for (int q = 1; q < 7; ++q) acc[q] *= -0.5;
+    double v[10] = {0.5 * acc[0], acc[1], acc[4], acc[5], acc[4], acc[2], acc[6], acc[5], acc[6], acc[3]};
     block_sum_t<10>(v, lds);
     if (threadIdx.x == 0) {
         double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;

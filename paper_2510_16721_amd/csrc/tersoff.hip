@@ -77,17 +77,6 @@ __device__ inline double exp64(double y)
     return ldexp(p, int(k));
 }
 
-// The potential's parameters are the same for every lane: marking them uniform lets
-// the compiler keep them in scalar registers instead of vector ones.
-__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
-__device__ inline double uni(double v)
-{
-    const long long bits = __double_as_longlong(v);
-    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(bits & 0xffffffffll)));
-    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(bits >> 32)));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 template <typename T>
 struct TersoffT {
     T A, B, l1, l2, c2, d2, c2d2, h, R, S, pi_w;
