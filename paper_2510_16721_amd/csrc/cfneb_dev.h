@@ -138,6 +138,7 @@ struct BandDev {
     double rc, rc2;
     double skin, rcl, rcl2;  // candidate skin, list cutoff rc + skin and its square
     double lj_eps, lj_sig2, lj_eshift;
+    int lj_lanes;  // lanes sharing an atom in the LJ force kernel (1, 2, 4 or 8)
     double ts_A, ts_B, ts_l1, ts_l2, ts_beta, ts_bn, ts_lnbeta, ts_n, ts_c2, ts_d2, ts_c2d2, ts_h, ts_R, ts_S;
     double k_spring;
     int climb_after, cell_filter;
@@ -486,6 +487,17 @@ __host__ __device__ inline int band_variant(const BandDev& b)
     return (b.potential == CFNEB_TERSOFF_C ? 2 : 0) + (b.fp64 ? 1 : 0);
 }
 
+// Bits 8..11 of a launch's variant set: the LJ lane counts 1, 2, 4, 8 present (each
+// band keeps its own count, alone and in a batch, so its sums never depend on its
+// batch-mates).
+__host__ __device__ inline unsigned lanes_bit(const BandDev& b)
+{
+    if (b.potential != CFNEB_LJ) return 0u;
+    const int k = b.lj_lanes;
+    return 1u << (8 + (k >= 8 ? 3 : k >= 4 ? 2 : k >= 2 ? 1 : 0));
+}
+__host__ __device__ inline unsigned launch_variants(const BandDev& b) { return (1u << band_variant(b)) | lanes_bit(b); }
+
 // Launch geometry of one batch: the grid of each kind, bounded by the most items
 // the table can ever hold, and the variants present.
 struct Launch {
@@ -497,7 +509,6 @@ struct Launch {
     // slots free first; chosen by timing before the step graphs are captured
     unsigned g_force, g_force_tile;
     unsigned variants;
-    int lj_lanes;  // lanes sharing an atom in the LJ force kernel (1, 2, 4 or 8)
 };
 
 __device__ inline void set_error(BandState* st, int code)

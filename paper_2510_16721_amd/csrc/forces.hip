@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_ima
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         BandState* st = b.st;
-        if (band_variant(b) != variant || band_stopped(st)) continue;  // uniform over the block
+        if (band_variant(b) != variant || b.lj_lanes != K || band_stopped(st)) continue;  // uniform over the block
         const int slot = st->slot[it.image];
         if constexpr (std::is_same<T, float>::value) {
             if (b.geom[slot].wrap) {  // uniform over the block
@@ -324,13 +324,12 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_ima
 template <typename T>
 void launch_lj(const Launch& L, int all_images, int variant, hipStream_t s)
 {
+    // one launch per lane count present (each skips the bands of the other counts)
     const unsigned g = L.g_force;
-    switch (L.lj_lanes) {
-    case 2: k_lj_cand<T, 2><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
-    case 4: k_lj_cand<T, 4><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
-    case 8: k_lj_cand<T, 8><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
-    default: k_lj_cand<T, 1><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant); break;
-    }
+    if (L.variants & (1u << 8)) k_lj_cand<T, 1><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant);
+    if (L.variants & (1u << 9)) k_lj_cand<T, 2><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant);
+    if (L.variants & (1u << 10)) k_lj_cand<T, 4><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant);
+    if (L.variants & (1u << 11)) k_lj_cand<T, 8><<<g, CFNEB_TILE, 0, s>>>(L.bd, all_images, variant);
 }
 
 // ------------------------------------------------------------ per-image reduction

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "cfneb_dev.h"
+#include "lj_lanes_table.h"
 
 using namespace cfneb;
 
@@ -99,16 +100,19 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     return true;
 }
 
-// Lanes sharing an atom in the LJ force kernel: one (measured fastest of 1, 2, 4 and
-// 8 on the 97,555-atom band), or CFNEB_LJ_LANES; one rule for the whole process, so a
-// band takes the same path alone and in a batch.
-int lj_lanes()
+// Lanes sharing an atom in the LJ force kernel, a property of the band: from the
+// table that tune_lanes.py measures (fastest lane count of a band stepped alone, by
+// atoms x images), or CFNEB_LJ_LANES.
+int lj_lanes_for(long long atoms, int images)
 {
     const char* v = std::getenv("CFNEB_LJ_LANES");
     if (v) {
         const int k = std::atoi(v);
         if (k == 1 || k == 2 || k == 4 || k == 8) return k;
     }
+    const long long work = atoms * images;
+    for (const auto& e : kLjLanesTable)
+        if (work <= e.max_atom_images) return e.lanes;
     return 1;
 }
 
@@ -127,7 +131,6 @@ void size_grids(Launch& L, long long atom_tiles, long long row_tiles, long long 
     L.g[KIND_BAND] = grid_for(bands, CFNEB_GRID_BANDS);
     L.g_force_tile = grid_for(atom_tiles, CFNEB_GRID_FORCE);
     L.g_force = L.g_force_tile;
-    L.lj_lanes = lj_lanes();
 }
 
 const char* err_text(int code)
@@ -239,6 +242,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.rcl = d.rc + d.skin;
     d.rcl2 = d.rcl * d.rcl;
     d.lj_eps = p->lj_eps;
+    d.lj_lanes = lj_lanes_for(L.N, p->n_images);
     d.lj_sig2 = p->lj_sigma * p->lj_sigma;
     if (p->lj_shift) {
         const double q = d.lj_sig2 / (p->lj_rc * p->lj_rc);
@@ -333,7 +337,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     const long long M = L.Mcap;
     size_grids(ln, M * L.ntA, M * L.ntR, M * ((L.nbcap + CFNEB_TILE - 1) / CFNEB_TILE), M, 1,
                M * ((L.N + CFNEB_TILE4 - 1) / CFNEB_TILE4), M * L.ntR4);
-    ln.variants = 1u << band_variant(d);
+    ln.variants = launch_variants(d);
 }
 
 int validate(const cfneb_params* p, int64_t n_atoms)
@@ -1290,7 +1294,7 @@ int cfneb_batch_attach(cfneb_batch* B, cfneb_band* band, int* slot)
     B->bands[s] = band;
     unsigned v = 0;
     for (auto* bb : B->bands)
-        if (bb) v |= 1u << band_variant(bb->d);
+        if (bb) v |= launch_variants(bb->d);
     B->launch.variants = v;
     if (slot) *slot = s;
     return CFNEB_OK;
@@ -1307,7 +1311,7 @@ int cfneb_batch_detach(cfneb_batch* B, int slot)
     B->owned[slot] = 0;  // a band of cfneb_batch_add detached here passes to the caller
     unsigned v = 0;
     for (auto* bb : B->bands)
-        if (bb) v |= 1u << band_variant(bb->d);
+        if (bb) v |= launch_variants(bb->d);
     B->launch.variants = v;
     return CFNEB_OK;
 }

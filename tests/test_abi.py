@@ -116,3 +116,23 @@ def test_applied_stress_is_validated_on_the_host(L):
         bad = cfneb.default_params(cfneb.CFNEB_TERSOFF_C, stress_GPa=tuple(s))
         with pytest.raises(cfneb.CfnebError):
             cfneb.band_bytes(bad, 100)
+
+
+def test_lane_table_rows_and_header():
+    # the tuner's table: thresholds at the geometric mean of neighbouring sizes whose
+    # fastest lane counts differ, runs of equal counts merged, the last row open-ended
+    from paper_2510_16721_amd import tune_lanes as T
+    res = [(100, {1: 3.0, 2: 2.0, 4: 1.0, 8: 1.5}), (400, {1: 3.0, 2: 2.0, 4: 1.0, 8: 1.5}),
+           (1600, {1: 2.0, 2: 1.0, 4: 1.5, 8: 3.0}), (6400, {1: 1.0, 2: 2.0, 4: 3.0, 8: 4.0})]
+    assert T.table_rows(res) == [(800, 4), (3200, 2), (None, 1)]
+    assert T.table_rows(res[3:]) == [(None, 1)]
+    # within 3 % of the fastest, the fewest lanes
+    assert T.pick({1: 1.02, 2: 1.0, 4: 1.1, 8: 1.2}) == 1
+    assert T.pick({1: 1.04, 2: 1.0, 4: 1.01, 8: 1.2}) == 2
+    # the committed table is well formed: increasing thresholds, lane counts 1/2/4/8,
+    # and an open-ended last row
+    src = open(T.TABLE).read()
+    rows = [(int(a), int(b)) for a, b in re.findall(r"\{(\d+)LL, (\d)\}", src)]
+    assert rows and rows[-1][0] == 9223372036854775807
+    assert all(r[1] in (1, 2, 4, 8) for r in rows)
+    assert [r[0] for r in rows] == sorted(r[0] for r in rows)

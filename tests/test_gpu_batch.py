@@ -316,3 +316,31 @@ def test_batch_tersoff_bands_match_oracle(fp64):
               f"oracle {od} steps barrier {oe['barrier']:.6f}, tolerance {tol:.2e}", flush=True)
         assert abs(ge["barrier"] - oe["barrier"]) <= tol, (q, ge["barrier"], oe["barrier"])
     batch.close()
+
+
+def test_lane_counts_are_kept_per_band_in_a_batch(monkeypatch):
+    # LJ bands created with 1, 2, 4 and 8 lanes per atom (two of them on the
+    # fixed-point path, 863 atoms) step in one batch, one force launch per lane count;
+    # each band ends bit for bit where it ends alone
+    from paper_2510_16721_amd import cfneb
+    cases = [("lj863", 1), ("lj863", 4), ("lj_ragged", 2), ("lj31", 8)]
+
+    def make():
+        out = []
+        for name, k in cases:
+            monkeypatch.setenv("CFNEB_LJ_LANES", str(k))
+            out.append(make_pair(name, oracle_too=False, n_images=5, max_images=5, climb_after=6)[0])
+        monkeypatch.delenv("CFNEB_LJ_LANES")
+        return out
+
+    alone = make()
+    for b in alone:
+        assert b.step(15)[0] == 15
+    mixed = make()
+    batch = cfneb.Batch(8)
+    slots = [batch.attach(b) for b in mixed]
+    steps, conv, errs = batch.step(15)
+    assert list(steps[slots]) == [15] * len(mixed) and not errs.any()
+    for a, b in zip(alone, mixed):
+        _same_state(a, b)
+    batch.close()

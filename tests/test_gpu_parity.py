@@ -290,6 +290,29 @@ def test_runs_are_bit_identical():
     np.testing.assert_array_equal(a.energies()["H"], b.energies()["H"])
 
 
+@pytest.mark.parametrize("name", ["lj863", "lj255"])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+def test_lj_lanes_per_atom(name, lanes, monkeypatch):
+    # every lane count of the LJ kernel, on the fixed-point path (863 atoms) and the
+    # FP64-separation path (255 atoms, a cell under twice rc + 2 skin wide), against
+    # the oracle on the device's positions
+    import oracle
+    monkeypatch.setenv("CFNEB_LJ_LANES", str(lanes))
+    g, _, w, kind = make_pair(name, n_images=5, max_images=5, oracle_too=False)
+    monkeypatch.delenv("CFNEB_LJ_LANES")
+    g.step(4)
+    assert g.step(1, 1e30)[2]  # evaluate, no move
+    p = oracle_params_like(kind)
+    n = g.n
+    for k in (1, 3):
+        img = g.image(k)
+        E, u, F, V = oracle.evaluate(p, img["R"], img["h"])
+        assert abs(img["E"] - E) / n <= TOL_E_PER_ATOM
+        assert np.abs(img["F"] - F).max() <= TOL_F
+        assert np.abs(img["V"] - V).max() / n <= TOL_V_PER_ATOM
+    g.close()
+
+
 def _cutoff_pairs(L, rc, deltas, seed):
     # isolated pairs at separations rc (1 + delta) along seeded directions, centres on a
     # 5x5x5 grid of spacing L/5 (>= rc + 1.0 between atoms of different pairs); every
