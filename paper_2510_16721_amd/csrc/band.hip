@@ -455,7 +455,8 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BatchDev bd, unsigne
     }
 }
 
-// fmax, convergence, step clamp; commit the FIRE proposal when the band moves.
+// fmax, convergence, step clamp; commit the FIRE proposal when the band moves (the
+// move itself, X += scale dt v', is left pending for the next pass over X).
 __device__ void finalize_item(const BandDev& b, BandState* st, double* lds)
 {
     const int M = st->M;
@@ -790,6 +791,19 @@ void launch_update(const Launch& L, hipStream_t s)
 
 void launch_finalize(const Launch& L, hipStream_t s) { k_band_finalize<<<L.g[KIND_BAND], 1024, 0, s>>>(L.bd); }
 
-void launch_move(const Launch& L, hipStream_t s) { k_band_move<<<L.g[KIND_ROW], CFNEB_TILE, 0, s>>>(L.bd); }
+// A step's move is applied by the next step's geometry (cell rows) and skin check
+// (atom rows), which read X anyway; this pair applies a pending move on its own, at
+// the end of a step call and before a refinement, and then clears the flag.
+__global__ void k_move_clear(BatchDev bd)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < bd.cap && bd.live[t]) bd.bands[t].st->move = 0;
+}
+
+void launch_flush_move(const Launch& L, hipStream_t s)
+{
+    k_band_move<<<L.g[KIND_ROW], CFNEB_TILE, 0, s>>>(L.bd);
+    k_move_clear<<<(L.bd.cap + 63) / 64, 64, 0, s>>>(L.bd);
+}
 
 }  // namespace cfneb

@@ -77,6 +77,8 @@ void launch_evaluate(const Launch& L, int all_images, hipStream_t s)
 }
 
 // One band step of every live band.
+// (the previous step's move is applied by the geometry and skin passes; this step's
+// is left pending)
 void launch_step_core(const Launch& L, hipStream_t s)
 {
     launch_evaluate(L, 0, s);
@@ -84,12 +86,13 @@ void launch_step_core(const Launch& L, hipStream_t s)
     launch_scalars(L, s);
     launch_update(L, s);
     launch_finalize(L, s);
-    launch_move(L, s);
 }
 
+// a refinement needs the moved band
 void launch_step(const Launch& L, hipStream_t s)
 {
     launch_step_core(L, s);
+    launch_flush_move(L, s);
     launch_refine(L, 0, s);
 }
 

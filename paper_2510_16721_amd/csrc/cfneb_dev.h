@@ -801,7 +801,14 @@ void launch_dots(const Launch& L, hipStream_t s);
 void launch_scalars(const Launch& L, hipStream_t s);
 void launch_update(const Launch& L, hipStream_t s);
 void launch_finalize(const Launch& L, hipStream_t s);
-void launch_move(const Launch& L, hipStream_t s);
+void launch_flush_move(const Launch& L, hipStream_t s);
+
+// The pending move of one row of a moving image: X += scale (dt v'), v' in the
+// committed velocity buffer (the same rounding as a separate move pass).
+__device__ inline bool move_pending(const BandState* st, int all_images)
+{
+    return all_images == 0 && st->move != 0 && st->err == 0;
+}
 void launch_refine(const Launch& L, int forced, hipStream_t s);
 void launch_readout(const Launch& L, hipStream_t s);
 void launch_evaluate(const Launch& L, int all_images, hipStream_t s);

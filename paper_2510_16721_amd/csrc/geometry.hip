@@ -153,10 +153,21 @@ __device__ __forceinline__ void fixed_point_bounds(const BandDev& b, ImageGeom& 
     g.r2hi = float(b.rc2 * (1.0 + rel));
 }
 
-// Geometry of image k of band b and its strain since the candidate build.
-__device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int k)
+// Geometry of image k of band b and its strain since the candidate build; in a step,
+// first the pending move of the image's cell rows.
+__device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int k, int all_images)
 {
     const int slot = st->slot[k];
+    if (move_pending(st, all_images)) {
+        double* X = Xs(b, slot);
+        const double* V = Vs(b, st->vcur, slot);
+        const double sc = st->scale, dt = st->dt;
+        for (int q = 0; q < 3; ++q)
+            for (int c = 0; c < 3; ++c) {
+                const size_t o = size_t(c) * b.ld + b.N + q;
+                X[o] += sc * (dt * V[o]);
+            }
+    }
     ImageGeom g;
     g.err = 0;
     if (!image_geometry(b, Xs(b, slot), g)) {
@@ -190,7 +201,7 @@ __global__ void __launch_bounds__(CFNEB_MAX_BANDS) k_geom(BatchDev bd, int all_i
         BandState* st = b.st;
         const int k = threadIdx.x;
         if (band_stopped(st) || k >= b.Mcap || !image_active(st, k, all_images)) continue;
-        geom_image(b, st, k);
+        geom_image(b, st, k, all_images);
     }
 }
 

@@ -13,8 +13,8 @@
 // (r + d_i + d_j) / (1 - |E|), so 2 max d_i + rcl |E| < skin keeps the list complete.
 //
 // Kernels, in order (each a persistent walk over the items of every live band):
-//   k_skin_check   R = R~ D (and its fixed-point fractional coordinates); max_i d_i^2
-//                  per 1024-atom tile
+//   k_skin_check   (steps) the previous step's move of the atom rows; R = R~ D (and
+//                  its fixed-point fractional coordinates); max_i d_i^2 per 1024-atom tile
 //   k_skin_decide  max over an image's tiles, rebuild flag per image; a rebuild takes
 //                  the current cell as reference
 //   k_bin_assign   (rebuilds) wrapped fractional coordinate, bin id; the count atomic
@@ -60,10 +60,11 @@ __device__ inline uint4 fixed_fraction(const double* r, const double* hi)
 }
 
 // 1024 atoms per item, four per thread: all loads of the four atoms are issued before
-// any position is stored.  R = R~ D (and its fixed-point fractional coordinates for
-// FP32 LJ bands); d_i^2 against the strained reference when a list exists; the tile's
-// maximum goes to its own slot (no atomics: many tiles per image would contend on one
-// address).
+// any position is stored.  In a step, first the previous step's pending move of these
+// atom rows (X += scale dt v', written back); R = R~ D (and its fixed-point fractional
+// coordinates for FP32 LJ bands); d_i^2 against the strained reference when a list
+// exists; the tile's maximum goes to its own slot (no atomics: many tiles per image
+// would contend on one address).
 __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_images)
 {
     __shared__ double lds[CFNEB_TILE / 64];
@@ -85,17 +86,45 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
         }
         const bool valid = b.skst[slot].valid != 0;
         gmem<uint4>* __restrict__ S = b.S ? gp(Ss(b, slot)) : nullptr;
-        const gmem<const double>* __restrict__ X = gp<const double>(Xs(b, slot));
+        gmem<double>* __restrict__ X = gp(Xs(b, slot));
         const gmem<const double>* __restrict__ Rr = gp<const double>(b.Rref + size_t(slot) * slot_rows(b));
         double x[Q][3], a[Q][3];
+        if (move_pending(st, all_images)) {  // uniform over the block
+            // the previous step's move of these rows: X += scale (dt v')
+            const gmem<const double>* __restrict__ V = gp<const double>(Vs(b, st->vcur, slot));
+            const double sc = st->scale, dt = st->dt;
+            double v[Q][3];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
-            const bool in = i < b.N;
+            for (int q = 0; q < Q; ++q) {
+                const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
+                const bool in = i < b.N;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                x[q][c] = in ? X[size_t(c) * b.ld + i] : 0.0;
-                a[q][c] = (in && valid) ? Rr[size_t(c) * b.ld + i] : 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    x[q][c] = in ? X[size_t(c) * b.ld + i] : 0.0;
+                    v[q][c] = in ? V[size_t(c) * b.ld + i] : 0.0;
+                    a[q][c] = (in && valid) ? Rr[size_t(c) * b.ld + i] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
+                if (i >= b.N) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    x[q][c] += sc * (dt * v[q][c]);
+                    X[size_t(c) * b.ld + i] = x[q][c];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
+                const bool in = i < b.N;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    x[q][c] = in ? X[size_t(c) * b.ld + i] : 0.0;
+                    a[q][c] = (in && valid) ? Rr[size_t(c) * b.ld + i] : 0.0;
+                }
             }
         }
         double m[1] = {0.0};
@@ -133,6 +162,8 @@ __global__ void __launch_bounds__(16 * CFNEB_MAX_IMAGES) k_skin_decide(BatchDev 
         const BandDev& b = bd.bands[it.band];
         BandState* st = b.st;
         const int k = threadIdx.x >> 4, lane = threadIdx.x & 15;
+        // the geometry and skin passes have applied the pending move
+        if (threadIdx.x == 0 && all_images == 0) st->move = 0;
         const bool act = !band_stopped(st) && k < b.Mcap && image_active(st, k, all_images);
         const int slot = act ? st->slot[k] : 0;
         const int nt = kind_tiles(b, KIND_ATOM4);

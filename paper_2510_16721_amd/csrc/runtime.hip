@@ -763,6 +763,7 @@ int cfneb_step(cfneb_band* b, int max_steps, double f_tol, int* steps_done, doub
             next = b->host_state->step;  // the loop's ++next makes it the next launch's
         }
     }
+    launch_flush_move(b->launch, b->stream);  // the last step's move
     rc = read_state(b);
     if (rc != CFNEB_OK) return rc;
     const BandState& st = *b->host_state;
@@ -813,9 +814,12 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
             case CFNEB_PH_SCALARS: launch_scalars(d, s); break;
             case CFNEB_PH_UPDATE: launch_update(d, s); break;
             case CFNEB_PH_FINALIZE: launch_finalize(d, s); break;
-            case CFNEB_PH_MOVE: launch_move(d, s); break;
+            case CFNEB_PH_MOVE: break;  // applied by the next step's geometry and skin passes
             case CFNEB_PH_REFINE:
-                if (with_refine) launch_refine(d, 0, s);
+                if (with_refine) {
+                    launch_flush_move(d, s);
+                    launch_refine(d, 0, s);
+                }
                 break;
             default: break;
             }
@@ -823,6 +827,7 @@ int cfneb_step_profiled(cfneb_band* b, int max_steps, double f_tol, int* steps_d
         (void)hipEventRecord(e[NP], s);
         rc = check_kernels(b, "step_profiled");
     }
+    launch_flush_move(d, s);  // the last step's move
     if (rc == CFNEB_OK) rc = read_state(b);
     if (rc == CFNEB_OK) {
         for (int ph = 0; ph < nphase; ++ph) phase_ms[ph] = 0.0;
@@ -1404,6 +1409,7 @@ int cfneb_batch_step(cfneb_batch* B, int max_steps, double f_tol, int* steps_don
             if (!active) break;
         }
     }
+    launch_flush_move(B->launch, B->stream);  // the last step's moves
     rc = read_summary(B);
     if (rc != CFNEB_OK) return rc;
     for (int q = 0; q < B->cap; ++q) {
