@@ -417,6 +417,13 @@ def throughput(args):
                                      mean_moving),
                     algorithmic_bytes=float((20.0 * counts + 36.0).mean()) * atoms,
                     valu_issue_util=recorded("tersoff_graphite_98304_valu_counters.md", "valu_issue_util"))
+    elif dom == "force0":
+        # the LJ candidate kernel (exact test and pair term of every candidate)
+        achieved = flops_per_atom * atoms / (kernel_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", kernel="k_lj_cand<float, 1>", achieved=achieved, peak=VALU_FP32_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=achieved / VALU_FP32_PEAK_TFLOPS,
+                    traffic=recorded("lj_fcc_vacancy_97555_hbm_counters.md", "force_kernel_hbm_bytes", mean_moving),
+                    valu_issue_util=recorded("lj_fcc_vacancy_97555_valu_counters.md", "valu_issue_util"))
     elif dom in ALGO:
         m = ALGO[dom]
         units = rows if m["per"] == "row" else atoms
