@@ -221,13 +221,18 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
         // four of the lane's candidates at a time, loads first; past the last candidate
         // the loads repeat the batch's first and the pair is masked out
         constexpr int U = 4;
-        for (int e0 = lane; e0 < nc; e0 += U * K) {
+        // candidate c = base + u K + lane of this atom sits at byte (c N + i) 4: a uniform
+        // row offset plus this lane's constant (no per-candidate multiply)
+        const uint32_t own = (uint32_t(lane) * N + ii) * 4u, row = N * 4u;
+        for (int base = 0; base + lane < nc; base += U * K) {
+            const int e0 = base + lane;
             uint32_t ent[U];
             uint4 sj[U];
+            const uint32_t o0 = uint32_t(base) * row + own;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int c = e0 + u * K;
-                ent[u] = ld_u32(cand, (uint32_t(c < nc ? c : e0) * N + ii) * 4u);
+                const uint32_t o = o0 + uint32_t(u * K) * row;
+                ent[u] = ld_u32(cand, e0 + u * K < nc ? o : o0);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) sj[u] = ld_u128(S, uint32_t(nbr_j(ent[u])) * 16u);
