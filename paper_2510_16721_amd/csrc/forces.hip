@@ -7,10 +7,11 @@
 // (Eqs. (6)-(8)).  Lists are full, so every force is a gather: no atomics.
 // Lennard-Jones lives here; the Tersoff kernels are in tersoff.hip.
 //
-// Precision: bond vectors are formed in FP64 from FP64 positions, then the pair and
-// three-body arithmetic runs in T (float, or double for FP64 bands); per-atom
-// energy and virial terms are summed in FP64, then per block and per image in a
-// fixed order.
+// Precision: bond vectors are formed in FP64 (from FP64 positions, or for FP32 LJ
+// bands in wide cells from 32-bit fixed-point fractional coordinates, exact to
+// 2^-33 of a cell), then the pair and three-body arithmetic runs in T (float, or
+// double for FP64 bands); per-atom energy and virial terms are summed in FP64, then
+// per block and per image in a fixed order.
 #include <type_traits>
 
 #include "cfneb_dev.h"
@@ -26,8 +27,8 @@ namespace cfneb {
 // is the fixed butterfly sum of its lanes, energy and virial go into the block sums.
 // A tile of 256 atoms is covered in K passes of 256 / K atoms.
 //
-// The inclusion test decides on the exact FP64 r^2 (every operation rounded on its
-// own): the separation d is formed in FP64 (a candidate without a lattice shift, most
+// FP64-record path (FP64 bands, narrow cells): the inclusion test decides on the
+// exact FP64 r^2 (every operation rounded on its own): the separation d is formed in FP64 (a candidate without a lattice shift, most
 // of them in a large cell, skips the shift arithmetic, which adds an exact zero), and
 // its FP32 square, within 3e-7 of r^2 relative, settles every pair outside a 1e-6
 // band around rc^2; only pairs inside the band square d in FP64.  The virial of a
