@@ -413,6 +413,37 @@ def test_full_size_band_sampled_image():
     assert abs(ref_cf["H"] - img["H"]) / n <= TOL_E_PER_ATOM
 
 
+def test_full_size_lj_band_sampled_image():
+    # The 97,555-atom LJ FCC vacancy hop, 24 images up to 40, as in the LJ benchmark: the
+    # fixed-point force kernel (the cell is 45 sigma wide) with the lane count of the
+    # table, after a candidate build and two steps; one moving image against the oracle
+    # in full (energy, every force, virial) and a sample of its neighbour sets
+    import oracle
+    import workloads as W
+    from paper_2510_16721_amd import cfneb
+    w = W.fcc_vacancy_hop(29, 29, 29, 1.5496)
+    kw = dict(n_images=24, max_images=40, min_images=5, refine_every=20, climb_after=100, k_spring=1.0)
+    g = cfneb.Band(cfneb.default_params(cfneb.CFNEB_LJ, force_fp64=0, **kw), w["pos_init"], w["cell_init"],
+                   w["pos_final"], w["cell_final"])
+    print("lj97555: two steps", flush=True)
+    g.step(2)
+    assert g.step(1, 1e30)[2]  # evaluate, no move
+    k = 13
+    img = g.image(k)
+    n = g.n
+    p = oracle_params_like("lj")
+    E, u, F, V = oracle.evaluate(p, img["R"], img["h"])
+    assert abs(img["E"] - E) / n <= TOL_E_PER_ATOM
+    assert np.abs(img["F"] - F).max() <= TOL_F
+    assert np.abs(img["V"] - V).max() / n <= TOL_V_PER_ATOM
+    cnt, ent = g.neighbours(k)
+    ref = oracle.nlist(img["R"], img["h"], 2.5)
+    for i in range(0, n, 211):
+        np.testing.assert_array_equal(sort_entries(ent[i]), ref[i])
+    assert np.array_equal(cnt, [len(x) for x in ref])
+    g.close()
+
+
 def _rotated_strained(name):
     from gpu_cases import workload
     w, kind = workload(name)
