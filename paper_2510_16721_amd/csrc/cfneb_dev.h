@@ -66,6 +66,7 @@ struct ImageGeom {
     double w[3];
     int nb[3];
     int reach[3];
+    int sub;  // bins per rcl along each axis (2 for dense systems)
     int nbins;
     int err;
     // strain since the last candidate build: h = h_ref (I + E), and |E|_F

@@ -99,6 +99,7 @@ __device__ __forceinline__ bool image_geometry(const BandDev& b, const double* X
     // would be mostly empty.  Cells narrower than that get one bin and a stencil wide
     // enough for all the periodic images needed.
     const int sub = (double(b.N) * b.rcl * b.rcl * b.rcl >= 8.0 * g.omega) ? 2 : 1;
+    g.sub = sub;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double q = g.w[k] * sub / (b.rcl * (1.0 + 1e-9));

@@ -24,7 +24,8 @@
 //   k_bin_scatter  (rebuilds) atom -> bin-ordered 32-byte record (position, id, image)
 //   k_bin_sort     (rebuilds) sort each bin by atom id, so lists are deterministic
 //   k_cand         (rebuilds) stencil walk over bin-ordered records, pairs within rcl,
-//                  packed entry-major candidate lists; R_ref = R
+//                  packed entry-major candidate lists; R_ref = R (threads take atoms in
+//                  bin order when the bins are half-width)
 //   k_filter       (host readouts only: the force kernels test their candidates
 //                  themselves) exact test of every candidate, packed entry-major
 //                  neighbour lists (entry e of atom i at [e][i])
@@ -461,10 +462,19 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_cand(BatchDev bd, int all_images
     while (loop.next(it)) {
         const BandDev& b = bd.bands[it.band];
         BandState* st = b.st;
-        const int i = it.tile * CFNEB_TILE + threadIdx.x;
-        if (band_stopped(st) || i >= b.N) continue;
+        const int p = it.tile * CFNEB_TILE + threadIdx.x;
+        if (band_stopped(st) || p >= b.N) continue;
         const int slot = st->slot[it.image];
         if (!b.skst[slot].rebuild) continue;
+        // with half-width bins (dense systems) threads take the atoms in bin order
+        // (record p of the sorted bins), so the lanes of a wave share their stencil
+        // rows; each atom's list is the same in either order
+        int i = p;
+        if (b.geom[slot].sub == 2) {
+            const double4 rec =
+                load4(gp<const double4>(reinterpret_cast<const double4*>(b.bpos + size_t(slot) * b.N)), p);
+            i = info_j(__double_as_longlong(rec.w));
+        }
         cand_item(b, st, slot, i);
     }
 }
