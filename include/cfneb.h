@@ -26,7 +26,10 @@
  *   - Threading: one host thread per band handle at a time.
  *   - Environment: CFNEB_NO_GRAPH=1 launches every step kernel by kernel instead of
  *     through captured hipGraphs (same results); CFNEB_FORCE_GRID=persistent|tile
- *     fixes the force kernels' grid instead of choosing it by timing (same results).
+ *     fixes the force kernels' grid instead of choosing it by timing (same results);
+ *     CFNEB_LJ_LANES=1|2|4|8, read when an LJ band is created, fixes the lanes that
+ *     share an atom in its force kernel instead of the measured table (results equal
+ *     to rounding: the lanes' partial forces are summed in a different order).
  */
 #ifndef CFNEB_H
 #define CFNEB_H
