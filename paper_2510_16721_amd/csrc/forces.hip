@@ -206,9 +206,9 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
     }
     const float lo = uni(g->r2lo), hi = uni(g->r2hi);
     const double rc2 = uni(b.rc2);
-    const float eps4 = uni(float(4.0 * b.lj_eps)), eps24 = uni(float(24.0 * b.lj_eps)), sig2 = uni(float(b.lj_sig2)),
-                esh = uni(float(b.lj_eshift));
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // 2 u, then -2 V: xx yy zz xy xz yz
+    const float eps24 = uni(float(24.0 * b.lj_eps)), sig2 = uni(float(b.lj_sig2));
+    const double e4 = uni(4.0 * b.lj_eps), e24 = uni(24.0 * b.lj_eps), esh64 = uni(b.lj_eshift);
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // 2 u, then -2 V / (24 eps): xx yy zz xy xz yz
     bool over = false, bad = false;
 #pragma unroll 1
     for (int sub = 0; sub < K; ++sub) {
@@ -239,6 +239,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
             for (int u = 0; u < U; ++u) sj[u] = ld_u128(S, uint32_t(nbr_j(ent[u])) * 16u);
             __builtin_amdgcn_sched_barrier(0);
             float w[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const int cnt0 = cnt;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const double a0 = double(int(sj[u].x - si.x));
@@ -257,12 +258,15 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
                     separation(ri, load4(R, nbr_j(ent[u])), h, ent[u], d);
                     inside = exact_r2(d) < rc2;
                 }
-                // every lane takes the pair arithmetic; pairs outside rc add zeros
+                // every lane takes the pair arithmetic; pairs outside rc add zeros.  The
+                // terms are in units of 24 eps (force) and 4 eps (energy, before the
+                // shift): the constants multiply the sums
                 const float ir2 = __builtin_amdgcn_rcpf(r2);
                 float s6 = sig2 * ir2;
                 s6 = s6 * s6 * s6;
-                const float fr = inside ? eps24 * (s6 - 2.f * s6 * s6) * ir2 : 0.f;  // phi'(r) / r
-                const float phi = inside ? eps4 * (s6 * s6 - s6) - esh : 0.f;
+                const float s12 = s6 * s6;
+                const float fr = inside ? (s6 - 2.f * s12) * ir2 : 0.f;  // phi'(r) / (24 eps r)
+                const float phi = inside ? s12 - s6 : 0.f;               // (phi(r) + shift) / (4 eps)
                 cnt += inside ? 1 : 0;
                 const float px = fr * dx, py = fr * dy, pz = fr * dz;
                 fx += px;
@@ -276,8 +280,9 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
                 w[5] += px * dz;
                 w[6] += py * dz;
             }
+            acc[0] += e4 * double(w[0]) - esh64 * double(cnt - cnt0);
 #pragma unroll
-            for (int q = 0; q < 7; ++q) acc[q] += double(w[q]);
+            for (int q = 1; q < 7; ++q) acc[q] += double(w[q]);
         }
 #pragma unroll
         for (int off = K / 2; off > 0; off >>= 1) {
@@ -287,9 +292,9 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
             cnt += __shfl_xor(cnt, off, 64);
         }
         if (in && lane == 0) {
-            F[i] = fx;
-            F[ld + i] = fy;
-            F[2 * size_t(ld) + i] = fz;
+            F[i] = eps24 * fx;
+            F[ld + i] = eps24 * fy;
+            F[2 * size_t(ld) + i] = eps24 * fz;
             over = over || cnt > cap;
             bad = bad || !isfinite(double(fx) + double(fy) + double(fz));
         }
@@ -297,7 +302,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
     if (over) set_error(st, CFNEB_ENEIGH);
     if (bad) set_error(st, CFNEB_ENONFINITE);
     // u_i = 1/2 sum_j phi; V = -1/2 sum_ij (phi'/r) d (x) d
-    for (int q = 1; q < 7; ++q) acc[q] *= -0.5;
+    for (int q = 1; q < 7; ++q) acc[q] *= -0.5 * e24;
     double v[10] = {0.5 * acc[0], acc[1], acc[4], acc[5], acc[4], acc[2], acc[6], acc[5], acc[6], acc[3]};
     block_sum_t<10>(v, lds);
     if (threadIdx.x == 0) {
