@@ -169,12 +169,12 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_band_dots(BatchDev bd, unsigned 
 // lane sums every 64th tile partial, then the wave sums its lanes, in a fixed order.
 __global__ void __launch_bounds__(1024) k_band_dots_reduce(BatchDev bd)
 {
-    ItemLoop loop(bd, KIND_IMAGE, 0);
+    ItemLoopRO loop(bd, KIND_IMAGE, 0);
     Item it;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     while (loop.next(it)) {
-        const BandDev& b = bd.bands[it.band];
-        if (band_stopped(b.st)) continue;  // uniform over the block
+        const BandDev b = band_ro(bd, it.band);
+        if (band_stopped(cp(b.st))) continue;  // uniform over the block
         const int k = it.image;
         const gmem<const double>* part = gp<const double>(b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4);
         for (int q = w; q < CFNEB_NDOT; q += 16) {
@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(1024) k_band_scalars(BatchDev bd)
 // rows only), v' = (cv v + cf F_NEB) + dt' F_NEB; returns |F_NEB|^2 and |dt' v'|^2.
 struct UpdateCoef {
     double cp, cm, cv, cf, dt;
-    const double* mean;
+    double mean[9];
 };
 __device__ inline void update_row(const UpdateCoef& u, const double (&x0)[3], const double (&xm)[3],
                                   const double (&xp)[3], const double (&v)[3], const double (&f)[3], bool atom,
@@ -357,7 +357,7 @@ __device__ inline void update_row(const UpdateCoef& u, const double (&x0)[3], co
 // |F_NEB| and |dt' v'|; 1024 rows per item, four per thread, loads of atom-row tiles
 // all issued before the first store.
 template <typename T>
-__device__ void update_item(const BandDev& b, const BandState* st, int k, int tile, double* lds)
+__device__ void update_item(const BandDev& b, const cmem<BandState>* st, int k, int tile, double* lds)
 {
     constexpr int Q = CFNEB_TILE4 / CFNEB_TILE;
     const int s0 = st->slot[k], sm = st->slot[k - 1], sp = st->slot[k + 1];
@@ -368,7 +368,8 @@ __device__ void update_item(const BandDev& b, const BandState* st, int k, int ti
     u.cv = st->cv;
     u.cf = st->cf;
     u.dt = st->dt_new;
-    u.mean = st->tmean[k];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) u.mean[q] = st->tmean[k][q];
     const gmem<const double>* __restrict__ X0 = gp<const double>(Xs(b, s0));
     const gmem<const double>* __restrict__ Xm = gp<const double>(Xs(b, sm));
     const gmem<const double>* __restrict__ Xp = gp<const double>(Xs(b, sp));
@@ -446,12 +447,12 @@ template <typename T>
 __global__ void __launch_bounds__(CFNEB_TILE) k_band_update(BatchDev bd, unsigned vmask)
 {
     __shared__ double lds[4 * 3];
-    ItemLoop loop(bd, KIND_ROW4, 0);
+    ItemLoopRO loop(bd, KIND_ROW4, 0);
     Item it;
     while (loop.next(it)) {
-        const BandDev& b = bd.bands[it.band];
-        if (!((vmask >> band_variant(b)) & 1u) || band_stopped(b.st)) continue;  // uniform
-        update_item<T>(b, b.st, it.image, it.tile, lds);
+        const BandDev b = band_ro(bd, it.band);
+        if (!((vmask >> band_variant(b)) & 1u) || band_stopped(cp(b.st))) continue;  // uniform
+        update_item<T>(b, cp(b.st), it.image, it.tile, lds);
     }
 }
 

@@ -203,6 +203,17 @@ __device__ inline gmem<T>* gp(T* p)
 {
     return (gmem<T>*)p;
 }
+// Constant-memory views, for data that no block writes while the kernel runs (the
+// band table, the work plan, a band's state in the kernels that only read it):
+// uniform reads through them become scalar loads through the scalar cache, which
+// the compiler cannot otherwise prove safe once the kernel has stored anything.
+template <typename T>
+using cmem = __attribute__((address_space(4))) T;
+template <typename T>
+__device__ inline const cmem<T>* cp(const T* p)
+{
+    return (const cmem<T>*)p;
+}
 // Values that are the same for every lane (band fields, the potential's parameters):
 // marking them uniform lets the compiler keep them in scalar registers, and a pointer
 // so marked serves as the scalar base of a load with a 32-bit lane offset.
@@ -292,6 +303,7 @@ __device__ inline bool image_active(const BandState* st, int k, int all_images)
 }
 
 __device__ inline bool band_stopped(const BandState* st) { return st->done != 0 || st->err != 0; }
+__device__ inline bool band_stopped(const cmem<BandState>* st) { return (st->done | st->err) != 0; }
 
 // ---------------------------------------------------------------- work plan
 // Every kernel of a step is persistent: a fixed grid walks a work plan of items
@@ -336,6 +348,10 @@ __device__ inline int* rebuild_flag(const BatchDev& bd) { return bd.plan + NKIND
 // (cleared by the plan kernel); the step-end refine kernels return at once without it.
 __device__ inline int* refine_flag(const BatchDev& bd) { return bd.plan + NKIND * (bd.cap + 1) + 1; }
 
+// A band's table entry copied out of the constant view: the fields a kernel uses
+// become scalar loads (the copy itself is taken apart into registers).
+__device__ inline BandDev band_ro(const BatchDev& bd, int i) { return *(const BandDev*)(cp(bd.bands) + i); }
+
 struct Item {
     int band, tile, image;
 };
@@ -377,14 +393,16 @@ __device__ inline void kind_span(const BandDev& b, int kind, int M, int all_imag
     }
 }
 
-// Persistent, XCD-ordered walk over the items of one kind.
-struct ItemLoop {
+// Persistent, XCD-ordered walk over the items of one kind.  RO: the kernel writes
+// no band's image count, so the plan, band table and counts are read as constants.
+template <bool RO>
+struct ItemLoopT {
     const BatchDev* bd;
     int kind, total, chunk, xcd, j, per, n, first_mode;
-    __device__ ItemLoop(const BatchDev& b, int k, int all_images)
+    __device__ ItemLoopT(const BatchDev& b, int k, int all_images)
         : bd(&b), kind(k), n(0), first_mode(all_images)
     {
-        total = b.plan[k * (b.cap + 1) + b.cap];
+        total = RO ? cp(b.plan)[k * (b.cap + 1) + b.cap] : b.plan[k * (b.cap + 1) + b.cap];
         per = int(gridDim.x) / CFNEB_XCDS;
         xcd = int(blockIdx.x) % CFNEB_XCDS;
         j = int(blockIdx.x) / CFNEB_XCDS;
@@ -401,16 +419,22 @@ struct ItemLoop {
         int lo = 0, hi = bd->cap;  // off[lo] <= L < off[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (off[mid] <= L)
+            if ((RO ? cp(off)[mid] : off[mid]) <= L)
                 lo = mid;
             else
                 hi = mid;
         }
-        const BandDev& b = bd->bands[lo];
-        int count, first;
-        kind_span(b, kind, b.st->M, first_mode, count, first);
-        const int local = L - off[lo];
-        const int nt = kind_tiles(b, kind);
+        int count, first, nt;
+        if constexpr (RO) {
+            const BandDev b = band_ro(*bd, lo);
+            kind_span(b, kind, cp(b.st)->M, first_mode, count, first);
+            nt = kind_tiles(b, kind);
+        } else {
+            const BandDev& b = bd->bands[lo];
+            kind_span(b, kind, b.st->M, first_mode, count, first);
+            nt = kind_tiles(b, kind);
+        }
+        const int local = L - (RO ? cp(off)[lo] : off[lo]);
         it.band = lo;
         if (kind == KIND_ROW4) {
             // tile-major: the same rows of consecutive images are neighbouring items,
@@ -426,6 +450,8 @@ struct ItemLoop {
         return true;
     }
 };
+using ItemLoop = ItemLoopT<false>;
+using ItemLoopRO = ItemLoopT<true>;
 
 // The work plan of a table, written by one block of CFNEB_MAX_BANDS threads: each
 // thread counts one band's items of every kind, then the exclusive prefix offsets go
@@ -809,6 +835,10 @@ void launch_flush_move(const Launch& L, hipStream_t s);
 __device__ inline bool move_pending(const BandState* st, int all_images)
 {
     return all_images == 0 && st->move != 0 && st->err == 0;
+}
+__device__ inline bool move_pending(const cmem<BandState>* st, int all_images)
+{
+    return all_images == 0 && (st->move != 0) & (st->err == 0);
 }
 void launch_refine(const Launch& L, int forced, hipStream_t s);
 void launch_readout(const Launch& L, hipStream_t s);

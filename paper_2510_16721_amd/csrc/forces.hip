@@ -75,9 +75,9 @@ __device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile
     const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
     const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
     gmem<T>* F = gp(reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b));
-    const ImageGeom& g = b.geom[slot];
+    const cmem<ImageGeom>* g = cp(b.geom + slot);
     double h[9];
-    for (int q = 0; q < 9; ++q) h[q] = g.h[q];
+    for (int q = 0; q < 9; ++q) h[q] = g->h[q];
     const double rc2 = b.rc2;
     const float lo = float(rc2 * (1.0 - 1e-6)), hi = float(rc2 * (1.0 + 1e-6));
     const T eps4 = T(4.0 * b.lj_eps), eps24 = T(24.0 * b.lj_eps), sig2 = T(b.lj_sig2), esh = T(b.lj_eshift);
@@ -197,7 +197,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
     const gmem<const int>* __restrict__ ncand = gp<const int>(uni(b.ncand + size_t(slot) * N));
     gmem<float>* F = gp(uni(reinterpret_cast<float*>(b.F) + size_t(slot) * slot_rows(b)));
     const gmem<const double4>* R = gp<const double4>(uni(Rs(b, slot)));
-    const gmem<const ImageGeom>* g = gp<const ImageGeom>(b.geom + slot);
+    const cmem<ImageGeom>* g = cp(b.geom + slot);
     double h[9], H[9];  // h, and h 2^-32 (exact)
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -315,15 +315,16 @@ template <typename T, int K>
 __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_images, int variant)
 {
     __shared__ double lds[4 * 10];
-    ItemLoop loop(bd, KIND_ATOM, all_images);
+    ItemLoopRO loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
-        const BandDev& b = bd.bands[it.band];
+        const BandDev b = band_ro(bd, it.band);
         BandState* st = b.st;
-        if (band_variant(b) != variant || b.lj_lanes != K || band_stopped(st)) continue;  // uniform over the block
-        const int slot = st->slot[it.image];
+        const cmem<BandState>* sr = cp(st);
+        if ((band_variant(b) != variant) | (b.lj_lanes != K) | band_stopped(sr)) continue;  // uniform over the block
+        const int slot = sr->slot[it.image];
         if constexpr (std::is_same<T, float>::value) {
-            if (b.geom[slot].wrap) {  // uniform over the block
+            if (cp(b.geom + slot)->wrap) {  // uniform over the block
                 lj_fixed_item<K>(b, st, slot, it.tile, lds);
                 continue;
             }

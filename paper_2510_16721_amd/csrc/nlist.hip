@@ -70,14 +70,14 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
 {
     __shared__ double lds[CFNEB_TILE / 64];
     constexpr int Q = CFNEB_TILE4 / CFNEB_TILE;
-    ItemLoop loop(bd, KIND_ATOM4, all_images);
+    ItemLoopRO loop(bd, KIND_ATOM4, all_images);
     Item it;
     while (loop.next(it)) {
-        const BandDev& b = bd.bands[it.band];
-        const BandState* st = b.st;
+        const BandDev b = band_ro(bd, it.band);
+        const cmem<BandState>* st = cp(b.st);
         if (band_stopped(st)) continue;  // uniform over the block
         const int slot = st->slot[it.image];
-        const gmem<const ImageGeom>* g = gp<const ImageGeom>(b.geom + slot);
+        const cmem<ImageGeom>* g = cp(b.geom + slot);
         double D[9], E[9], hi[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
             E[q] = g->E[q];
             hi[q] = g->hinv[q];
         }
-        const bool valid = b.skst[slot].valid != 0;
+        const bool valid = cp(b.skst + slot)->valid != 0;
         gmem<uint4>* __restrict__ S = b.S ? gp(Ss(b, slot)) : nullptr;
         gmem<double>* __restrict__ X = gp(Xs(b, slot));
         const gmem<const double>* __restrict__ Rr = gp<const double>(b.Rref + size_t(slot) * slot_rows(b));

@@ -432,7 +432,7 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
     const size_t N = b.N;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < b.N) {
-        const ImageGeom& g = b.geom[slot];
+        const cmem<ImageGeom>* g = cp(b.geom + slot);
         const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
         const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
         vec4_t<T>* Praw = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.ccap * N;
@@ -440,13 +440,13 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
         vec4_t<T>* dv = reinterpret_cast<vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
         int* bcid = reinterpret_cast<int*>(b.bcid) + size_t(slot) * b.cap * N;
         double h[9];
-        for (int q = 0; q < 9; ++q) h[q] = g.h[q];
+        for (int q = 0; q < 9; ++q) h[q] = g->h[q];
         const double4 r4 = load4(R, i);
         const double ri[3] = {r4.x, r4.y, r4.z};
         const int nc = gp<const int>(b.ncand)[size_t(slot) * N + i];
         const double rc2 = b.rc2;
         const int cap = b.cap;
-        if (b.skst[slot].rebuild) ts_reverse_candidates(b, st, slot, i, nc);
+        if (cp(b.skst + slot)->rebuild) ts_reverse_candidates(b, st, slot, i, nc);
         const vec4_t<T> zero{};
         int cnt = 0;
         // four candidates at a time (carbon atoms have three or four): one round of
@@ -519,12 +519,13 @@ __device__ void ts_filter_bonds_loop(const BatchDev& bd, int all_images, int var
     __shared__ double lds[4 * 10];
     __shared__ vec4_t<T> lbond[TS_LDS_BONDS * CFNEB_TILE];
     __shared__ int lcid[TS_LDS_BONDS * CFNEB_TILE];
-    ItemLoop loop(bd, KIND_ATOM, all_images);
+    ItemLoopRO loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
-        const BandDev& b = bd.bands[it.band];
-        if (band_variant(b) != variant || band_stopped(b.st)) continue;  // uniform over the block
-        ts_filter_bonds_item<T>(b, b.st, b.st->slot[it.image], it.tile, lds, lbond, lcid);
+        const BandDev b = band_ro(bd, it.band);
+        const cmem<BandState>* sr = cp(b.st);
+        if ((band_variant(b) != variant) | band_stopped(sr)) continue;  // uniform over the block
+        ts_filter_bonds_item<T>(b, b.st, sr->slot[it.image], it.tile, lds, lbond, lcid);
     }
 }
 
@@ -561,14 +562,14 @@ __device__ void ts_gather_item(const BandDev& b, BandState* st, int slot, int i)
 template <typename T>
 __global__ void __launch_bounds__(CFNEB_TILE) k_ts_gather(BatchDev bd, int all_images, int variant)
 {
-    ItemLoop loop(bd, KIND_ATOM, all_images);
+    ItemLoopRO loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
-        const BandDev& b = bd.bands[it.band];
-        BandState* st = b.st;
+        const BandDev b = band_ro(bd, it.band);
+        const cmem<BandState>* sr = cp(b.st);
         const int i = it.tile * CFNEB_TILE + threadIdx.x;
-        if (band_variant(b) != variant || band_stopped(st) || i >= b.N) continue;
-        ts_gather_item<T>(b, st, st->slot[it.image], i);
+        if ((band_variant(b) != variant) | band_stopped(sr) || i >= b.N) continue;
+        ts_gather_item<T>(b, b.st, sr->slot[it.image], i);
     }
 }
 
