@@ -144,11 +144,14 @@ __device__ void dots_item(const BandDev& b, const BandState* st, int k, int tile
             dots_row(a, x0, xm, xp, v, f, r < b.N);
         }
     }
-    block_sum_t<CFNEB_NDOT>(a, lds);
-    if (threadIdx.x == 0) {
-        // [image][dot][tile]: the reduction reads consecutive tiles
-        double* out = b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4 + tile;
-        for (int q = 0; q < CFNEB_NDOT; ++q) out[size_t(q) * b.ntR4] = a[q];
+    // each wave stores its own partials (no block barrier): [image][dot][tile][wave],
+    // so the reduction reads consecutive partials
+    const double s = wave_sum_t<CFNEB_NDOT>(a);
+    constexpr int LOGP = wave_sum_logp<CFNEB_NDOT>();
+    const int lane = int(threadIdx.x) & 63, idx = lane >> (6 - LOGP);
+    if ((lane & ((64 >> LOGP) - 1)) == 0 && idx < CFNEB_NDOT) {
+        const int parts = b.ntR4 * CFNEB_WAVES;
+        b.dotpart[(size_t(k) * CFNEB_NDOT + idx) * parts + tile * CFNEB_WAVES + (int(threadIdx.x) >> 6)] = s;
     }
 }
 
@@ -176,10 +179,11 @@ __global__ void __launch_bounds__(1024) k_band_dots_reduce(BatchDev bd)
         const BandDev b = band_ro(bd, it.band);
         if (band_stopped(cp(b.st))) continue;  // uniform over the block
         const int k = it.image;
-        const gmem<const double>* part = gp<const double>(b.dotpart + size_t(k) * CFNEB_NDOT * b.ntR4);
+        const int parts = b.ntR4 * CFNEB_WAVES;
+        const gmem<const double>* part = gp<const double>(b.dotpart + size_t(k) * CFNEB_NDOT * parts);
         for (int q = w; q < CFNEB_NDOT; q += 16) {
             double a = 0.0;
-            for (int t = lane; t < b.ntR4; t += 64) a += part[size_t(q) * b.ntR4 + t];
+            for (int t = lane; t < parts; t += 64) a += part[size_t(q) * parts + t];
             a = wave_sum(a);
             if (lane == 0) b.dotred[size_t(k) * CFNEB_NDOT + q] = a;
         }

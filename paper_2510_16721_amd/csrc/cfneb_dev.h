@@ -35,6 +35,7 @@
 #define CFNEB_MAX_IMAGES 64
 #define CFNEB_TILE 256           // threads per block of every streaming kernel
 #define CFNEB_TILE4 1024         // rows (atoms) of a streaming item with 4 per thread
+#define CFNEB_WAVES 4            // waves per block of CFNEB_TILE threads
 #define CFNEB_NDOT 22            // band-dot partial sums per moving image and row tile
 #define CFNEB_NPROF 14           // energy-profile partial sums per image and row tile
 #define CFNEB_PROFILE_SAMPLES CFNEB_PROFILE_MAX_SAMPLES
@@ -182,7 +183,7 @@ struct BandDev {
     ImageGeom* geom;
     ImageScal* scal;
     double* evpart;     // [slot][ntA][10]
-    double* dotpart;    // [k][CFNEB_NDOT][ntR4]
+    double* dotpart;    // [k][CFNEB_NDOT][ntR4][4]: one partial per wave of each 1024-row item
     double* dotred;     // [k][CFNEB_NDOT] reduced band dots
     double* maxpart;    // [k][3][ntR4]
     double* skmax;      // [slot][1024-atom tile] max |R_i - R_i,ref (I + E)|^2 of the tile
@@ -584,12 +585,19 @@ __device__ inline void block_sum(double (&v)[NV], double* lds)
 // thread 0.  lds must hold (blockDim.x / 64) * NV doubles.
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 template <int NV>
-__device__ inline void block_sum_t(double (&v)[NV], double* lds)
+constexpr int wave_sum_logp()
+{
+    constexpr int P = pow2_at_least(NV);
+    return P <= 1 ? 0 : P <= 2 ? 1 : P <= 4 ? 2 : P <= 8 ? 3 : P <= 16 ? 4 : P <= 32 ? 5 : 6;
+}
+// The wave stage of block_sum_t: returns the lane's sum, which is the wave's total of
+// value (lane >> (6 - LOGP)) & (P - 1) on lanes whose low 6 - LOGP bits are zero.
+template <int NV>
+__device__ inline double wave_sum_t(const double (&v)[NV])
 {
     constexpr int P = pow2_at_least(NV);
     static_assert(P <= 64, "at most 64 values");
-    constexpr int LOGP = P <= 1 ? 0 : P <= 2 ? 1 : P <= 4 ? 2 : P <= 8 ? 3 : P <= 16 ? 4 : P <= 32 ? 5 : 6;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
+    const int lane = threadIdx.x & 63;
     double u[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) u[i] = i < NV ? v[i] : 0.0;
@@ -610,9 +618,18 @@ __device__ inline void block_sum_t(double (&v)[NV], double* lds)
             u[0] += __shfl_xor(u[0], m, 64);
         }
     }
+    return u[0];
+}
+template <int NV>
+__device__ inline void block_sum_t(double (&v)[NV], double* lds)
+{
+    constexpr int P = pow2_at_least(NV);
+    constexpr int LOGP = wave_sum_logp<NV>();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
+    const double ws = wave_sum_t<NV>(v);
     // the lane's sum is value (lane >> (6 - LOGP)) of the wave
     const int idx = (lane >> (6 - LOGP)) & (P - 1);
-    if ((lane & ((64 >> LOGP) - 1)) == 0 && idx < NV) lds[wid * NV + idx] = u[0];
+    if ((lane & ((64 >> LOGP) - 1)) == 0 && idx < NV) lds[wid * NV + idx] = ws;
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll

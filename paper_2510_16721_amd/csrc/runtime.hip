@@ -86,7 +86,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->scal = take(M * sizeof(ImageScal));
     L->evpart = take(M * L->ntA * 10 * 8);
     L->dotred = take(M * CFNEB_NDOT * 8);
-    L->dotpart = take(M * L->ntR4 * CFNEB_NDOT * 8);
+    L->dotpart = take(M * L->ntR4 * CFNEB_WAVES * CFNEB_NDOT * 8);
     L->maxpart = take(M * L->ntR4 * 3 * 8);
     L->skmax = take(M * size_t((L->N + CFNEB_TILE4 - 1) / CFNEB_TILE4) * 8);
     L->refpart = take(M * L->ntR * 2 * 8);
