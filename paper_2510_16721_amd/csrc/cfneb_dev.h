@@ -578,11 +578,64 @@ __device__ inline void block_sum(double (&v)[NV], double* lds)
     __syncthreads();
 }
 
+// Lane exchanges of the transposed wave reduction.  A step halves the n values each
+// lane holds: the lane whose bit m is set keeps the upper half, its partner (bit m
+// clear) the lower half, and each adds the partner's copy of the half it keeps.  Any
+// partner that differs in bit m and agrees in the bits above it gives the same
+// result, so the row-internal steps take the DPP mirror patterns.
+// Steps of 32 and 16 lanes: v_permlane32_swap / v_permlane16_swap exchange the
+// upper lanes of the first operand with the lower lanes of the second, so with the
+// lower half of the values as the first operand and the upper half as the second,
+// the two results always add up to the kept half plus the partner's copy of it.
+template <bool S32>
+__device__ inline double swap_add(double a, double b)
+{
+    const unsigned long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    const auto lo = S32 ? __builtin_amdgcn_permlane32_swap(unsigned(x), unsigned(y), false, false)
+                        : __builtin_amdgcn_permlane16_swap(unsigned(x), unsigned(y), false, false);
+    const auto hi = S32 ? __builtin_amdgcn_permlane32_swap(unsigned(x >> 32), unsigned(y >> 32), false, false)
+                        : __builtin_amdgcn_permlane16_swap(unsigned(x >> 32), unsigned(y >> 32), false, false);
+    const double p = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    const double q = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+    return p + q;
+}
+template <int N, bool S32>
+__device__ inline void wave_swap_step(double* u)
+{
+    constexpr int half = N > 1 ? N / 2 : 1;
+#pragma unroll
+    for (int i = 0; i < half; ++i) u[i] = swap_add<S32>(u[i], N > 1 ? u[half + i] : u[i]);
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double x)
+{
+    const unsigned long long v = __double_as_longlong(x);
+    const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, true));
+    const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, true));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int N, int M, int CTRL>
+__device__ inline void wave_dpp_step(double* u, int lane)
+{
+    if constexpr (N > 1) {
+        constexpr int half = N / 2;
+        const bool up = (lane & M) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = up ? u[i] : u[half + i];
+            const double keep = up ? u[half + i] : u[i];
+            u[i] = keep + dpp_f64<CTRL>(send);
+        }
+    } else {
+        u[0] += dpp_f64<CTRL>(u[0]);
+    }
+}
 // Block sum of NV doubles by a transposed wave reduction: at each halving step a lane
 // keeps half of its values and trades the other half with its partner, so a wave
 // makes P - 1 + 6 - log2 P exchanges instead of 6 NV (P = NV rounded up to a power of
-// two, at most 64), at the price of selects.  Fixed order; the result is valid in
-// thread 0.  lds must hold (blockDim.x / 64) * NV doubles.
+// two, at most 64), through lane swaps and DPP moves rather than LDS permutes.  Fixed
+// order; the result is valid in thread 0.  lds must hold (blockDim.x / 64) * NV
+// doubles.
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 template <int NV>
 constexpr int wave_sum_logp()
@@ -601,23 +654,14 @@ __device__ inline double wave_sum_t(const double (&v)[NV])
     double u[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) u[i] = i < NV ? v[i] : 0.0;
-#pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int m = 32 >> st;
-        const int n = (P >> st) > 1 ? (P >> st) : 1;  // values a lane still holds
-        if (n > 1) {
-            const int half = n / 2;
-            const bool up = (lane & m) != 0;
-#pragma unroll
-            for (int i = 0; i < half; ++i) {
-                const double send = up ? u[i] : u[half + i];
-                const double keep = up ? u[half + i] : u[i];
-                u[i] = keep + __shfl_xor(send, m, 64);
-            }
-        } else {
-            u[0] += __shfl_xor(u[0], m, 64);
-        }
-    }
+    // lanes 32 apart, then 16 apart: one swap trades the halves both ways
+    wave_swap_step<P, true>(u);
+    wave_swap_step<(P > 1 ? P / 2 : 1), false>(u);
+    // within a row of 16: partners by mirror images and quad permutations (DPP)
+    wave_dpp_step<(P > 4 ? P / 4 : 1), 8, 0x140>(u, lane);   // row_mirror: lane ^ 15
+    wave_dpp_step<(P > 8 ? P / 8 : 1), 4, 0x141>(u, lane);   // row_half_mirror: lane ^ 7
+    wave_dpp_step<(P > 16 ? P / 16 : 1), 2, 0x4E>(u, lane);  // quad_perm [2,3,0,1]: lane ^ 2
+    wave_dpp_step<(P > 32 ? P / 32 : 1), 1, 0xB1>(u, lane);  // quad_perm [1,0,3,2]: lane ^ 1
     return u[0];
 }
 template <int NV>
