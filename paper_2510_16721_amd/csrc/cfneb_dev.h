@@ -182,7 +182,7 @@ struct BandDev {
     uint16_t* crev;
     ImageGeom* geom;
     ImageScal* scal;
-    double* evpart;     // [slot][ntA][10]
+    double* evpart;     // [slot][ntA][4][10]: energy and virial sums of each wave of a tile
     double* dotpart;    // [k][CFNEB_NDOT][ntR4][4]: one partial per wave of each 1024-row item
     double* dotred;     // [k][CFNEB_NDOT] reduced band dots
     double* maxpart;    // [k][3][ntR4]
@@ -544,15 +544,65 @@ __device__ inline void set_error(BandState* st, int code)
     atomicCAS(&st->err, 0, code);
 }
 
-// 64-lane wavefront sum with a fixed butterfly order (deterministic).
+// Lane exchanges of the transposed wave reduction.  A step halves the n values each
+// lane holds: the lane whose bit m is set keeps the upper half, its partner (bit m
+// clear) the lower half, and each adds the partner's copy of the half it keeps.  Any
+// partner that differs in bit m and agrees in the bits above it gives the same
+// result, so the row-internal steps take the DPP mirror patterns.
+// Steps of 32 and 16 lanes: v_permlane32_swap / v_permlane16_swap exchange the
+// upper lanes of the first operand with the lower lanes of the second, so with the
+// lower half of the values as the first operand and the upper half as the second,
+// the two results always add up to the kept half plus the partner's copy of it.
+template <bool S32>
+__device__ inline void swap_pair(double a, double b, double& p, double& q)
+{
+    const unsigned long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    const auto lo = S32 ? __builtin_amdgcn_permlane32_swap(unsigned(x), unsigned(y), false, false)
+                        : __builtin_amdgcn_permlane16_swap(unsigned(x), unsigned(y), false, false);
+    const auto hi = S32 ? __builtin_amdgcn_permlane32_swap(unsigned(x >> 32), unsigned(y >> 32), false, false)
+                        : __builtin_amdgcn_permlane16_swap(unsigned(x >> 32), unsigned(y >> 32), false, false);
+    p = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    q = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+template <bool S32>
+__device__ inline double swap_add(double a, double b)
+{
+    double p, q;
+    swap_pair<S32>(a, b, p, q);
+    return p + q;
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double x)
+{
+    const unsigned long long v = __double_as_longlong(x);
+    const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, true));
+    const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, true));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// Sum and maximum over a wave, the same value in every lane: partners 32 and 16
+// lanes apart through the lane swaps, then lane ^ 15, ^ 7, ^ 2 and ^ 1 within a row
+// (DPP); each step pairs lanes by an xor mask, so partners hold identical results.
 __device__ inline double wave_sum(double v)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = swap_add<true>(v, v);
+    v = swap_add<false>(v, v);
+    v += dpp_f64<0x140>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0xB1>(v);
     return v;
 }
 __device__ inline double wave_max(double v)
 {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    double p, q;
+    swap_pair<true>(v, v, p, q);
+    v = fmax(p, q);
+    swap_pair<false>(v, v, p, q);
+    v = fmax(p, q);
+    v = fmax(v, dpp_f64<0x140>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0xB1>(v));
     return v;
 }
 
@@ -578,41 +628,12 @@ __device__ inline void block_sum(double (&v)[NV], double* lds)
     __syncthreads();
 }
 
-// Lane exchanges of the transposed wave reduction.  A step halves the n values each
-// lane holds: the lane whose bit m is set keeps the upper half, its partner (bit m
-// clear) the lower half, and each adds the partner's copy of the half it keeps.  Any
-// partner that differs in bit m and agrees in the bits above it gives the same
-// result, so the row-internal steps take the DPP mirror patterns.
-// Steps of 32 and 16 lanes: v_permlane32_swap / v_permlane16_swap exchange the
-// upper lanes of the first operand with the lower lanes of the second, so with the
-// lower half of the values as the first operand and the upper half as the second,
-// the two results always add up to the kept half plus the partner's copy of it.
-template <bool S32>
-__device__ inline double swap_add(double a, double b)
-{
-    const unsigned long long x = __double_as_longlong(a), y = __double_as_longlong(b);
-    const auto lo = S32 ? __builtin_amdgcn_permlane32_swap(unsigned(x), unsigned(y), false, false)
-                        : __builtin_amdgcn_permlane16_swap(unsigned(x), unsigned(y), false, false);
-    const auto hi = S32 ? __builtin_amdgcn_permlane32_swap(unsigned(x >> 32), unsigned(y >> 32), false, false)
-                        : __builtin_amdgcn_permlane16_swap(unsigned(x >> 32), unsigned(y >> 32), false, false);
-    const double p = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-    const double q = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-    return p + q;
-}
 template <int N, bool S32>
 __device__ inline void wave_swap_step(double* u)
 {
     constexpr int half = N > 1 ? N / 2 : 1;
 #pragma unroll
     for (int i = 0; i < half; ++i) u[i] = swap_add<S32>(u[i], N > 1 ? u[half + i] : u[i]);
-}
-template <int CTRL>
-__device__ inline double dpp_f64(double x)
-{
-    const unsigned long long v = __double_as_longlong(x);
-    const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, 0xF, 0xF, true));
-    const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, 0xF, 0xF, true));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 template <int N, int M, int CTRL>
 __device__ inline void wave_dpp_step(double* u, int lane)
@@ -795,6 +816,18 @@ __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int st
     }
 }
 
+// Energy and virial partials of one 256-atom tile: each wave stores its own ten sums
+// (transposed wave reduction, no block barrier).  Every wave of the tile stores, so
+// no partial of an earlier evaluation survives.
+__device__ inline void store_ev_partials(const BandDev& b, int slot, int tile, const double (&v)[10])
+{
+    const double s = wave_sum_t<10>(v);
+    constexpr int LOGP = wave_sum_logp<10>();
+    const int lane = int(threadIdx.x) & 63, idx = lane >> (6 - LOGP);
+    if ((lane & ((64 >> LOGP) - 1)) == 0 && idx < 10)
+        b.evpart[((size_t(slot) * b.ntA + tile) * CFNEB_WAVES + (int(threadIdx.x) >> 6)) * 10 + idx] = s;
+}
+
 // ---------------------------------------------------------------- launchers
 // Defined in the kernel translation units, called by the host runtime.
 // One band, direct launches (construction and readout helpers):
@@ -804,8 +837,8 @@ __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int st
 __device__ inline void image_reduce_item(const BandDev& b, BandState* st, int slot, double* lds)
 {
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const double* part = b.evpart + size_t(slot) * b.ntA * 10;
-    for (int t = threadIdx.x; t < b.ntA; t += CFNEB_TILE)
+    const double* part = b.evpart + size_t(slot) * b.ntA * CFNEB_WAVES * 10;
+    for (int t = threadIdx.x; t < b.ntA * CFNEB_WAVES; t += CFNEB_TILE)
         for (int q = 0; q < 10; ++q) acc[q] += part[size_t(t) * 10 + q];
     block_sum<10>(acc, lds);
     if (threadIdx.x != 0) return;

@@ -158,11 +158,7 @@ __device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile
     if (over) set_error(st, CFNEB_ENEIGH);
     if (bad) set_error(st, CFNEB_ENONFINITE);
     double v[10] = {acc[0], acc[1], acc[4], acc[5], acc[4], acc[2], acc[6], acc[5], acc[6], acc[3]};
-    block_sum_t<10>(v, lds);
-    if (threadIdx.x == 0) {
-        double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
-        for (int q = 0; q < 10; ++q) out[q] = v[q];
-    }
+    store_ev_partials(b, slot, tile, v);
 }
 
 // FP32 bands whose cell is wide enough (ImageGeom::wrap): the separation comes from
@@ -304,11 +300,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
     // u_i = 1/2 sum_j phi; V = -1/2 sum_ij (phi'/r) d (x) d
     for (int q = 1; q < 7; ++q) acc[q] *= -0.5 * e24;
     double v[10] = {0.5 * acc[0], acc[1], acc[4], acc[5], acc[4], acc[2], acc[6], acc[5], acc[6], acc[3]};
-    block_sum_t<10>(v, lds);
-    if (threadIdx.x == 0) {
-        double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
-        for (int q = 0; q < 10; ++q) out[q] = v[q];
-    }
+    store_ev_partials(b, slot, tile, v);
 }
 
 template <typename T, int K>

@@ -84,7 +84,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->crev = take(L->tersoff ? M * size_t(L->ccap) * N * 2 : 0);
     L->geom = take(M * sizeof(ImageGeom));
     L->scal = take(M * sizeof(ImageScal));
-    L->evpart = take(M * L->ntA * 10 * 8);
+    L->evpart = take(M * L->ntA * CFNEB_WAVES * 10 * 8);
     L->dotred = take(M * CFNEB_NDOT * 8);
     L->dotpart = take(M * L->ntR4 * CFNEB_WAVES * CFNEB_NDOT * 8);
     L->maxpart = take(M * L->ntR4 * 3 * 8);

@@ -506,11 +506,7 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
             ts_atom_generic<T>(P, dv, bo, bcid, Praw, N, i, nb, acc);
         }
     }
-    block_sum_t<10>(acc, lds);
-    if (threadIdx.x == 0) {
-        double* out = b.evpart + (size_t(slot) * b.ntA + tile) * 10;
-        for (int q = 0; q < 10; ++q) out[q] = acc[q];
-    }
+    store_ev_partials(b, slot, tile, acc);
 }
 
 template <typename T>
