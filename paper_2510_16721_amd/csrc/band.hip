@@ -181,11 +181,22 @@ __global__ void __launch_bounds__(1024) k_band_dots_reduce(BatchDev bd)
         const int k = it.image;
         const int parts = b.ntR4 * CFNEB_WAVES;
         const gmem<const double>* part = gp<const double>(b.dotpart + size_t(k) * CFNEB_NDOT * parts);
-        for (int q = w; q < CFNEB_NDOT; q += 16) {
-            double a = 0.0;
-            for (int t = lane; t < parts; t += 64) a += part[size_t(q) * parts + t];
-            a = wave_sum(a);
-            if (lane == 0) b.dotred[size_t(k) * CFNEB_NDOT + q] = a;
+        // a wave sums dots w and w + 16 together, each lane its every 64th partial in
+        // order; the unrolled loop keeps several partials' loads in flight
+        static_assert(CFNEB_NDOT <= 32, "two dots per wave");
+        const int q1 = w + 16;
+        const bool two = q1 < CFNEB_NDOT;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+        for (int t = lane; t < parts; t += 64) {
+            a0 += part[size_t(w) * parts + t];
+            if (two) a1 += part[size_t(q1) * parts + t];
+        }
+        a0 = wave_sum(a0);
+        if (lane == 0) b.dotred[size_t(k) * CFNEB_NDOT + w] = a0;
+        if (two) {
+            a1 = wave_sum(a1);
+            if (lane == 0) b.dotred[size_t(k) * CFNEB_NDOT + q1] = a1;
         }
     }
 }

@@ -163,11 +163,13 @@ __device__ __forceinline__ void fixed_point_bounds(const BandDev& b, ImageGeom& 
 // first the pending move of the image's cell rows.
 __device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int k, int all_images)
 {
-    const int slot = st->slot[k];
-    if (move_pending(st, all_images)) {
-        double* X = Xs(b, slot);
-        const double* V = Vs(b, st->vcur, slot);
-        const double sc = st->scale, dt = st->dt;
+    // the band state's fields read here are not written by this kernel
+    const cmem<BandState>* sr = cp(st);
+    const int slot = sr->slot[k];
+    if (move_pending(sr, all_images)) {
+        gmem<double>* X = gp(Xs(b, slot));
+        const gmem<const double>* V = gp<const double>(Vs(b, sr->vcur, slot));
+        const double sc = sr->scale, dt = sr->dt;
         for (int q = 0; q < 3; ++q)
             for (int c = 0; c < 3; ++c) {
                 const size_t o = size_t(c) * b.ld + b.N + q;
@@ -181,10 +183,12 @@ __device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int 
         set_error(st, CFNEB_ECELL);
     }
     // strain since the candidate build: E = h_ref^-1 h - I
-    const SkinState& sk = b.skst[slot];
+    const cmem<SkinState>& sk = *cp(b.skst + slot);
     g.enorm = 0.0;
     if (sk.valid) {
-        mm3(sk.hrefinv, g.h, g.E);
+        double hri[9];
+        for (int q = 0; q < 9; ++q) hri[q] = sk.hrefinv[q];
+        mm3(hri, g.h, g.E);
         for (int q = 0; q < 3; ++q) g.E[4 * q] -= 1.0;
         for (int q = 0; q < 9; ++q) g.enorm += g.E[q] * g.E[q];
         g.enorm = sqrt(g.enorm);
@@ -197,11 +201,15 @@ __device__ __forceinline__ void geom_image(const BandDev& b, BandState* st, int 
 
 // One block per band, one thread per image; the bands are taken from the table
 // directly, so block 0 can write the step's work plan (every later kernel of the
-// step walks it) in the same launch.
+// step walks it) in the same launch, alongside the geometry of the other blocks.
 __global__ void __launch_bounds__(CFNEB_MAX_BANDS) k_geom(BatchDev bd, int all_images)
 {
-    if (blockIdx.x == 0) plan_block(bd, all_images, 0);
-    for (int t = blockIdx.x; t < bd.cap; t += int(gridDim.x)) {
+    // block 0 writes the plan while the others take the bands (grids of at least 8)
+    if (blockIdx.x == 0) {
+        plan_block(bd, all_images, 0);
+        return;
+    }
+    for (int t = int(blockIdx.x) - 1; t < bd.cap; t += int(gridDim.x) - 1) {
         if (!bd.live[t]) continue;
         const BandDev& b = bd.bands[t];
         BandState* st = b.st;
