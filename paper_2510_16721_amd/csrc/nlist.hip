@@ -169,8 +169,11 @@ __global__ void __launch_bounds__(16 * CFNEB_MAX_IMAGES) k_skin_decide(BatchDev 
         const int slot = act ? st->slot[k] : 0;
         const int nt = kind_tiles(b, KIND_ATOM4);
         double m = 0.0;
-        if (act)
-            for (int t = lane; t < nt; t += 16) m = fmax(m, b.skmax[size_t(slot) * nt + t]);
+        if (act) {
+            const gmem<const double>* mx = gp<const double>(b.skmax + size_t(slot) * nt);
+#pragma unroll 4
+            for (int t = lane; t < nt; t += 16) m = fmax(m, mx[t]);
+        }
         for (int off = 8; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 16));
         if (!act || lane != 0) continue;
         SkinState& sk = b.skst[slot];
