@@ -759,6 +759,26 @@ __host__ __device__ inline void mm3(const double* a, const double* b, double* c)
 // own P of every atom), then every reverse P, are in flight together.
 template <typename T>
 using vec4_of = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+// dU_i/dr^ij of a Tersoff candidate slot: three packed components (12 bytes in FP32,
+// one dwordx3 access)
+template <typename T>
+struct P3 {
+    T x, y, z;
+};
+template <typename T>
+__device__ inline P3<T> load3(const gmem<const P3<T>>* p, size_t i)
+{
+    const gmem<const T>* q = reinterpret_cast<const gmem<const T>*>(p + i);
+    return P3<T>{q[0], q[1], q[2]};
+}
+template <typename T>
+__device__ inline void store3(gmem<P3<T>>* p, size_t i, T x, T y, T z)
+{
+    gmem<T>* q = reinterpret_cast<gmem<T>*>(p + i);
+    q[0] = x;
+    q[1] = y;
+    q[2] = z;
+}
 
 template <typename T, int Q>
 __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int stride, T (&f)[Q][3])
@@ -766,8 +786,8 @@ __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int st
     const size_t N = b.N;
     const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
     const gmem<const uint16_t>* __restrict__ crev = gp<const uint16_t>(b.crev + size_t(slot) * b.ccap * N);
-    const gmem<const vec4_of<T>>* __restrict__ Pb =
-        gp<const vec4_of<T>>(reinterpret_cast<const vec4_of<T>*>(b.P) + size_t(slot) * b.ccap * N);
+    const gmem<const P3<T>>* __restrict__ Pb =
+        gp<const P3<T>>(reinterpret_cast<const P3<T>*>(b.P) + size_t(slot) * b.ccap * N);
     const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
     constexpr int U = 4;
     int nc[Q], ii[Q], nmax = 0;
@@ -783,7 +803,7 @@ __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int st
     for (int c0 = 0; c0 < nmax; c0 += U) {
         uint32_t ent[Q][U];
         int rv[Q][U];
-        vec4_of<T> pe[Q][U], pr[Q][U];
+        P3<T> pe[Q][U], pr[Q][U];
         // past an atom's last candidate the loads repeat it (always in bounds, no
         // branch between the loads) and its sum below stops
 #pragma unroll
@@ -793,13 +813,13 @@ __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int st
                 const size_t o = size_t(max(min(c0 + u, nc[q] - 1), 0)) * N + ii[q];
                 ent[q][u] = cand[o];
                 rv[q][u] = int(crev[o]);
-                pe[q][u] = load4(Pb, o);
+                pe[q][u] = load3(Pb, o);
             }
         __builtin_amdgcn_sched_barrier(0);  // keep the loads of the round ahead of their uses
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int u = 0; u < U; ++u) pr[q][u] = load4(Pb, size_t(rv[q][u]) * N + nbr_j(ent[q][u]));
+            for (int u = 0; u < U; ++u) pr[q][u] = load3(Pb, size_t(rv[q][u]) * N + nbr_j(ent[q][u]));
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < Q; ++q)

@@ -80,7 +80,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->dvec = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
     L->bo = take(L->tersoff ? M * size_t(L->cap) * N * 2 * tsz : 0);
     L->bcid = take(L->tersoff ? M * size_t(L->cap) * N * 4 : 0);
-    L->P = take(L->tersoff ? M * size_t(L->ccap) * N * 4 * tsz : 0);
+    L->P = take(L->tersoff ? M * size_t(L->ccap) * N * 3 * tsz : 0);
     L->crev = take(L->tersoff ? M * size_t(L->ccap) * N * 2 : 0);
     L->geom = take(M * sizeof(ImageGeom));
     L->scal = take(M * sizeof(ImageScal));

@@ -205,7 +205,7 @@ __device__ inline void add_virial(double* acc, T dx, T dy, T dz, T px, T py, T p
 // to the bond's candidate slot cid (LDS, one per bond at the given stride).
 template <typename T, int MAXB>
 __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB], const int* cid, int stride,
-                             gmem<vec4_t<T>>* Pout, size_t N, int i, int cnt, double* acc)
+                             gmem<P3<T>>* Pout, size_t N, int i, int cnt, double* acc)
 {
     constexpr int NP = MAXB * (MAXB - 1) / 2;
     T dx[MAXB], dy[MAXB], dz[MAXB], ir[MAXB], fc[MAXB], dfc[MAXB], fr[MAXB], fa[MAXB];
@@ -308,12 +308,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
 #pragma unroll
     for (int e = 0; e < MAXB; ++e) {
         if (e >= cnt) continue;
-        vec4_t<T> o;
-        o.x = px[e];
-        o.y = py[e];
-        o.z = pz[e];
-        o.w = T(0);
-        store4(Pout, size_t(cid[e * stride]) * N + i, o);
+        store3(Pout, size_t(cid[e * stride]) * N + i, px[e], py[e], pz[e]);
         add_virial<T>(acc, dx[e], dy[e], dz[e], px[e], py[e], pz[e]);
     }
 }
@@ -322,7 +317,7 @@ __device__ void ts_atom_regs(const TersoffT<T>& P, const vec4_t<T> (&bond)[MAXB]
 // each bond's candidate slot.
 template <typename T>
 __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_t<T>* bo, const int* bcid,
-                                vec4_t<T>* Pout, size_t N, int i, int cnt, double* acc)
+                                P3<T>* Pout, size_t N, int i, int cnt, double* acc)
 {
     for (int e = 0; e < cnt; ++e) {
         const vec4_t<T> de = dv[size_t(e) * N + i];
@@ -374,12 +369,7 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
             py -= ang * cy + rad * hy;
             pz -= ang * cz + rad * hz;
         }
-        vec4_t<T> o;
-        o.x = px;
-        o.y = py;
-        o.z = pz;
-        o.w = T(0);
-        Pout[size_t(bcid[size_t(e) * N + i]) * N + i] = o;
+        Pout[size_t(bcid[size_t(e) * N + i]) * N + i] = P3<T>{px, py, pz};
         add_virial<T>(acc, de.x, de.y, de.z, px, py, pz);
     }
 }
@@ -435,8 +425,8 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
         const cmem<ImageGeom>* g = cp(b.geom + slot);
         const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
         const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
-        vec4_t<T>* Praw = reinterpret_cast<vec4_t<T>*>(b.P) + size_t(slot) * b.ccap * N;
-        gmem<vec4_t<T>>* __restrict__ Pout = gp(Praw);
+        P3<T>* Praw = reinterpret_cast<P3<T>*>(b.P) + size_t(slot) * b.ccap * N;
+        gmem<P3<T>>* __restrict__ Pout = gp(Praw);
         vec4_t<T>* dv = reinterpret_cast<vec4_t<T>*>(b.dvec) + size_t(slot) * b.cap * N;
         int* bcid = reinterpret_cast<int*>(b.bcid) + size_t(slot) * b.cap * N;
         double h[9];
@@ -469,7 +459,7 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
                 const double rr = exact_r2(ri, rj[u].x, rj[u].y, rj[u].z, h, nbr_n(ent[u], 0), nbr_n(ent[u], 1),
                                            nbr_n(ent[u], 2), d);
                 if (!(rr < rc2)) {
-                    store4(Pout, size_t(e0 + u) * N + i, zero);
+                    store3(Pout, size_t(e0 + u) * N + i, T(0), T(0), T(0));
                     continue;
                 }
                 if (cnt < cap) {
