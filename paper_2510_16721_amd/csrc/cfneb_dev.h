@@ -158,7 +158,7 @@ struct BandDev {
     double* X;
     double* V;
     double* R;
-    uint4* S;           // FP32 LJ bands, else null
+    uint32_t* S;        // FP32 LJ bands, else null: three words per atom
     void* F;
     double* FN;
     int4* binfo;
@@ -274,7 +274,7 @@ __device__ inline double* Vs(const BandDev& b, int buf, int slot)
 // Cartesian positions R = R~ D, one 32-byte record (x, y, z, 0) per atom, so a
 // neighbour's position is one aligned load.
 __device__ inline double4* Rs(const BandDev& b, int slot) { return reinterpret_cast<double4*>(b.R) + size_t(slot) * b.ld; }
-__device__ inline uint4* Ss(const BandDev& b, int slot) { return b.S + size_t(slot) * b.ld; }
+__device__ inline uint32_t* Ss(const BandDev& b, int slot) { return b.S + size_t(slot) * b.ld * 3; }
 
 __device__ inline uint32_t pack_nbr(int j, int n0, int n1, int n2)
 {

@@ -162,7 +162,7 @@ __device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile
 }
 
 // FP32 bands whose cell is wide enough (ImageGeom::wrap): the separation comes from
-// the fixed-point fractional coordinates, one 16-byte gather per candidate and no
+// the fixed-point fractional coordinates, one 12-byte gather per candidate and no
 // lattice-shift arithmetic: the wrapped 32-bit difference of two coordinates is the
 // fractional separation times 2^32, and d = (that difference) (h 2^-32) in FP64, then
 // rounded to FP32 per pair (an FP32 h would scale every separation by the same
@@ -174,11 +174,10 @@ __device__ inline uint32_t ld_u32(const void* base, uint32_t off)
 {
     return *reinterpret_cast<const gmem<const uint32_t>*>(gp(static_cast<const char*>(base)) + off);
 }
-__device__ inline uint4 ld_u128(const void* base, uint32_t off)
+__device__ inline uint4 ld_u96(const void* base, uint32_t off)
 {
-    const nvec4<uint32_t> v =
-        *reinterpret_cast<const gmem<const nvec4<uint32_t>>*>(gp(static_cast<const char*>(base)) + off);
-    return make_uint4(v.x, v.y, v.z, v.w);
+    const gmem<const uint32_t>* p = reinterpret_cast<const gmem<const uint32_t>*>(gp(static_cast<const char*>(base)) + off);
+    return make_uint4(p[0], p[1], p[2], 0u);
 }
 
 template <int K>
@@ -188,7 +187,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
     const int Ni = uni(b.N), ld = uni(b.ld), cap = uni(b.cap);
     const uint32_t N = uint32_t(Ni);
     const int lane = int(threadIdx.x) % K;
-    const uint4* S = uni(Ss(b, slot));
+    const uint32_t* S = uni(Ss(b, slot));
     const uint32_t* cand = uni(b.cand + size_t(slot) * b.ccap * N);
     const gmem<const int>* __restrict__ ncand = gp<const int>(uni(b.ncand + size_t(slot) * N));
     gmem<float>* F = gp(uni(reinterpret_cast<float*>(b.F) + size_t(slot) * slot_rows(b)));
@@ -211,7 +210,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
         const int i = tile * CFNEB_TILE + sub * (CFNEB_TILE / K) + int(threadIdx.x) / K;
         const bool in = i < Ni;
         const uint32_t ii = in ? uint32_t(i) : 0u;
-        const uint4 si = ld_u128(S, ii * 16u);
+        const uint4 si = ld_u96(S, ii * 12u);
         const int nc = in ? ncand[ii] : 0;
         float fx = 0.f, fy = 0.f, fz = 0.f;
         int cnt = 0;
@@ -232,7 +231,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
                 ent[u] = ld_u32(cand, e0 + u * K < nc ? o : o0);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) sj[u] = ld_u128(S, uint32_t(nbr_j(ent[u])) * 16u);
+            for (int u = 0; u < U; ++u) sj[u] = ld_u96(S, uint32_t(nbr_j(ent[u])) * 12u);
             __builtin_amdgcn_sched_barrier(0);
             float w[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             const int cnt0 = cnt;

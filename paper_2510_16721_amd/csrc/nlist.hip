@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
             hi[q] = g->hinv[q];
         }
         const bool valid = cp(b.skst + slot)->valid != 0;
-        gmem<uint4>* __restrict__ S = b.S ? gp(Ss(b, slot)) : nullptr;
+        gmem<uint32_t>* __restrict__ S = b.S ? gp(Ss(b, slot)) : nullptr;
         gmem<double>* __restrict__ X = gp(Xs(b, slot));
         const gmem<const double>* __restrict__ Rr = gp<const double>(b.Rref + size_t(slot) * slot_rows(b));
         double x[Q][3], a[Q][3];
@@ -137,7 +137,12 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
             double r[3];
             for (int c = 0; c < 3; ++c) r[c] = (x[q][0] * D[c] + x[q][1] * D[3 + c]) + x[q][2] * D[6 + c];
             store4(R, i, make_double4(r[0], r[1], r[2], 0.0));
-            if (S) store4(S, i, fixed_fraction(r, hi));
+            if (S) {
+                const uint4 f = fixed_fraction(r, hi);
+                S[3 * size_t(i)] = f.x;
+                S[3 * size_t(i) + 1] = f.y;
+                S[3 * size_t(i) + 2] = f.z;
+            }
             if (valid) {
                 double d2 = 0.0;
                 for (int c = 0; c < 3; ++c) {

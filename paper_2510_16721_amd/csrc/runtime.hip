@@ -64,7 +64,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->X = take(M * rows * 8);
     L->V = take(2 * M * rows * 8);
     L->R = take(M * size_t(L->ld) * 32);
-    L->S = take(L->tersoff || L->fp64 ? 0 : M * size_t(L->ld) * 16);
+    L->S = take(L->tersoff || L->fp64 ? 0 : M * size_t(L->ld) * 12);
     L->F = take(M * rows * tsz);
     L->FN = take(M * rows * 8);
     L->binfo = take(M * N * 16);
@@ -301,7 +301,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.X = reinterpret_cast<double*>(base + L.X);
     d.V = reinterpret_cast<double*>(base + L.V);
     d.R = reinterpret_cast<double*>(base + L.R);
-    d.S = (L.tersoff || d.fp64) ? nullptr : reinterpret_cast<uint4*>(base + L.S);
+    d.S = (L.tersoff || d.fp64) ? nullptr : reinterpret_cast<uint32_t*>(base + L.S);
     d.F = base + L.F;
     d.FN = reinterpret_cast<double*>(base + L.FN);
     d.binfo = reinterpret_cast<int4*>(base + L.binfo);
