@@ -252,6 +252,23 @@ __device__ inline V load4(const gmem<const V>* p, size_t i)
     o.w = v.w;
     return o;
 }
+// packed FP64 position record (x, y, z)
+struct R3 {
+    double x, y, z;
+};
+// a packed position record (w = 0)
+__device__ inline double4 load4(const gmem<const R3>* p, size_t i)
+{
+    const gmem<const double>* q = reinterpret_cast<const gmem<const double>*>(p + i);
+    return make_double4(q[0], q[1], q[2], 0.0);
+}
+__device__ inline void store3(gmem<R3>* p, size_t i, double x, double y, double z)
+{
+    gmem<double>* q = reinterpret_cast<gmem<double>*>(p + i);
+    q[0] = x;
+    q[1] = y;
+    q[2] = z;
+}
 template <typename V>
 __device__ inline void store4(gmem<V>* p, size_t i, const V& o)
 {
@@ -271,9 +288,9 @@ __device__ inline double* Vs(const BandDev& b, int buf, int slot)
 {
     return b.V + (size_t(buf) * b.Mcap + slot) * slot_rows(b);
 }
-// Cartesian positions R = R~ D, one 32-byte record (x, y, z, 0) per atom, so a
-// neighbour's position is one aligned load.
-__device__ inline double4* Rs(const BandDev& b, int slot) { return reinterpret_cast<double4*>(b.R) + size_t(slot) * b.ld; }
+// Cartesian positions R = R~ D, one packed 24-byte record (x, y, z) per atom, so a
+// neighbour's position is one contiguous gather.
+__device__ inline R3* Rs(const BandDev& b, int slot) { return reinterpret_cast<R3*>(b.R) + size_t(slot) * b.ld; }
 __device__ inline uint32_t* Ss(const BandDev& b, int slot) { return b.S + size_t(slot) * b.ld * 3; }
 
 __device__ inline uint32_t pack_nbr(int j, int n0, int n1, int n2)

@@ -71,7 +71,7 @@ __device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile
 {
     const size_t N = b.N;
     const int lane = int(threadIdx.x) % K;
-    const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
+    const gmem<const R3>* __restrict__ R = gp<const R3>(Rs(b, slot));
     const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
     const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
     gmem<T>* F = gp(reinterpret_cast<T*>(b.F) + size_t(slot) * slot_rows(b));
@@ -191,7 +191,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
     const uint32_t* cand = uni(b.cand + size_t(slot) * b.ccap * N);
     const gmem<const int>* __restrict__ ncand = gp<const int>(uni(b.ncand + size_t(slot) * N));
     gmem<float>* F = gp(uni(reinterpret_cast<float*>(b.F) + size_t(slot) * slot_rows(b)));
-    const gmem<const double4>* R = gp<const double4>(uni(Rs(b, slot)));
+    const gmem<const R3>* R = gp<const R3>(uni(Rs(b, slot)));
     const cmem<ImageGeom>* g = cp(b.geom + slot);
     double h[9], H[9];  // h, and h 2^-32 (exact)
 #pragma unroll

@@ -129,14 +129,14 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
             }
         }
         double m[1] = {0.0};
-        gmem<double4>* __restrict__ R = gp(Rs(b, slot));
+        gmem<R3>* __restrict__ R = gp(Rs(b, slot));
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int i = it.tile * CFNEB_TILE4 + q * CFNEB_TILE + threadIdx.x;
             if (i >= b.N) continue;
             double r[3];
             for (int c = 0; c < 3; ++c) r[c] = (x[q][0] * D[c] + x[q][1] * D[3 + c]) + x[q][2] * D[6 + c];
-            store4(R, i, make_double4(r[0], r[1], r[2], 0.0));
+            store3(R, i, r[0], r[1], r[2]);
             if (S) {
                 const uint4 f = fixed_fraction(r, hi);
                 S[3 * size_t(i)] = f.x;
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(16 * CFNEB_MAX_IMAGES) k_skin_decide(BatchDev 
 __device__ void bin_assign_item(const BandDev& b, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const double4 ri = Rs(b, slot)[i];
+    const double4 ri = load4(gp<const R3>(Rs(b, slot)), i);
     const double r[3] = {ri.x, ri.y, ri.z};
     int bi[3], img[3];
     for (int q = 0; q < 3; ++q) {
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_bin_scatter(BatchDev bd, int all
         const int4 bi = b.binfo[size_t(slot) * b.N + i];
         const int pos = b.bstart[bin_base(b, slot) + bi.x] + bi.y;
         if (pos < 0 || pos >= b.N) continue;
-        const double4 ri = Rs(b, slot)[i];
+        const double4 ri = load4(gp<const R3>(Rs(b, slot)), i);
         BinAtom a;
         a.x = ri.x;
         a.y = ri.y;
@@ -369,7 +369,7 @@ __device__ inline void wrap_bin(int v, int nb, int& a, int& m)
 __device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const double4 r4 = load4(gp<const double4>(Rs(b, slot)), i);
+    const double4 r4 = load4(gp<const R3>(Rs(b, slot)), i);
     const gmem<const int>* __restrict__ start = gp<const int>(b.bstart + bin_base(b, slot));
     const gmem<const double4>* __restrict__ bp =
         gp<const double4>(reinterpret_cast<const double4*>(b.bpos + size_t(slot) * b.N));
@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_cand(BatchDev bd, int all_images
 __device__ void filter_item(const BandDev& b, BandState* st, int slot, int i)
 {
     const ImageGeom& g = b.geom[slot];
-    const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
+    const gmem<const R3>* __restrict__ R = gp<const R3>(Rs(b, slot));
     const size_t N = b.N;
     const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
     gmem<uint32_t>* __restrict__ nbr = gp(b.nbr + size_t(slot) * b.cap * N);

@@ -63,7 +63,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     };
     L->X = take(M * rows * 8);
     L->V = take(2 * M * rows * 8);
-    L->R = take(M * size_t(L->ld) * 32);
+    L->R = take(M * size_t(L->ld) * 24);
     L->S = take(L->tersoff || L->fp64 ? 0 : M * size_t(L->ld) * 12);
     L->F = take(M * rows * tsz);
     L->FN = take(M * rows * 8);
@@ -1073,10 +1073,8 @@ int cfneb_image_data(const cfneb_band* cb, int k, double* E, double* H, double* 
         soa_to_aos(slab.data(), ld, N + 3, Fneb);
     }
     if (R) {
-        std::vector<double> r4(4 * size_t(ld));
-        HIP_TRY(b, hipMemcpy(r4.data(), b->d.R + size_t(slot) * 4 * ld, r4.size() * 8, hipMemcpyDeviceToHost));
-        for (int i = 0; i < N; ++i)
-            for (int c = 0; c < 3; ++c) R[3 * size_t(i) + c] = r4[4 * size_t(i) + c];
+        // packed (x, y, z) records: the first N are the caller's layout
+        HIP_TRY(b, hipMemcpy(R, b->d.R + size_t(slot) * 3 * ld, 3 * size_t(N) * 8, hipMemcpyDeviceToHost));
     }
     return CFNEB_OK;
 }

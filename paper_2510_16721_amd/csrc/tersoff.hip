@@ -423,7 +423,7 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < b.N) {
         const cmem<ImageGeom>* g = cp(b.geom + slot);
-        const gmem<const double4>* __restrict__ R = gp<const double4>(Rs(b, slot));
+        const gmem<const R3>* __restrict__ R = gp<const R3>(Rs(b, slot));
         const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
         P3<T>* Praw = reinterpret_cast<P3<T>*>(b.P) + size_t(slot) * b.ccap * N;
         gmem<P3<T>>* __restrict__ Pout = gp(Praw);
