@@ -169,7 +169,7 @@ struct BandDev {
     int* ncnt;
     uint32_t* cand;     // [slot][ccap][N] candidate entries, packed like nbr
     int* ncand;         // [slot][N]
-    double* Rref;       // [slot][3][ld] positions at the candidate build
+    float* Rref;        // [slot][3][ld] positions at the candidate build, rounded to FP32
     SkinState* skst;    // [slot]
     // Tersoff bond scratch: bond vectors, bond orders and candidate slots of bonds
     // past the fourth ([slot][cap][N]); the per-candidate derivatives P
@@ -186,7 +186,7 @@ struct BandDev {
     double* dotpart;    // [k][CFNEB_NDOT][ntR4][4]: one partial per wave of each 1024-row item
     double* dotred;     // [k][CFNEB_NDOT] reduced band dots
     double* maxpart;    // [k][3][ntR4]
-    double* skmax;      // [slot][1024-atom tile] max |R_i - R_i,ref (I + E)|^2 of the tile
+    double* skmax;      // [slot][1024-atom tile][2] max |R_i - R_i,ref (I + E)|^2 and max |R_i,ref|^2 of the tile
     uint64_t* refpart;  // [k][ntR][2]
     double* staging;    // endpoint upload and readout area
     BandState* st;

@@ -11,6 +11,8 @@
 // rebuilt when a pair could have come from outside rcl: with h = h_ref (I + E) and
 // d_i = |R_i - R_i,ref (I + E)|, a pair's separation at the build is at most
 // (r + d_i + d_j) / (1 - |E|), so 2 max d_i + rcl |E| < skin keeps the list complete.
+// R_ref is kept in FP32: each component within 2^-24 of its magnitude, so d_i measured
+// against it is within 2^-24 |R_ref,i| (1 + |E|) of the true one, added to the bound.
 //
 // Kernels, in order (each a persistent walk over the items of every live band):
 //   k_skin_check   (steps) the previous step's move of the atom rows; R = R~ D (and
@@ -68,7 +70,7 @@ __device__ inline uint4 fixed_fraction(const double* r, const double* hi)
 // would contend on one address).
 __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_images)
 {
-    __shared__ double lds[CFNEB_TILE / 64];
+    __shared__ double lds[(CFNEB_TILE / 64) * 2];
     constexpr int Q = CFNEB_TILE4 / CFNEB_TILE;
     ItemLoopRO loop(bd, KIND_ATOM4, all_images);
     Item it;
@@ -88,7 +90,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
         const bool valid = cp(b.skst + slot)->valid != 0;
         gmem<uint32_t>* __restrict__ S = b.S ? gp(Ss(b, slot)) : nullptr;
         gmem<double>* __restrict__ X = gp(Xs(b, slot));
-        const gmem<const double>* __restrict__ Rr = gp<const double>(b.Rref + size_t(slot) * slot_rows(b));
+        const gmem<const float>* __restrict__ Rr = gp<const float>(b.Rref + size_t(slot) * slot_rows(b));
         double x[Q][3], a[Q][3];
         if (move_pending(st, all_images)) {  // uniform over the block
             // the previous step's move of these rows: X += scale (dt v')
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
                 for (int c = 0; c < 3; ++c) {
                     x[q][c] = in ? X[size_t(c) * b.ld + i] : 0.0;
                     v[q][c] = in ? V[size_t(c) * b.ld + i] : 0.0;
-                    a[q][c] = (in && valid) ? Rr[size_t(c) * b.ld + i] : 0.0;
+                    a[q][c] = (in && valid) ? double(Rr[size_t(c) * b.ld + i]) : 0.0;
                 }
             }
 #pragma unroll
@@ -124,11 +126,12 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     x[q][c] = in ? X[size_t(c) * b.ld + i] : 0.0;
-                    a[q][c] = (in && valid) ? Rr[size_t(c) * b.ld + i] : 0.0;
+                    a[q][c] = (in && valid) ? double(Rr[size_t(c) * b.ld + i]) : 0.0;
                 }
             }
         }
-        double m[1] = {0.0};
+        // max d_i^2 against the FP32 reference, and max |R_ref,i|^2 for its rounding
+        double m[2] = {0.0, 0.0};
         gmem<R3>* __restrict__ R = gp(Rs(b, slot));
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -151,10 +154,15 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_skin_check(BatchDev bd, int all_
                     d2 += d * d;
                 }
                 m[0] = fmax(m[0], d2);
+                m[1] = fmax(m[1], (a[q][0] * a[q][0] + a[q][1] * a[q][1]) + a[q][2] * a[q][2]);
             }
         }
-        block_max<1>(m, lds);
-        if (threadIdx.x == 0) b.skmax[size_t(slot) * kind_tiles(b, KIND_ATOM4) + it.tile] = m[0];
+        block_max<2>(m, lds);
+        if (threadIdx.x == 0) {
+            double* out = b.skmax + (size_t(slot) * kind_tiles(b, KIND_ATOM4) + it.tile) * 2;
+            out[0] = m[0];
+            out[1] = m[1];
+        }
     }
 }
 
@@ -173,18 +181,27 @@ __global__ void __launch_bounds__(16 * CFNEB_MAX_IMAGES) k_skin_decide(BatchDev 
         const bool act = !band_stopped(st) && k < b.Mcap && image_active(st, k, all_images);
         const int slot = act ? st->slot[k] : 0;
         const int nt = kind_tiles(b, KIND_ATOM4);
-        double m = 0.0;
+        double m = 0.0, ma = 0.0;
         if (act) {
-            const gmem<const double>* mx = gp<const double>(b.skmax + size_t(slot) * nt);
+            const gmem<const double>* mx = gp<const double>(b.skmax + size_t(slot) * nt * 2);
 #pragma unroll 4
-            for (int t = lane; t < nt; t += 16) m = fmax(m, mx[t]);
+            for (int t = lane; t < nt; t += 16) {
+                m = fmax(m, mx[2 * t]);
+                ma = fmax(ma, mx[2 * t + 1]);
+            }
         }
-        for (int off = 8; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 16));
+        for (int off = 8; off > 0; off >>= 1) {
+            m = fmax(m, __shfl_xor(m, off, 16));
+            ma = fmax(ma, __shfl_xor(ma, off, 16));
+        }
         if (!act || lane != 0) continue;
         SkinState& sk = b.skst[slot];
         const ImageGeom& g = b.geom[slot];
         bool rebuild = true;
-        if (b.skin > 0.0 && sk.valid) rebuild = !(2.0 * sqrt(m) + b.rcl * g.enorm < b.skin * (1.0 - 1e-6));
+        // the FP32 reference is within 2^-24 |R_ref,i| of the build positions, so every
+        // displacement is within that times (1 + |E|) of the one measured against it
+        const double dmax = sqrt(m) + 0x1p-24 * (1.0 + 1e-6) * sqrt(ma) * (1.0 + g.enorm);
+        if (b.skin > 0.0 && sk.valid) rebuild = !(2.0 * dmax + b.rcl * g.enorm < b.skin * (1.0 - 1e-6));
         sk.rebuild = rebuild ? 1 : 0;
         if (rebuild) {
             for (int q = 0; q < 9; ++q) {
@@ -379,10 +396,10 @@ __device__ void cand_item(const BandDev& b, BandState* st, int slot, int i)
     double h[9];
     for (int q = 0; q < 9; ++q) h[q] = g.h[q];
     const double ri[3] = {r4.x, r4.y, r4.z};
-    gmem<double>* __restrict__ Rr = gp(b.Rref + size_t(slot) * slot_rows(b));
-    Rr[i] = ri[0];
-    Rr[b.ld + i] = ri[1];
-    Rr[2 * size_t(b.ld) + i] = ri[2];
+    gmem<float>* __restrict__ Rr = gp(b.Rref + size_t(slot) * slot_rows(b));
+    Rr[i] = float(ri[0]);
+    Rr[b.ld + i] = float(ri[1]);
+    Rr[2 * size_t(b.ld) + i] = float(ri[2]);
     const int4 me = b.binfo[size_t(slot) * N + i];
     const int im0 = (me.z & 0x3FF) - 512, im1 = ((me.z >> 10) & 0x3FF) - 512, im2 = ((me.z >> 20) & 0x3FF) - 512;
     const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];

@@ -75,7 +75,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->ncnt = take(M * N * 4);
     L->cand = take(M * size_t(L->ccap) * N * 4);
     L->ncand = take(M * N * 4);
-    L->Rref = take(M * rows * 8);
+    L->Rref = take(M * rows * 4);
     L->skin = take(M * sizeof(SkinState));
     L->dvec = take(L->tersoff ? M * size_t(L->cap) * N * 4 * tsz : 0);
     L->bo = take(L->tersoff ? M * size_t(L->cap) * N * 2 * tsz : 0);
@@ -88,7 +88,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->dotred = take(M * CFNEB_NDOT * 8);
     L->dotpart = take(M * L->ntR4 * CFNEB_WAVES * CFNEB_NDOT * 8);
     L->maxpart = take(M * L->ntR4 * 3 * 8);
-    L->skmax = take(M * size_t((L->N + CFNEB_TILE4 - 1) / CFNEB_TILE4) * 8);
+    L->skmax = take(M * size_t((L->N + CFNEB_TILE4 - 1) / CFNEB_TILE4) * 2 * 8);
     L->refpart = take(M * L->ntR * 2 * 8);
     L->staging = take(std::max<size_t>(6 * N + 64, CFNEB_PROF_DOUBLES) * 8);
     L->state = take(sizeof(BandState));
@@ -312,7 +312,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.ncnt = reinterpret_cast<int*>(base + L.ncnt);
     d.cand = reinterpret_cast<uint32_t*>(base + L.cand);
     d.ncand = reinterpret_cast<int*>(base + L.ncand);
-    d.Rref = reinterpret_cast<double*>(base + L.Rref);
+    d.Rref = reinterpret_cast<float*>(base + L.Rref);
     d.skst = reinterpret_cast<SkinState*>(base + L.skin);
     d.dvec = L.tersoff ? base + L.dvec : nullptr;
     d.bo = L.tersoff ? base + L.bo : nullptr;
