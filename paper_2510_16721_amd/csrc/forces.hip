@@ -24,7 +24,7 @@ namespace cfneb {
 // exact inclusion test and, if it is a neighbour, its pair term, so neither a packed
 // neighbour list nor a second gather of the positions is needed in a step.  K lanes
 // share an atom, taking candidates l, l + K, l + 2K, ... (lane l); the atom's force
-// is the fixed butterfly sum of its lanes, energy and virial go into the block sums.
+// is the fixed butterfly sum of its lanes, energy and virial go into the wave sums.
 // A tile of 256 atoms is covered in K passes of 256 / K atoms.
 //
 // FP64-record path (FP64 bands, narrow cells): the inclusion test decides on the
@@ -67,7 +67,7 @@ __device__ inline bool exact_inside(const double* d, float r2f, float lo, float 
 }
 
 template <typename T, int K>
-__device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
+__device__ void lj_cand_item(const BandDev& b, BandState* st, int slot, int tile)
 {
     const size_t N = b.N;
     const int lane = int(threadIdx.x) % K;
@@ -181,7 +181,7 @@ __device__ inline uint4 ld_u96(const void* base, uint32_t off)
 }
 
 template <int K>
-__device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int tile, double* lds)
+__device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int tile)
 {
     // band fields as uniform locals: read once, held in scalar registers
     const int Ni = uni(b.N), ld = uni(b.ld), cap = uni(b.cap);
@@ -305,7 +305,6 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
 template <typename T, int K>
 __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_images, int variant)
 {
-    __shared__ double lds[4 * 10];
     ItemLoopRO loop(bd, KIND_ATOM, all_images);
     Item it;
     while (loop.next(it)) {
@@ -316,11 +315,11 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_ima
         const int slot = sr->slot[it.image];
         if constexpr (std::is_same<T, float>::value) {
             if (cp(b.geom + slot)->wrap) {  // uniform over the block
-                lj_fixed_item<K>(b, st, slot, it.tile, lds);
+                lj_fixed_item<K>(b, st, slot, it.tile);
                 continue;
             }
         }
-        lj_cand_item<T, K>(b, st, slot, it.tile, lds);
+        lj_cand_item<T, K>(b, st, slot, it.tile);
     }
 }
 

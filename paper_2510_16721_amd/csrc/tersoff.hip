@@ -407,13 +407,13 @@ __device__ void ts_reverse_candidates(const BandDev& b, BandState* st, int slot,
 #define TS_LDS_BONDS 4
 
 // Neighbours of atom i by the exact test of its candidates (as the candidate filter
-// does for LJ), then u_i, P_ij and the per-atom virial from the bond vectors; block
+// does for LJ), then u_i, P_ij and the per-atom virial from the bond vectors; wave
 // partials of (E, V) in FP64.  The first four bonds go to this thread's LDS slots
 // (an LDS store at a per-lane index, where registers would need a select per slot)
 // and then to registers; an atom with more bonds writes them to global scratch and
 // takes the general path.
 template <typename T>
-__device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, int tile, double* lds,
+__device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, int tile,
                                      vec4_t<T>* lbond, int* lcid)
 {
     constexpr int MB = TS_LDS_BONDS;
@@ -502,7 +502,6 @@ __device__ void ts_filter_bonds_item(const BandDev& b, BandState* st, int slot, 
 template <typename T>
 __device__ void ts_filter_bonds_loop(const BatchDev& bd, int all_images, int variant)
 {
-    __shared__ double lds[4 * 10];
     __shared__ vec4_t<T> lbond[TS_LDS_BONDS * CFNEB_TILE];
     __shared__ int lcid[TS_LDS_BONDS * CFNEB_TILE];
     ItemLoopRO loop(bd, KIND_ATOM, all_images);
@@ -511,7 +510,7 @@ __device__ void ts_filter_bonds_loop(const BatchDev& bd, int all_images, int var
         const BandDev b = band_ro(bd, it.band);
         const cmem<BandState>* sr = cp(b.st);
         if ((band_variant(b) != variant) | band_stopped(sr)) continue;  // uniform over the block
-        ts_filter_bonds_item<T>(b, b.st, sr->slot[it.image], it.tile, lds, lbond, lcid);
+        ts_filter_bonds_item<T>(b, b.st, sr->slot[it.image], it.tile, lbond, lcid);
     }
 }
 
