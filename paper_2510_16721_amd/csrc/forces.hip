@@ -303,7 +303,7 @@ __device__ void lj_fixed_item(const BandDev& b, BandState* st, int slot, int til
 }
 
 template <typename T, int K>
-__global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_images, int variant)
+__device__ void lj_cand_loop(const BatchDev& bd, int all_images, int variant)
 {
     ItemLoopRO loop(bd, KIND_ATOM, all_images);
     Item it;
@@ -321,6 +321,22 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_ima
         }
         lj_cand_item<T, K>(b, st, slot, it.tile);
     }
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(CFNEB_TILE) k_lj_cand(BatchDev bd, int all_images, int variant)
+{
+    lj_cand_loop<T, K>(bd, all_images, variant);
+}
+
+// FP32, one lane per atom (the large bands): five waves per SIMD at a small spill run
+// faster than four without one (force kernel 391 -> 365 us on the 97,555-atom band);
+// the other variants keep their registers (they spill 20-24 dwords at five).
+template <>
+__global__ void __launch_bounds__(CFNEB_TILE) __attribute__((amdgpu_waves_per_eu(5)))
+k_lj_cand<float, 1>(BatchDev bd, int all_images, int variant)
+{
+    lj_cand_loop<float, 1>(bd, all_images, variant);
 }
 
 template <typename T>
