@@ -599,6 +599,8 @@ __device__ inline double dpp_f64(double x)
 // Sum and maximum over a wave, the same value in every lane: partners 32 and 16
 // lanes apart through the lane swaps, then lane ^ 15, ^ 7, ^ 2 and ^ 1 within a row
 // (DPP); each step pairs lanes by an xor mask, so partners hold identical results.
+// These exchanges and the transposed ones below read every lane: all 64 lanes of the
+// wave must take part (no caller sits inside a lane-dependent branch).
 __device__ inline double wave_sum(double v)
 {
     v = swap_add<true>(v, v);
