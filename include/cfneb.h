@@ -265,7 +265,7 @@ int cfneb_relax(const cfneb_params* p, int64_t n_atoms, const int32_t* types, do
  * no graph, stream or event).  Kernels are launched one by one on hip_stream; the call
  * synchronises it before returning.  Arguments and results as cfneb_relax.  Errors:
  * CFNEB_ENOMEM when cfneb_band_bytes(p, n_atoms, 3) exceeds
- * CFNEB_RELAX_SCRATCH_BYTES (about 13,000 atoms for LJ, 16,000 for FP32 Tersoff
+ * CFNEB_RELAX_SCRATCH_BYTES (about 13,500 atoms for LJ, 17,500 for FP32 Tersoff
  * carbon), CFNEB_EHIP if the array's address cannot be found; otherwise those of
  * cfneb_relax.  Every call on one GPU uses that GPU's array and clears it first; two
  * calls that overlap on one GPU (two host threads, or two streams) race and must not
