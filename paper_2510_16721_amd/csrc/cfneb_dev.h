@@ -173,13 +173,13 @@ struct BandDev {
     SkinState* skst;    // [slot]
     // Tersoff bond scratch: bond vectors, bond orders and candidate slots of bonds
     // past the fourth ([slot][cap][N]); the per-candidate derivatives P
-    // ([slot][ccap][N], zero for candidates that are not bonds) and the reverse
-    // candidate of each candidate (the slot of (i, -n) in j's list).
+    // ([slot][ccap][N], zero for candidates that are not bonds) and, per candidate,
+    // the index in P of its reverse (i, -n) in j's list: q N + j for j's slot q.
     void* dvec;
     void* bo;
     void* bcid;
     void* P;
-    uint16_t* crev;
+    uint32_t* crev;
     ImageGeom* geom;
     ImageScal* scal;
     double* evpart;     // [slot][ntA][4][10]: energy and virial sums of each wave of a tile
@@ -803,8 +803,7 @@ template <typename T, int Q>
 __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int stride, T (&f)[Q][3])
 {
     const size_t N = b.N;
-    const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
-    const gmem<const uint16_t>* __restrict__ crev = gp<const uint16_t>(b.crev + size_t(slot) * b.ccap * N);
+    const gmem<const uint32_t>* __restrict__ crev = gp<const uint32_t>(b.crev + size_t(slot) * b.ccap * N);
     const gmem<const P3<T>>* __restrict__ Pb =
         gp<const P3<T>>(reinterpret_cast<const P3<T>*>(b.P) + size_t(slot) * b.ccap * N);
     const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
@@ -820,8 +819,7 @@ __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int st
 #pragma unroll
     for (int q = 0; q < Q; ++q) nmax = max(nmax, nc[q]);
     for (int c0 = 0; c0 < nmax; c0 += U) {
-        uint32_t ent[Q][U];
-        int rv[Q][U];
+        uint32_t rv[Q][U];
         P3<T> pe[Q][U], pr[Q][U];
         // past an atom's last candidate the loads repeat it (always in bounds, no
         // branch between the loads) and its sum below stops
@@ -830,15 +828,14 @@ __device__ inline void tersoff_gather(const BandDev& b, int slot, int i0, int st
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const size_t o = size_t(max(min(c0 + u, nc[q] - 1), 0)) * N + ii[q];
-                ent[q][u] = cand[o];
-                rv[q][u] = int(crev[o]);
+                rv[q][u] = crev[o];
                 pe[q][u] = load3(Pb, o);
             }
         __builtin_amdgcn_sched_barrier(0);  // keep the loads of the round ahead of their uses
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int u = 0; u < U; ++u) pr[q][u] = load3(Pb, size_t(rv[q][u]) * N + nbr_j(ent[q][u]));
+            for (int u = 0; u < U; ++u) pr[q][u] = load3(Pb, rv[q][u]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < Q; ++q)

@@ -49,8 +49,8 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
         const double ratio = (rc + p->nbr_skin) / rc;
         L->ccap = int(std::ceil(1.25 * p->nbr_cap * ratio * ratio * ratio));
     }
-    // Tersoff candidate slots are 16-bit in the reverse index
-    if (p->potential == CFNEB_TERSOFF_C && L->ccap > 65535) return false;
+    // the Tersoff reverse index (slot x N + atom) is 32-bit
+    if (p->potential == CFNEB_TERSOFF_C && size_t(L->ccap) * size_t(L->N) > 0xFFFFFFFFull) return false;
     L->fp64 = p->force_fp64 ? 1 : 0;
     L->tersoff = (p->potential == CFNEB_TERSOFF_C) ? 1 : 0;
     const size_t M = size_t(L->Mcap), N = size_t(L->N), rows = 3 * size_t(L->ld);
@@ -81,7 +81,7 @@ bool make_layout(const cfneb_params* p, int64_t n_atoms, int max_images, Layout*
     L->bo = take(L->tersoff ? M * size_t(L->cap) * N * 2 * tsz : 0);
     L->bcid = take(L->tersoff ? M * size_t(L->cap) * N * 4 : 0);
     L->P = take(L->tersoff ? M * size_t(L->ccap) * N * 3 * tsz : 0);
-    L->crev = take(L->tersoff ? M * size_t(L->ccap) * N * 2 : 0);
+    L->crev = take(L->tersoff ? M * size_t(L->ccap) * N * 4 : 0);
     L->geom = take(M * sizeof(ImageGeom));
     L->scal = take(M * sizeof(ImageScal));
     L->evpart = take(M * L->ntA * CFNEB_WAVES * 10 * 8);
@@ -318,7 +318,7 @@ void fill_dev(cfneb_band* b, void* ws, const double* h0, int relax)
     d.bo = L.tersoff ? base + L.bo : nullptr;
     d.bcid = L.tersoff ? base + L.bcid : nullptr;
     d.P = L.tersoff ? base + L.P : nullptr;
-    d.crev = L.tersoff ? reinterpret_cast<uint16_t*>(base + L.crev) : nullptr;
+    d.crev = L.tersoff ? reinterpret_cast<uint32_t*>(base + L.crev) : nullptr;
     d.geom = reinterpret_cast<ImageGeom*>(base + L.geom);
     d.scal = reinterpret_cast<ImageScal*>(base + L.scal);
     d.evpart = reinterpret_cast<double*>(base + L.evpart);

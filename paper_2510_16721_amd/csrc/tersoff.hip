@@ -374,14 +374,15 @@ __device__ void ts_atom_generic(const TersoffT<T>& P, const vec4_t<T>* dv, vec2_
     }
 }
 
-// Reverse candidate of each of atom i's candidates: the slot of (i, -n) in j's list.
-// Runs on the steps that rebuild the image's candidates.
+// Reverse candidate of each of atom i's candidates: the slot q of (i, -n) in j's list,
+// stored as its index q N + j in P (the gather's one load).  Runs on the steps that
+// rebuild the image's candidates.
 __device__ void ts_reverse_candidates(const BandDev& b, BandState* st, int slot, int i, int nc)
 {
     const size_t N = b.N;
     const gmem<const uint32_t>* __restrict__ cand = gp<const uint32_t>(b.cand + size_t(slot) * b.ccap * N);
     const gmem<const int>* __restrict__ ncand = gp<const int>(b.ncand + size_t(slot) * N);
-    gmem<uint16_t>* __restrict__ crev = gp(b.crev + size_t(slot) * b.ccap * N);
+    gmem<uint32_t>* __restrict__ crev = gp(b.crev + size_t(slot) * b.ccap * N);
     bool missing = false;
     for (int c = 0; c < nc; ++c) {
         const uint32_t ent = cand[size_t(c) * N + i];
@@ -398,7 +399,7 @@ __device__ void ts_reverse_candidates(const BandDev& b, BandState* st, int slot,
             missing = true;
             found = 0;
         }
-        crev[size_t(c) * N + i] = uint16_t(found);
+        crev[size_t(c) * N + i] = uint32_t(size_t(found) * N + size_t(j));
     }
     if (missing) set_error(st, CFNEB_ENEIGH);
 }
