@@ -311,7 +311,7 @@ __device__ void lj_cand_loop(const BatchDev& bd, int all_images, int variant)
         const BandDev b = band_ro(bd, it.band);
         BandState* st = b.st;
         const cmem<BandState>* sr = cp(st);
-        if ((band_variant(b) != variant) | (b.lj_lanes != K) | band_stopped(sr)) continue;  // uniform over the block
+        if (int(band_variant(b) != variant) | int(b.lj_lanes != K) | int(band_stopped(sr))) continue;  // uniform over the block
         const int slot = sr->slot[it.image];
         if constexpr (std::is_same<T, float>::value) {
             if (cp(b.geom + slot)->wrap) {  // uniform over the block

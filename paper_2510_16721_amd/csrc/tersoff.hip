@@ -510,7 +510,7 @@ __device__ void ts_filter_bonds_loop(const BatchDev& bd, int all_images, int var
     while (loop.next(it)) {
         const BandDev b = band_ro(bd, it.band);
         const cmem<BandState>* sr = cp(b.st);
-        if ((band_variant(b) != variant) | band_stopped(sr)) continue;  // uniform over the block
+        if (int(band_variant(b) != variant) | int(band_stopped(sr))) continue;  // uniform over the block
         ts_filter_bonds_item<T>(b, b.st, sr->slot[it.image], it.tile, lbond, lcid);
     }
 }
@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(CFNEB_TILE) k_ts_gather(BatchDev bd, int all_i
         const BandDev b = band_ro(bd, it.band);
         const cmem<BandState>* sr = cp(b.st);
         const int i = it.tile * CFNEB_TILE + threadIdx.x;
-        if ((band_variant(b) != variant) | band_stopped(sr) || i >= b.N) continue;
+        if ((int(band_variant(b) != variant) | int(band_stopped(sr))) || i >= b.N) continue;
         ts_gather_item<T>(b, b.st, sr->slot[it.image], i);
     }
 }
